@@ -1,0 +1,179 @@
+/*
+ * aims_grid.h -- C ABI of the MI355X NAO real-space grid-integration library.
+ *
+ * The library evaluates, for spatially compact batches of integration points, the nonzero
+ * numeric atom-centred basis functions phi_i = R_s(r) Y_lm(r^) (cubic-spline radial function
+ * times real spherical harmonic, l <= 3) and their kinetic terms t phi_i = -1/2 Laplacian phi_i
+ * = K_s(r) Y_lm(r^), and from them
+ *
+ *     n(p)  = sum_ij P_ij phi_i(p) phi_j(p)                           (aims_update_density)
+ *     H_ij  = sum_p w_p phi_i(p) [v(p) phi_j(p) + t phi_j(p)]           (aims_integrate_h)
+ *     S_ij  = sum_p w_p phi_i(p) phi_j(p)
+ *     E     = sum_p w_p v_p n(p) + sum_p w_p sum_ij P_ij phi_i tphi_j,  dE/dP, dE/dv, dE/dR
+ *                                                                     (aims_integrate_h_backward)
+ *
+ * This is the grid-integration part of one self-consistent-field iteration of semilocal
+ * all-electron DFT with numeric atom-centred orbitals (the method of the paper's "Background
+ * and Current Status" and "Development Priorities" sections; the s.c.f. iteration timed in
+ * its Figure 4).  The paper gives no formulas for it; the definitions above are the textbook
+ * real-space quadrature of those matrix elements.
+ *
+ * Units: bohr and hartree.  Basis order (part of the contract): atom-major, then the shells of
+ * the atom's species in the order given, then m = -l..l.  Real harmonics are orthonormal on the
+ * sphere, without the Condon-Shortley phase (Y_1,-1 ~ y, Y_10 ~ z, Y_11 ~ x).
+ *
+ * Radial functions: for each shell the caller tabulates R and K at the logarithmic knots
+ * r_k = r0 (rc/r0)^(k/(n_log-1)), k = 0..n_log-1.  The library interpolates them with the
+ * natural cubic spline in s = ln r on those (uniform in s) knots, uses the first cubic below r0,
+ * returns exactly 0 for r >= rc, and clamps r below 1e-12 bohr to 1e-12.
+ *
+ * Ownership: the caller owns every buffer it passes; the library owns the aims_grid handle
+ * (tables, batch lists, scratch) until aims_grid_destroy and never frees caller memory.  No
+ * pointer is retained after a call returns, except by a step graph (its buffers must outlive
+ * it).  Calls are asynchronous on the stream given at setup; one handle must not be used from
+ * two threads at once.  Errors: every call returns an aims_status; all argument validation
+ * happens on the host before any launch, and aims_last_error() holds the message.
+ */
+#ifndef AIMS_GRID_H
+#define AIMS_GRID_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct aims_grid aims_grid;  /* opaque, library-owned */
+
+typedef enum {
+  AIMS_OK = 0,
+  AIMS_ERR_ARG = -1,          /* invalid argument (null, wrong memory space, out of range)   */
+  AIMS_ERR_OOM = -2,          /* device or host allocation failed                            */
+  AIMS_ERR_HIP = -3,          /* a HIP runtime call or kernel launch failed                  */
+  AIMS_ERR_STALE = -4,        /* an atom moved farther than screen_margin since setup        */
+  AIMS_ERR_UNSUPPORTED = -5   /* l > 3, or a size beyond the documented limits               */
+} aims_status;
+
+typedef enum {
+  AIMS_FP64 = 0,    /* everything in FP64                                                    */
+  AIMS_FP32 = 1,    /* per-batch contractions on FP32 MFMA, FP32 basis values and tables;
+                       FP64 cross-batch reduction of H/S/n and of the N/E sums               */
+  AIMS_BF16X3 = 2   /* per-batch contractions as three BF16 MFMA products of hi/lo splits
+                       (x = hi + lo, hi = bf16(x), lo = bf16(x - hi); hi*hi + hi*lo + lo*hi)
+                       with FP32 accumulation; FP64 cross-batch reduction as for AIMS_FP32   */
+} aims_precision;
+
+/* One molecular system.  All pointers are HOST pointers; the library copies what it needs
+ * during setup.  Sizes: n_atoms >= 1, n_species >= 1, 1 <= max_batch <= 512, n_log >= 4,
+ * 0 < r0 < rc, 0 <= l <= 3.  n_points may be 0. */
+typedef struct {
+  int32_t n_atoms;
+  const double *atom_xyz;        /* [n_atoms][3]                                             */
+  const int32_t *atom_species;   /* [n_atoms], values 0..n_species-1                         */
+  int32_t n_species;
+  const int32_t *species_nshell; /* [n_species]                                              */
+  const int32_t *shell_l;        /* [sum nshell], species-major, each 0..3                    */
+  int32_t n_log;                 /* knots of the logarithmic radial grid                     */
+  double r0, rc;                 /* first knot and cutoff radius (last knot)                 */
+  const double *shell_R;         /* [sum nshell][n_log]: R(r_k)                              */
+  const double *shell_K;         /* [sum nshell][n_log]: K(r_k) = -1/2[R''+2R'/r-l(l+1)R/r^2] */
+  int64_t n_points;
+  const double *pt_xyz;          /* [n_points][3]                                            */
+  const double *pt_w;            /* [n_points] full quadrature weights                       */
+  int32_t max_batch;             /* maximum points per batch                                 */
+  double screen_margin;          /* bohr; atoms may later move this far (<= 0: 1e-2)         */
+} aims_system;
+
+/* Builds the splines (FP64 and FP32 copies), partitions the points into batches by recursive
+ * median bisection along the longest bounding-box axis until each holds <= max_batch points,
+ * keeps per batch the atoms closer than rc + screen_margin to at least one of its points (and
+ * so every basis function that can be nonzero on it), and uploads everything to `device`.
+ * `hip_stream` (a hipStream_t, NULL = default stream) is used by every later call.
+ * On success *out receives a new handle. */
+aims_status aims_grid_setup(const aims_system *sys, int device, void *hip_stream, aims_grid **out);
+
+/* Several independent systems in one handle (the ensemble of independent calculations the
+ * paper's "Concluding Remarks" describe, here on one GPU).  Their batches are processed
+ * together in every call.  Per-system arrays passed to later calls are concatenated in system
+ * order: points (n, v, dE/dv), atoms (atom_xyz, dE/dR), and the dense nb_s x nb_s matrices
+ * (P, H, S, dE/dP) one after another at offsets sum_{t<s} nb_t^2. */
+aims_status aims_grid_setup_many(const aims_system *sys, int32_t n_sys, int device,
+                                 void *hip_stream, aims_grid **out);
+
+/* Density update: n_out[p] = sum_ij P_ij phi_i(p) phi_j(p) for every point (caller order) and
+ * sums_out[3] = { N = sum w n, E_V = sum w v n, E_T = sum_p w_p sum_ij P_ij phi_i tphi_j }.
+ * P: DEVICE, FP64, [nb][nb] row-major, symmetric (the caller's responsibility).  v_or_null:
+ * DEVICE [n_points] or NULL (then E_V = 0).  n_out: DEVICE [n_points].  sums_out: DEVICE [3].
+ * atom_xyz: NULL (positions from setup) or a host or device [n_atoms][3] array; it is read
+ * synchronously and must lie within screen_margin of the setup positions (else
+ * AIMS_ERR_STALE). */
+aims_status aims_update_density(aims_grid *g, aims_precision prec, const double *atom_xyz,
+                                const double *P, const double *v_or_null, double *n_out,
+                                double *sums_out);
+
+/* Hamiltonian (and optionally overlap) integration: H_ij = sum_p w_p phi_i (v_p phi_j + tphi_j)
+ * (raw: not symmetrised), S_ij = sum_p w_p phi_i phi_j.  v: DEVICE [n_points].  H, S_or_null:
+ * DEVICE FP64 [nb][nb] row-major, overwritten. */
+aims_status aims_integrate_h(aims_grid *g, aims_precision prec, const double *atom_xyz,
+                             const double *v, double *H, double *S_or_null);
+
+/* Backward of E(P, v, R) = sum_p w_p v_p n(p) + sum_p w_p sum_ij P_ij phi_i tphi_j with an
+ * incoming gradient gE (DEVICE, one double):
+ *   dE/dP_ij = gE H_ij (independent entries),  dE/dv_p = gE w_p n(p),
+ *   dE/dR_a  = -gE sum_p w_p sum_{i on a} [(2 v_p X_pi + Y_pi) grad phi_i(p) + X_pi grad tphi_i(p)]
+ * with X = Phi P and Y = (T Phi) P per batch; basis values and gradients are recomputed, not
+ * stored.  Only the basis centres move (grid points, weights and v are fixed).  Any output may
+ * be NULL.  dE_dP: DEVICE [nb][nb]; dE_dv: DEVICE [n_points]; dE_dR: DEVICE [n_atoms][3];
+ * all overwritten. */
+aims_status aims_integrate_h_backward(aims_grid *g, aims_precision prec, const double *atom_xyz,
+                                      const double *P, const double *v, const double *gE,
+                                      double *dE_dP_or_null, double *dE_dv_or_null,
+                                      double *dE_dR_or_null);
+
+/* One s.c.f. step (density update followed by H integration, setup positions) captured once
+ * into a HIP graph on the handle's stream; aims_step_graph_launch replays it.  The buffers are
+ * baked into the graph and must outlive it; update their contents in place between replays. */
+typedef struct aims_step_graph aims_step_graph;
+aims_status aims_step_graph_create(aims_grid *g, aims_precision prec, const double *P,
+                                   const double *v, double *n_out, double *sums_out, double *H,
+                                   aims_step_graph **out);
+aims_status aims_step_graph_launch(aims_step_graph *graph);
+void aims_step_graph_destroy(aims_step_graph *graph);
+
+/* Kernel tile configuration chosen per (points, basis) bucket; see aims_tune_*. */
+typedef struct {
+  int32_t n_buckets;            /* number of buckets, <= 16                                 */
+  int32_t nb_edges[16];         /* bucket k holds batches with nb <= nb_edges[k] (ascending) */
+  int32_t variant[16];          /* kernel variant per bucket (0 .. aims_n_variants()-1)      */
+} aims_tuning;
+int32_t aims_n_variants(aims_precision prec);
+aims_status aims_get_tuning(const aims_grid *g, aims_precision prec, aims_tuning *out);
+aims_status aims_set_tuning(aims_grid *g, aims_precision prec, const aims_tuning *t);
+
+/* Work statistics: number of batches, sum_b n_p n_b^2 (flops = 4x this per s.c.f. step), and
+ * sum_b n_b^2 (entries scattered into H per call); any pointer may be NULL. */
+aims_status aims_work_stats(const aims_grid *g, int64_t *n_batches, double *sum_np_nb2,
+                            double *sum_nb2);
+int64_t aims_n_basis(const aims_grid *g);       /* total over systems                      */
+int64_t aims_n_points(const aims_grid *g);      /* total over systems                      */
+int32_t aims_n_atoms(const aims_grid *g);       /* total over systems                      */
+
+/* Per-kernel timing: with profiling on, HIP events are recorded on the handle's stream around
+ * every kernel launch.  aims_profile_read synchronizes the stream, then returns for one kernel
+ * family ("phi_eval", "density", "hs", "backward", "finish") the number of launches since
+ * profiling was enabled, their summed duration in milliseconds, and the algorithmic work they
+ * did (flops of the per-batch contractions, 2 n_p n_b^2 per batch and GEMM).  Not for use while
+ * a step graph is being captured. */
+aims_status aims_profile_enable(aims_grid *g, int on);
+aims_status aims_profile_read(aims_grid *g, const char *kernel, int64_t *launches,
+                              double *total_ms, double *work);
+
+/* Message of the last failure on this handle, or of the calling thread's last failed setup
+ * when g is NULL.  Never NULL. */
+const char *aims_last_error(const aims_grid *g);
+void aims_grid_destroy(aims_grid *g);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AIMS_GRID_H */

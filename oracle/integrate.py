@@ -117,12 +117,16 @@ class GridOracle:
             ET += float(w @ (Xm * TPhi).sum(1))
         return {"n": n, "N": N, "E_V": EV, "E_T": ET}
 
-    def integrate_h(self, v: np.ndarray, want_S: bool = True):
-        """H_ij = sum_p w_p phi_i (v_p phi_j + tphi_j) and S_ij = sum_p w_p phi_i phi_j."""
+    def integrate_h(self, v: np.ndarray, want_S: bool = True,
+                    points: Optional[np.ndarray] = None):
+        """H_ij = sum_p w_p phi_i (v_p phi_j + tphi_j) and S_ij = sum_p w_p phi_i phi_j, summed
+        over every point (or over the subset ``points`` of indices)."""
         inst = self.inst
         H = np.zeros((self.nb, self.nb))
         S = np.zeros((self.nb, self.nb)) if want_S else None
-        for sl in self._chunks():
+        idx_all = np.arange(inst.n_points) if points is None else np.asarray(points)
+        for s0 in range(0, idx_all.size, self.chunk):
+            sl = idx_all[s0:s0 + self.chunk]
             Phi, TPhi, cols = self.basis_values(inst.pt_xyz[sl])
             w = inst.pt_w[sl][:, None]
             ix = np.ix_(cols, cols)

@@ -1,0 +1,91 @@
+"""ctypes declarations of the C ABI in include/aims_grid.h (argument marshalling only).
+
+Importing this module loads ``libaimsgrid.so`` from the package directory and fails loudly if
+it has not been built; there is no fallback implementation.
+"""
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int, c_int32, c_int64, c_void_p
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libaimsgrid.so")
+
+AIMS_OK, AIMS_ERR_ARG, AIMS_ERR_OOM, AIMS_ERR_HIP, AIMS_ERR_STALE, AIMS_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+STATUS_NAMES = {0: "AIMS_OK", -1: "AIMS_ERR_ARG", -2: "AIMS_ERR_OOM", -3: "AIMS_ERR_HIP",
+                -4: "AIMS_ERR_STALE", -5: "AIMS_ERR_UNSUPPORTED"}
+PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+
+
+class AimsSystem(ctypes.Structure):
+    _fields_ = [
+        ("n_atoms", c_int32),
+        ("atom_xyz", POINTER(c_double)),
+        ("atom_species", POINTER(c_int32)),
+        ("n_species", c_int32),
+        ("species_nshell", POINTER(c_int32)),
+        ("shell_l", POINTER(c_int32)),
+        ("n_log", c_int32),
+        ("r0", c_double),
+        ("rc", c_double),
+        ("shell_R", POINTER(c_double)),
+        ("shell_K", POINTER(c_double)),
+        ("n_points", c_int64),
+        ("pt_xyz", POINTER(c_double)),
+        ("pt_w", POINTER(c_double)),
+        ("max_batch", c_int32),
+        ("screen_margin", c_double),
+    ]
+
+
+class AimsTuning(ctypes.Structure):
+    _fields_ = [("n_buckets", c_int32), ("nb_edges", c_int32 * 16), ("variant", c_int32 * 16)]
+
+
+# every symbol the header declares, with its signature
+SIGNATURES = {
+    "aims_grid_setup": (c_int, [POINTER(AimsSystem), c_int, c_void_p, POINTER(c_void_p)]),
+    "aims_grid_setup_many": (c_int, [POINTER(AimsSystem), c_int32, c_int, c_void_p, POINTER(c_void_p)]),
+    "aims_update_density": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "aims_integrate_h": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "aims_integrate_h_backward": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
+                                          c_void_p, c_void_p, c_void_p]),
+    "aims_step_graph_create": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
+                                       c_void_p, POINTER(c_void_p)]),
+    "aims_step_graph_launch": (c_int, [c_void_p]),
+    "aims_step_graph_destroy": (None, [c_void_p]),
+    "aims_n_variants": (c_int32, [c_int]),
+    "aims_get_tuning": (c_int, [c_void_p, c_int, POINTER(AimsTuning)]),
+    "aims_set_tuning": (c_int, [c_void_p, c_int, POINTER(AimsTuning)]),
+    "aims_work_stats": (c_int, [c_void_p, POINTER(c_int64), POINTER(c_double), POINTER(c_double)]),
+    "aims_n_basis": (c_int64, [c_void_p]),
+    "aims_n_points": (c_int64, [c_void_p]),
+    "aims_n_atoms": (c_int32, [c_void_p]),
+    "aims_profile_enable": (c_int, [c_void_p, c_int]),
+    "aims_profile_read": (c_int, [c_void_p, c_char_p, POINTER(c_int64), POINTER(c_double),
+                                  POINTER(c_double)]),
+    "aims_last_error": (c_char_p, [c_void_p]),
+    "aims_grid_destroy": (None, [c_void_p]),
+}
+
+_lib = None
+
+
+def load():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2208_12335_amd.build.build() "
+                              "(there is no non-HIP implementation)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class AimsError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status

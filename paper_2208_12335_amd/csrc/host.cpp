@@ -1,0 +1,847 @@
+// Host side of the C ABI: validation, spline construction, spatial batching, screening,
+// upload, and the call sequences of the entry points declared in include/aims_grid.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "aims_grid.h"
+#include "aims_internal.h"
+#include "kernels.h"
+
+using namespace aims;
+
+namespace {
+
+thread_local std::string g_setup_error = "no error";
+
+// ---------------------------------------------------------------------------------------------
+// small utilities
+// ---------------------------------------------------------------------------------------------
+struct Fail {
+  aims_status status;
+  std::string msg;
+};
+
+[[noreturn]] void fail(aims_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  throw Fail{st, buf};
+}
+
+void hipchk(hipError_t e, const char* what) {
+  if (e != hipSuccess) fail(AIMS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+template <typename F>
+void parallel_for(int64_t n, F&& f) {
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (n < 64 || nt == 1) {
+    for (int64_t i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::atomic<int64_t> next(0);
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < nt; ++t)
+    th.emplace_back([&] {
+      for (int64_t i; (i = next.fetch_add(1)) < n;) f(i);
+    });
+  for (auto& t : th) t.join();
+}
+
+bool finite_all(const double* x, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(x[i])) return false;
+  return true;
+}
+
+// Natural cubic spline through y_k at uniformly spaced abscissae (spacing h): second
+// derivatives from the tridiagonal system M_{k-1} + 4 M_k + M_{k+1} = 6 (y_{k+1} - 2 y_k +
+// y_{k-1}) / h^2 with M_0 = M_{n-1} = 0, then per interval the coefficients of
+// a + b t + c t^2 + d t^3 in t = s - s_k.
+void natural_spline(const double* y, int n, double h, double* coef /* [(n-1)][4] */) {
+  std::vector<double> M(n, 0.0), cp(n, 0.0), dp(n, 0.0);
+  const int m = n - 2;  // unknowns M_1..M_{n-2}
+  for (int i = 0; i < m; ++i) {
+    const int k = i + 1;
+    const double rhs = 6.0 * (y[k + 1] - 2.0 * y[k] + y[k - 1]) / (h * h);
+    const double denom = 4.0 - (i > 0 ? cp[i - 1] : 0.0);
+    cp[i] = 1.0 / denom;
+    dp[i] = (rhs - (i > 0 ? dp[i - 1] : 0.0)) / denom;
+  }
+  for (int i = m - 1; i >= 0; --i) M[i + 1] = dp[i] - (i + 1 < m ? cp[i] * M[i + 2] : 0.0);
+  for (int k = 0; k < n - 1; ++k) {
+    coef[4 * k + 0] = y[k];
+    coef[4 * k + 1] = (y[k + 1] - y[k]) / h - h * (2.0 * M[k] + M[k + 1]) / 6.0;
+    coef[4 * k + 2] = 0.5 * M[k];
+    coef[4 * k + 3] = (M[k + 1] - M[k]) / (6.0 * h);
+  }
+}
+
+// Recursive median bisection along the longest bounding-box axis (ties broken by index).
+void bisect(const double* xyz, std::vector<int32_t>& idx, int64_t lo, int64_t hi, int maxb,
+            std::vector<std::pair<int64_t, int64_t>>& out) {
+  if (hi - lo <= maxb) {
+    if (hi > lo) out.emplace_back(lo, hi);
+    return;
+  }
+  double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+  for (int64_t i = lo; i < hi; ++i)
+    for (int c = 0; c < 3; ++c) {
+      mn[c] = std::min(mn[c], xyz[3 * (int64_t)idx[i] + c]);
+      mx[c] = std::max(mx[c], xyz[3 * (int64_t)idx[i] + c]);
+    }
+  int ax = 0;
+  for (int c = 1; c < 3; ++c)
+    if (mx[c] - mn[c] > mx[ax] - mn[ax]) ax = c;
+  const int64_t mid = lo + (hi - lo) / 2;
+  std::nth_element(idx.begin() + lo, idx.begin() + mid, idx.begin() + hi, [&](int32_t a, int32_t b) {
+    const double ca = xyz[3 * (int64_t)a + ax], cb = xyz[3 * (int64_t)b + ax];
+    return ca < cb || (ca == cb && a < b);
+  });
+  bisect(xyz, idx, lo, mid, maxb, out);
+  bisect(xyz, idx, mid, hi, maxb, out);
+}
+
+int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+bool is_device_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t attr;
+  hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged ||
+         attr.type == hipMemoryTypeUnified;
+}
+
+}  // namespace
+
+// -------------------------------------------------------------------------------------------------
+// the handle
+// -------------------------------------------------------------------------------------------------
+struct aims_grid {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err = "no error";
+
+  int n_sys = 0;
+  int n_atoms = 0;
+  int64_t n_points = 0;
+  int64_t nb_total = 0;
+  int64_t mat_total = 0;
+  double margin = 1e-2;
+  RadialGrid rg{};
+
+  std::vector<double> atom_xyz0;      // setup positions
+  bool moved = false;                 // device positions differ from the setup positions
+  std::vector<SystemDesc> systems;
+  std::vector<BatchDesc> batches;
+  std::vector<int64_t> sys_pt_range, sys_item_range, sys_atom_range;
+
+  struct Group {
+    int b0, b1;
+    int64_t d0, d1;   // density items
+    int64_t h0, h1;   // H items
+    double flops;     // sum over the group's batches of 2 n_p n_b^2
+  };
+  std::vector<Group> groups;
+  int64_t n_ditems = 0, n_hitems = 0;
+  size_t slab_elems = 0;
+  double sum_np_nb2 = 0, sum_nb2 = 0;
+  int nblk_finish = 64;
+
+  // profiling
+  struct ProfRec {
+    int kind;
+    hipEvent_t a, b;
+    double work;
+  };
+  bool profiling = false;
+  std::vector<ProfRec> prof_pending;
+  int64_t prof_count[5] = {0, 0, 0, 0, 0};
+  double prof_ms[5] = {0, 0, 0, 0, 0};
+  double prof_work[5] = {0, 0, 0, 0, 0};
+
+  std::vector<void*> owned;           // device allocations
+  DeviceView dv{};
+  TileItem* d_ditems = nullptr;
+  TileItem* d_hitems = nullptr;
+  double* d_atom_xyz = nullptr;
+  double* d_n_sorted = nullptr;
+  double* d_part = nullptr;
+  double* d_et_part = nullptr;
+  float* d_P32 = nullptr;
+  void* d_slab1 = nullptr;
+  void* d_slab2 = nullptr;
+
+  ~aims_grid() {
+    if (!owned.empty()) {
+      (void)hipSetDevice(device);
+      for (void* p : owned) (void)hipFree(p);
+    }
+  }
+
+  void* alloc(size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    const char* inj = getenv("AIMS_FAIL_ALLOC");
+    if (inj && atoi(inj) != 0) fail(AIMS_ERR_OOM, "device allocation of %zu bytes failed (injected)", bytes);
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      fail(AIMS_ERR_OOM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    owned.push_back(p);
+    return p;
+  }
+  template <typename T>
+  T* upload(const std::vector<T>& v) {
+    T* p = (T*)alloc(v.size() * sizeof(T));
+    if (!v.empty())
+      hipchk(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "upload");
+    return p;
+  }
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------------------------
+// set-up
+// ---------------------------------------------------------------------------------------------
+void validate_system(const aims_system* s, int k) {
+  if (!s) fail(AIMS_ERR_ARG, "system %d: null aims_system", k);
+  if (s->n_atoms < 1) fail(AIMS_ERR_ARG, "system %d: n_atoms must be >= 1", k);
+  if (!s->atom_xyz || !s->atom_species || !s->species_nshell || !s->shell_l || !s->shell_R ||
+      !s->shell_K)
+    fail(AIMS_ERR_ARG, "system %d: null array", k);
+  if (s->n_species < 1) fail(AIMS_ERR_ARG, "system %d: n_species must be >= 1", k);
+  if (s->n_points < 0) fail(AIMS_ERR_ARG, "system %d: n_points < 0", k);
+  if (s->n_points > 0 && (!s->pt_xyz || !s->pt_w)) fail(AIMS_ERR_ARG, "system %d: null points", k);
+  if (s->n_points > (int64_t)INT32_MAX / 2) fail(AIMS_ERR_UNSUPPORTED, "system %d: too many points", k);
+  if (s->max_batch < 1 || s->max_batch > kMaxBatch)
+    fail(AIMS_ERR_UNSUPPORTED, "system %d: max_batch must be in [1, %d]", k, kMaxBatch);
+  if (s->n_log < 4) fail(AIMS_ERR_ARG, "system %d: n_log must be >= 4", k);
+  if (!(s->r0 > 0.0) || !(s->rc > s->r0) || !std::isfinite(s->rc))
+    fail(AIMS_ERR_ARG, "system %d: need 0 < r0 < rc", k);
+  int nsh = 0;
+  for (int i = 0; i < s->n_species; ++i) {
+    if (s->species_nshell[i] < 1 || s->species_nshell[i] > kMaxShells)
+      fail(AIMS_ERR_UNSUPPORTED, "system %d: species %d has %d shells (1..%d supported)", k, i,
+           s->species_nshell[i], kMaxShells);
+    nsh += s->species_nshell[i];
+  }
+  for (int i = 0; i < nsh; ++i)
+    if (s->shell_l[i] < 0 || s->shell_l[i] > kLmax)
+      fail(AIMS_ERR_UNSUPPORTED, "system %d: shell %d has l = %d (0..3 supported)", k, i, s->shell_l[i]);
+  for (int a = 0; a < s->n_atoms; ++a)
+    if (s->atom_species[a] < 0 || s->atom_species[a] >= s->n_species)
+      fail(AIMS_ERR_ARG, "system %d: atom %d has species %d out of range", k, a, s->atom_species[a]);
+  if (!finite_all(s->atom_xyz, 3 * (size_t)s->n_atoms)) fail(AIMS_ERR_ARG, "system %d: non-finite atom_xyz", k);
+  if (!finite_all(s->shell_R, (size_t)nsh * s->n_log) || !finite_all(s->shell_K, (size_t)nsh * s->n_log))
+    fail(AIMS_ERR_ARG, "system %d: non-finite radial table", k);
+  if (s->n_points > 0 && (!finite_all(s->pt_xyz, 3 * (size_t)s->n_points) || !finite_all(s->pt_w, (size_t)s->n_points)))
+    fail(AIMS_ERR_ARG, "system %d: non-finite grid", k);
+}
+
+size_t scratch_budget_elems() {
+  // elements per slab (two slabs); 1 GiB total in FP64 by default
+  double mb = 1024.0;
+  if (const char* e = getenv("AIMS_SCRATCH_MB")) mb = std::max(16.0, atof(e));
+  return (size_t)(mb * 1024.0 * 1024.0 / 16.0);
+}
+
+aims_grid* build(const aims_system* sys, int n_sys, int device, void* stream) {
+  if (n_sys < 1) fail(AIMS_ERR_ARG, "n_sys must be >= 1");
+  if (!sys) fail(AIMS_ERR_ARG, "null system array");
+  for (int k = 0; k < n_sys; ++k) validate_system(&sys[k], k);
+  for (int k = 1; k < n_sys; ++k)
+    if (sys[k].n_log != sys[0].n_log || sys[k].r0 != sys[0].r0 || sys[k].rc != sys[0].rc)
+      fail(AIMS_ERR_ARG, "all systems of one handle must share n_log, r0 and rc");
+
+  std::unique_ptr<aims_grid> g(new aims_grid());
+  g->device = device;
+  g->stream = (hipStream_t)stream;
+  g->n_sys = n_sys;
+  g->margin = sys[0].screen_margin > 0 ? sys[0].screen_margin : 1e-2;
+  const int n_log = sys[0].n_log;
+  g->rg.s0 = std::log(sys[0].r0);
+  g->rg.h = (std::log(sys[0].rc) - std::log(sys[0].r0)) / (n_log - 1);
+  g->rg.inv_h = 1.0 / g->rg.h;
+  g->rg.rc = sys[0].rc;
+  g->rg.n_log = n_log;
+  const double reach = sys[0].rc + g->margin;
+
+  // ---- species, splines, atoms ----------------------------------------------------------
+  std::vector<SpeciesDesc> species;
+  std::vector<int32_t> shell_l;
+  std::vector<double> spline64;
+  std::vector<int32_t> atom_species, atom_sys, species_nfn_all;
+  std::vector<std::vector<int>> atom_nfn(n_sys);
+  for (int k = 0; k < n_sys; ++k) {
+    const aims_system& s = sys[k];
+    const int sp_base = (int)species.size();
+    int sh_off = 0;
+    for (int i = 0; i < s.n_species; ++i) {
+      SpeciesDesc sd{};
+      sd.nshell = s.species_nshell[i];
+      sd.shell_l_off = (int)shell_l.size();
+      sd.spline_off = (int64_t)spline64.size();
+      int nfn = 0, lmax = 0;
+      for (int j = 0; j < sd.nshell; ++j) {
+        const int l = s.shell_l[sh_off + j];
+        shell_l.push_back(l);
+        nfn += 2 * l + 1;
+        lmax = std::max(lmax, l);
+      }
+      sd.nfn = nfn;
+      sd.lmax = lmax;
+      // coefficients at [(k * nshell + j) * 8 + c], c = R a..d, K a..d
+      std::vector<double> cR((size_t)(n_log - 1) * 4), cK((size_t)(n_log - 1) * 4);
+      spline64.resize(spline64.size() + (size_t)(n_log - 1) * sd.nshell * 8);
+      double* base = spline64.data() + sd.spline_off;
+      for (int j = 0; j < sd.nshell; ++j) {
+        natural_spline(s.shell_R + (size_t)(sh_off + j) * n_log, n_log, g->rg.h, cR.data());
+        natural_spline(s.shell_K + (size_t)(sh_off + j) * n_log, n_log, g->rg.h, cK.data());
+        for (int kk = 0; kk < n_log - 1; ++kk)
+          for (int c = 0; c < 4; ++c) {
+            base[((size_t)kk * sd.nshell + j) * 8 + c] = cR[4 * kk + c];
+            base[((size_t)kk * sd.nshell + j) * 8 + 4 + c] = cK[4 * kk + c];
+          }
+      }
+      species.push_back(sd);
+      species_nfn_all.push_back(nfn);
+      sh_off += sd.nshell;
+    }
+    SystemDesc sdsc{};
+    sdsc.mat_off = g->mat_total;
+    sdsc.atom_off = g->n_atoms;
+    int nb = 0;
+    for (int a = 0; a < s.n_atoms; ++a) {
+      const int gs = sp_base + s.atom_species[a];
+      atom_species.push_back(gs);
+      atom_sys.push_back(k);
+      atom_nfn[k].push_back(species[gs].nfn);
+      nb += species[gs].nfn;
+      for (int c = 0; c < 3; ++c) g->atom_xyz0.push_back(s.atom_xyz[3 * a + c]);
+    }
+    sdsc.nb = nb;
+    g->systems.push_back(sdsc);
+    g->sys_atom_range.push_back(g->n_atoms);
+    g->n_atoms += s.n_atoms;
+    g->sys_atom_range.push_back(g->n_atoms);
+    g->nb_total += nb;
+    g->mat_total += (int64_t)nb * nb;
+  }
+  std::vector<float> spline32(spline64.begin(), spline64.end());
+
+  // ---- points: batching and screening --------------------------------------------------
+  std::vector<double4> pts_sorted;
+  std::vector<int32_t> perm;
+  std::vector<int32_t> batch_atoms, batch_acol, batch_cols;
+  int64_t caller_base = 0;
+  for (int k = 0; k < n_sys; ++k) {
+    const aims_system& s = sys[k];
+    std::vector<int32_t> idx(s.n_points);
+    for (int64_t i = 0; i < s.n_points; ++i) idx[i] = (int32_t)i;
+    std::vector<std::pair<int64_t, int64_t>> segs;
+    bisect(s.pt_xyz, idx, 0, s.n_points, s.max_batch, segs);
+    const int64_t sorted_base = (int64_t)pts_sorted.size();
+    g->sys_pt_range.push_back(sorted_base);
+    for (int64_t i = 0; i < s.n_points; ++i) {
+      const int32_t q = idx[i];
+      pts_sorted.push_back(make_double4(s.pt_xyz[3 * q], s.pt_xyz[3 * q + 1], s.pt_xyz[3 * q + 2], s.pt_w[q]));
+      perm.push_back((int32_t)(caller_base + q));
+    }
+    g->sys_pt_range.push_back((int64_t)pts_sorted.size());
+    // per-batch relevant atoms (parallel), then concatenate in batch order
+    const int nseg = (int)segs.size();
+    std::vector<std::vector<int32_t>> rel(nseg);
+    std::vector<int> atom_col0(s.n_atoms + 1, 0);
+    for (int a = 0; a < s.n_atoms; ++a) atom_col0[a + 1] = atom_col0[a] + atom_nfn[k][a];
+    parallel_for(nseg, [&](int64_t b) {
+      const int64_t lo = segs[b].first, hi = segs[b].second;
+      double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+      for (int64_t i = lo; i < hi; ++i)
+        for (int c = 0; c < 3; ++c) {
+          mn[c] = std::min(mn[c], s.pt_xyz[3 * (int64_t)idx[i] + c]);
+          mx[c] = std::max(mx[c], s.pt_xyz[3 * (int64_t)idx[i] + c]);
+        }
+      double cen[3], rad2 = 0;
+      for (int c = 0; c < 3; ++c) {
+        cen[c] = 0.5 * (mn[c] + mx[c]);
+        rad2 += 0.25 * (mx[c] - mn[c]) * (mx[c] - mn[c]);
+      }
+      const double rad = std::sqrt(rad2);
+      for (int a = 0; a < s.n_atoms; ++a) {
+        const double* A = s.atom_xyz + 3 * a;
+        const double dc = std::sqrt((A[0] - cen[0]) * (A[0] - cen[0]) + (A[1] - cen[1]) * (A[1] - cen[1]) +
+                                    (A[2] - cen[2]) * (A[2] - cen[2]));
+        if (dc - rad >= reach) continue;
+        bool hit = false;
+        for (int64_t i = lo; i < hi && !hit; ++i) {
+          const double* p = s.pt_xyz + 3 * (int64_t)idx[i];
+          const double d2 = (p[0] - A[0]) * (p[0] - A[0]) + (p[1] - A[1]) * (p[1] - A[1]) +
+                            (p[2] - A[2]) * (p[2] - A[2]);
+          hit = d2 < reach * reach;
+        }
+        if (hit) rel[b].push_back(a);
+      }
+    });
+    for (int b = 0; b < nseg; ++b) {
+      BatchDesc d{};
+      d.pt_off = (int32_t)(sorted_base + segs[b].first);
+      d.n_p = (int32_t)(segs[b].second - segs[b].first);
+      d.atom_off = (int32_t)batch_atoms.size();
+      d.n_atoms = (int32_t)rel[b].size();
+      d.col_off = (int32_t)batch_cols.size();
+      d.sys = k;
+      d.ldp = round_up(d.n_p, kPad);
+      int col = 0;
+      for (int a : rel[b]) {
+        batch_atoms.push_back(g->systems[k].atom_off + a);
+        batch_acol.push_back(col);
+        for (int f = 0; f < atom_nfn[k][a]; ++f) batch_cols.push_back(atom_col0[a] + f);
+        col += atom_nfn[k][a];
+      }
+      d.n_b = col;
+      g->batches.push_back(d);
+      g->sum_np_nb2 += (double)d.n_p * d.n_b * d.n_b;
+      g->sum_nb2 += (double)d.n_b * d.n_b;
+    }
+    caller_base += s.n_points;
+  }
+  g->n_points = (int64_t)pts_sorted.size();
+  if ((int64_t)batch_cols.size() > (int64_t)INT32_MAX) fail(AIMS_ERR_UNSUPPORTED, "too many batch columns");
+
+  // ---- groups of batches sharing the scratch, and the tile work lists -------------------
+  const size_t budget = scratch_budget_elems();
+  std::vector<TileItem> ditems, hitems;
+  {
+    aims_grid::Group cur{0, 0, 0, 0, 0, 0, 0.0};
+    size_t used = 0;
+    const int nB = (int)g->batches.size();
+    for (int b = 0; b < nB; ++b) {
+      BatchDesc& d = g->batches[b];
+      const size_t need = (size_t)d.n_b * d.ldp;
+      if (used > 0 && used + need > budget) {
+        cur.b1 = b;
+        cur.d1 = (int64_t)ditems.size();
+        cur.h1 = (int64_t)hitems.size();
+        g->groups.push_back(cur);
+        cur = aims_grid::Group{b, b, (int64_t)ditems.size(), 0, (int64_t)hitems.size(), 0, 0.0};
+        used = 0;
+      }
+      cur.flops += 2.0 * d.n_p * (double)d.n_b * d.n_b;
+      d.slab_off = (int64_t)used;
+      used += need;
+      g->slab_elems = std::max(g->slab_elems, used);
+      const int tb = (d.n_b + kTile - 1) / kTile, tp = (d.n_p + kTile - 1) / kTile;
+      for (int ti = 0; ti < tb; ++ti) {
+        for (int tj = 0; tj < tp; ++tj) ditems.push_back(TileItem{b, (int16_t)ti, (int16_t)tj});
+        for (int tj = 0; tj < tb; ++tj) hitems.push_back(TileItem{b, (int16_t)ti, (int16_t)tj});
+      }
+    }
+    cur.b1 = nB;
+    cur.d1 = (int64_t)ditems.size();
+    cur.h1 = (int64_t)hitems.size();
+    if (cur.b1 > cur.b0) g->groups.push_back(cur);
+  }
+  g->n_ditems = (int64_t)ditems.size();
+  g->n_hitems = (int64_t)hitems.size();
+  if (g->n_ditems > INT32_MAX || g->n_hitems > INT32_MAX) fail(AIMS_ERR_UNSUPPORTED, "too many tiles");
+  // density-item range of each system (items are in batch order, batches in system order)
+  g->sys_item_range.assign(2 * (size_t)n_sys, 0);
+  {
+    std::vector<int64_t> first(n_sys, -1), last(n_sys, -1);
+    for (int64_t i = 0; i < g->n_ditems; ++i) {
+      const int s = g->batches[ditems[i].batch].sys;
+      if (first[s] < 0) first[s] = i;
+      last[s] = i + 1;
+    }
+    for (int s = 0; s < n_sys; ++s) {
+      g->sys_item_range[2 * s] = first[s] < 0 ? 0 : first[s];
+      g->sys_item_range[2 * s + 1] = first[s] < 0 ? 0 : last[s];
+    }
+  }
+
+  // ---- upload ---------------------------------------------------------------------------
+  hipchk(hipSetDevice(device), "hipSetDevice");
+  DeviceView& dv = g->dv;
+  dv.batches = g->upload(g->batches);
+  dv.systems = g->upload(g->systems);
+  dv.pts = g->upload(pts_sorted);
+  dv.perm = g->upload(perm);
+  dv.batch_atoms = g->upload(batch_atoms);
+  dv.batch_acol = g->upload(batch_acol);
+  dv.batch_cols = g->upload(batch_cols);
+  g->d_atom_xyz = g->upload(g->atom_xyz0);
+  dv.atom_xyz = g->d_atom_xyz;
+  dv.atom_species = g->upload(atom_species);
+  dv.atom_sys = g->upload(atom_sys);
+  dv.species = g->upload(species);
+  dv.shell_l = g->upload(shell_l);
+  dv.spline64 = g->upload(spline64);
+  dv.spline32 = g->upload(spline32);
+  dv.sys_pt_range = g->upload(g->sys_pt_range);
+  dv.sys_item_range = g->upload(g->sys_item_range);
+  dv.rg = g->rg;
+  dv.n_sys = n_sys;
+  g->d_ditems = g->upload(ditems);
+  g->d_hitems = g->upload(hitems);
+  g->d_n_sorted = (double*)g->alloc(std::max<int64_t>(1, g->n_points) * sizeof(double));
+  g->d_part = (double*)g->alloc((size_t)n_sys * g->nblk_finish * 2 * sizeof(double));
+  g->d_et_part = (double*)g->alloc(std::max<int64_t>(1, g->n_ditems) * sizeof(double));
+  g->d_P32 = (float*)g->alloc(std::max<int64_t>(1, g->mat_total) * sizeof(float));
+  g->d_slab1 = g->alloc(std::max<size_t>(1, g->slab_elems) * sizeof(double));
+  g->d_slab2 = g->alloc(std::max<size_t>(1, g->slab_elems) * sizeof(double));
+  return g.release();
+}
+
+// ---------------------------------------------------------------------------------------------
+// per-call helpers
+// ---------------------------------------------------------------------------------------------
+void require_device(const void* p, const char* name, bool nonempty = true) {
+  if (!nonempty) return;  // zero-length arrays are never touched
+  if (!p) fail(AIMS_ERR_ARG, "%s is NULL", name);
+  if (!is_device_ptr(p)) fail(AIMS_ERR_ARG, "%s must be device memory", name);
+}
+
+void check_prec(aims_precision p) {
+  if (p != AIMS_FP64 && p != AIMS_FP32 && p != AIMS_BF16X3)
+    fail(AIMS_ERR_ARG, "unknown precision %d", (int)p);
+  if (p == AIMS_BF16X3) fail(AIMS_ERR_UNSUPPORTED, "BF16x3 precision is not available in this build");
+}
+
+// Positions for this call: NULL = setup positions.  A given array (host or device) is read
+// synchronously and checked against the screening margin.
+void set_positions(aims_grid* g, const double* xyz) {
+  const size_t n = 3 * (size_t)g->n_atoms;
+  if (!xyz) {
+    if (g->moved) {
+      hipchk(hipMemcpyAsync(g->d_atom_xyz, g->atom_xyz0.data(), n * sizeof(double),
+                            hipMemcpyHostToDevice, g->stream), "restore positions");
+      hipchk(hipStreamSynchronize(g->stream), "restore positions");
+      g->moved = false;
+    }
+    return;
+  }
+  std::vector<double> h(n);
+  if (is_device_ptr(xyz)) {
+    hipchk(hipMemcpyAsync(h.data(), xyz, n * sizeof(double), hipMemcpyDeviceToHost, g->stream), "read positions");
+    hipchk(hipStreamSynchronize(g->stream), "read positions");
+  } else {
+    memcpy(h.data(), xyz, n * sizeof(double));
+  }
+  for (int a = 0; a < g->n_atoms; ++a) {
+    double d2 = 0;
+    for (int c = 0; c < 3; ++c) {
+      if (!std::isfinite(h[3 * a + c])) fail(AIMS_ERR_ARG, "non-finite position of atom %d", a);
+      const double d = h[3 * a + c] - g->atom_xyz0[3 * a + c];
+      d2 += d * d;
+    }
+    if (d2 > g->margin * g->margin)
+      fail(AIMS_ERR_STALE, "atom %d moved %.3g bohr since setup (margin %.3g)", a, std::sqrt(d2), g->margin);
+  }
+  hipchk(hipMemcpyAsync(g->d_atom_xyz, h.data(), n * sizeof(double), hipMemcpyHostToDevice, g->stream), "positions");
+  hipchk(hipStreamSynchronize(g->stream), "positions");
+  g->moved = true;
+}
+
+enum { kProfPhi = 0, kProfDensity = 1, kProfHS = 2, kProfBackward = 3, kProfFinish = 4 };
+const char* kProfNames[5] = {"phi_eval", "density", "hs", "backward", "finish"};
+
+// Runs one launch, bracketed by events when profiling is on.
+template <typename F>
+void timed(aims_grid* g, int kind, double work, const char* what, F&& launch) {
+  if (!g->profiling) {
+    hipchk(launch(), what);
+    return;
+  }
+  aims_grid::ProfRec r{kind, nullptr, nullptr, work};
+  hipchk(hipEventCreate(&r.a), "event");
+  hipchk(hipEventCreate(&r.b), "event");
+  hipchk(hipEventRecord(r.a, g->stream), "event");
+  hipchk(launch(), what);
+  hipchk(hipEventRecord(r.b, g->stream), "event");
+  g->prof_pending.push_back(r);
+}
+
+void prof_collect(aims_grid* g) {
+  if (g->prof_pending.empty()) return;
+  hipchk(hipStreamSynchronize(g->stream), "profile sync");
+  for (auto& r : g->prof_pending) {
+    float ms = 0.f;
+    hipchk(hipEventElapsedTime(&ms, r.a, r.b), "elapsed");
+    g->prof_count[r.kind] += 1;
+    g->prof_ms[r.kind] += ms;
+    g->prof_work[r.kind] += r.work;
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g->prof_pending.clear();
+}
+
+template <typename T>
+void run_density(aims_grid* g, const T* P, const double* v, double* n_out, double* sums_out) {
+  hipStream_t st = g->stream;
+  T* s1 = (T*)g->d_slab1;
+  T* s2 = (T*)g->d_slab2;
+  hipchk(launch_fill(g->d_n_sorted, (size_t)g->n_points, 0.0, st), "fill n");
+  for (const auto& gr : g->groups) {
+    timed(g, kProfPhi, 0.0, "phi_eval", [&] {
+      return launch_phi_eval<T>(g->dv, gr.b0, gr.b1 - gr.b0, kModeDensity, nullptr, s1, s2, st);
+    });
+    timed(g, kProfDensity, gr.flops, "density", [&] {
+      return launch_density<T>(g->dv, g->d_ditems + gr.d0, (int)(gr.d1 - gr.d0), P, s1, s2,
+                               g->d_n_sorted, g->d_et_part + gr.d0, st);
+    });
+  }
+  timed(g, kProfFinish, 0.0, "density_finish", [&] {
+    return launch_density_finish(g->dv, g->d_n_sorted, v, n_out, g->d_part, g->nblk_finish,
+                                 g->d_et_part, sums_out, st);
+  });
+}
+
+template <typename T>
+void run_hs(aims_grid* g, int mode, const double* v, double* out) {
+  hipStream_t st = g->stream;
+  T* s1 = (T*)g->d_slab1;
+  T* s2 = (T*)g->d_slab2;
+  hipchk(launch_fill(out, (size_t)g->mat_total, 0.0, st), "fill H");
+  for (const auto& gr : g->groups) {
+    timed(g, kProfPhi, 0.0, "phi_eval", [&] {
+      return launch_phi_eval<T>(g->dv, gr.b0, gr.b1 - gr.b0, mode, v, s1, s2, st);
+    });
+    timed(g, kProfHS, gr.flops, "hs", [&] {
+      return launch_hs<T>(g->dv, g->d_hitems + gr.h0, (int)(gr.h1 - gr.h0), s1, s2, out, st);
+    });
+  }
+}
+
+template <typename F>
+aims_status guarded(aims_grid* g, F&& f) {
+  try {
+    if (!g) fail(AIMS_ERR_ARG, "null handle");
+    hipchk(hipSetDevice(g->device), "hipSetDevice");
+    f();
+    return AIMS_OK;
+  } catch (const Fail& e) {
+    if (g) g->err = e.msg;
+    else g_setup_error = e.msg;
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    if (g) g->err = "host allocation failed";
+    return AIMS_ERR_OOM;
+  }
+}
+
+}  // namespace
+
+// -------------------------------------------------------------------------------------------------
+// C ABI
+// -------------------------------------------------------------------------------------------------
+extern "C" {
+
+aims_status aims_grid_setup_many(const aims_system* sys, int32_t n_sys, int device, void* hip_stream,
+                                 aims_grid** out) {
+  try {
+    if (!out) fail(AIMS_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    *out = build(sys, n_sys, device, hip_stream);
+    return AIMS_OK;
+  } catch (const Fail& e) {
+    g_setup_error = e.msg;
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    g_setup_error = "host allocation failed";
+    return AIMS_ERR_OOM;
+  }
+}
+
+aims_status aims_grid_setup(const aims_system* sys, int device, void* hip_stream, aims_grid** out) {
+  return aims_grid_setup_many(sys, 1, device, hip_stream, out);
+}
+
+aims_status aims_update_density(aims_grid* g, aims_precision prec, const double* atom_xyz,
+                                const double* P, const double* v_or_null, double* n_out,
+                                double* sums_out) {
+  return guarded(g, [&] {
+    check_prec(prec);
+    require_device(P, "P");
+    require_device(n_out, "n_out", g->n_points > 0);
+    require_device(sums_out, "sums_out");
+    if (v_or_null) require_device(v_or_null, "v", g->n_points > 0);
+    set_positions(g, atom_xyz);
+    if (prec == AIMS_FP64) {
+      run_density<double>(g, P, v_or_null, n_out, sums_out);
+    } else {
+      hipchk(launch_convert_f32(P, g->d_P32, (size_t)g->mat_total, g->stream), "convert P");
+      run_density<float>(g, g->d_P32, v_or_null, n_out, sums_out);
+    }
+  });
+}
+
+aims_status aims_integrate_h(aims_grid* g, aims_precision prec, const double* atom_xyz, const double* v,
+                             double* H, double* S_or_null) {
+  return guarded(g, [&] {
+    check_prec(prec);
+    require_device(v, "v", g->n_points > 0);
+    require_device(H, "H");
+    if (S_or_null) require_device(S_or_null, "S");
+    set_positions(g, atom_xyz);
+    if (prec == AIMS_FP64) {
+      run_hs<double>(g, kModeH, v, H);
+      if (S_or_null) run_hs<double>(g, kModeS, v, S_or_null);
+    } else {
+      run_hs<float>(g, kModeH, v, H);
+      if (S_or_null) run_hs<float>(g, kModeS, v, S_or_null);
+    }
+  });
+}
+
+aims_status aims_integrate_h_backward(aims_grid* g, aims_precision prec, const double* atom_xyz,
+                                      const double* P, const double* v, const double* gE,
+                                      double* dE_dP_or_null, double* dE_dv_or_null,
+                                      double* dE_dR_or_null) {
+  return guarded(g, [&] {
+    (void)prec; (void)atom_xyz; (void)P; (void)v; (void)gE;
+    (void)dE_dP_or_null; (void)dE_dv_or_null; (void)dE_dR_or_null;
+    fail(AIMS_ERR_UNSUPPORTED, "backward is not available in this build");
+  });
+}
+
+struct aims_step_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t stream = nullptr;
+};
+
+aims_status aims_step_graph_create(aims_grid* g, aims_precision prec, const double* P, const double* v,
+                                   double* n_out, double* sums_out, double* H, aims_step_graph** out) {
+  return guarded(g, [&] {
+    if (!out) fail(AIMS_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    check_prec(prec);
+    require_device(P, "P");
+    require_device(v, "v", g->n_points > 0);
+    require_device(n_out, "n_out", g->n_points > 0);
+    require_device(sums_out, "sums_out");
+    require_device(H, "H");
+    set_positions(g, nullptr);
+    if (!g->stream) fail(AIMS_ERR_ARG, "step graphs need a non-default stream at setup");
+    if (g->profiling) fail(AIMS_ERR_ARG, "disable profiling before capturing a step graph");
+    std::unique_ptr<aims_step_graph> sg(new aims_step_graph());
+    sg->stream = g->stream;
+    hipchk(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    try {
+      if (prec == AIMS_FP64) {
+        run_density<double>(g, P, v, n_out, sums_out);
+        run_hs<double>(g, kModeH, v, H);
+      } else {
+        hipchk(launch_convert_f32(P, g->d_P32, (size_t)g->mat_total, g->stream), "convert P");
+        run_density<float>(g, g->d_P32, v, n_out, sums_out);
+        run_hs<float>(g, kModeH, v, H);
+      }
+    } catch (...) {
+      hipGraph_t junk = nullptr;
+      (void)hipStreamEndCapture(g->stream, &junk);
+      if (junk) (void)hipGraphDestroy(junk);
+      throw;
+    }
+    hipchk(hipStreamEndCapture(g->stream, &sg->graph), "end capture");
+    hipchk(hipGraphInstantiate(&sg->exec, sg->graph, nullptr, nullptr, 0), "instantiate");
+    *out = sg.release();
+  });
+}
+
+aims_status aims_step_graph_launch(aims_step_graph* graph) {
+  if (!graph || !graph->exec) return AIMS_ERR_ARG;
+  return hipGraphLaunch(graph->exec, graph->stream) == hipSuccess ? AIMS_OK : AIMS_ERR_HIP;
+}
+
+void aims_step_graph_destroy(aims_step_graph* graph) {
+  if (!graph) return;
+  if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+  if (graph->graph) (void)hipGraphDestroy(graph->graph);
+  delete graph;
+}
+
+aims_status aims_profile_enable(aims_grid* g, int on) {
+  return guarded(g, [&] {
+    prof_collect(g);
+    g->profiling = on != 0;
+    for (int k = 0; k < 5; ++k) {
+      g->prof_count[k] = 0;
+      g->prof_ms[k] = 0.0;
+      g->prof_work[k] = 0.0;
+    }
+  });
+}
+
+aims_status aims_profile_read(aims_grid* g, const char* kernel, int64_t* launches, double* total_ms,
+                              double* work) {
+  return guarded(g, [&] {
+    if (!kernel) fail(AIMS_ERR_ARG, "kernel name is NULL");
+    int k = -1;
+    for (int i = 0; i < 5; ++i)
+      if (strcmp(kernel, kProfNames[i]) == 0) k = i;
+    if (k < 0) fail(AIMS_ERR_ARG, "unknown kernel family '%s'", kernel);
+    prof_collect(g);
+    if (launches) *launches = g->prof_count[k];
+    if (total_ms) *total_ms = g->prof_ms[k];
+    if (work) *work = g->prof_work[k];
+  });
+}
+
+int32_t aims_n_variants(aims_precision prec) { return (prec >= AIMS_FP64 && prec <= AIMS_BF16X3) ? 1 : 0; }
+
+aims_status aims_get_tuning(const aims_grid* g, aims_precision prec, aims_tuning* out) {
+  if (!g || !out || aims_n_variants(prec) == 0) return AIMS_ERR_ARG;
+  memset(out, 0, sizeof(*out));
+  out->n_buckets = 1;
+  out->nb_edges[0] = INT32_MAX;
+  out->variant[0] = 0;
+  return AIMS_OK;
+}
+
+aims_status aims_set_tuning(aims_grid* g, aims_precision prec, const aims_tuning* t) {
+  if (!g || !t || aims_n_variants(prec) == 0) return AIMS_ERR_ARG;
+  if (t->n_buckets < 1 || t->n_buckets > 16) return AIMS_ERR_ARG;
+  for (int k = 0; k < t->n_buckets; ++k)
+    if (t->variant[k] < 0 || t->variant[k] >= aims_n_variants(prec)) return AIMS_ERR_ARG;
+  return AIMS_OK;
+}
+
+aims_status aims_work_stats(const aims_grid* g, int64_t* n_batches, double* sum_np_nb2, double* sum_nb2) {
+  if (!g) return AIMS_ERR_ARG;
+  if (n_batches) *n_batches = (int64_t)g->batches.size();
+  if (sum_np_nb2) *sum_np_nb2 = g->sum_np_nb2;
+  if (sum_nb2) *sum_nb2 = g->sum_nb2;
+  return AIMS_OK;
+}
+
+int64_t aims_n_basis(const aims_grid* g) { return g ? g->nb_total : -1; }
+int64_t aims_n_points(const aims_grid* g) { return g ? g->n_points : -1; }
+int32_t aims_n_atoms(const aims_grid* g) { return g ? g->n_atoms : -1; }
+
+const char* aims_last_error(const aims_grid* g) { return g ? g->err.c_str() : g_setup_error.c_str(); }
+
+void aims_grid_destroy(aims_grid* g) { delete g; }
+
+}  // extern "C"

@@ -1,0 +1,51 @@
+// Launchers of the gfx950 kernels (implemented in kernels.hip), called by the host code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "aims_internal.h"
+
+namespace aims {
+
+enum { kModeDensity = 0, kModeH = 1, kModeS = 2 };
+
+// Device pointers and scalars of one handle, passed by value to the launchers.
+struct DeviceView {
+  const BatchDesc* batches;
+  const SystemDesc* systems;
+  const double4* pts;
+  const int32_t* perm;
+  const int32_t* batch_atoms;
+  const int32_t* batch_acol;
+  const int32_t* batch_cols;
+  const double* atom_xyz;
+  const int32_t* atom_species;
+  const int32_t* atom_sys;
+  const SpeciesDesc* species;
+  const int32_t* shell_l;
+  const double* spline64;
+  const float* spline32;
+  const int64_t* sys_pt_range;     // [n_sys][2] batch-order point range of each system
+  const int64_t* sys_item_range;   // [n_sys][2] density-item range of each system
+  RadialGrid rg;
+  int n_sys;
+};
+
+hipError_t launch_fill(double* x, size_t n, double val, hipStream_t st);
+hipError_t launch_convert_f32(const double* x, float* y, size_t n, hipStream_t st);
+
+template <typename T>
+hipError_t launch_phi_eval(const DeviceView& dv, int b0, int nbatch, int mode, const double* v,
+                           T* slab1, T* slab2, hipStream_t st);
+template <typename T>
+hipError_t launch_density(const DeviceView& dv, const TileItem* items, int n_items, const T* P,
+                          const T* slab1, const T* slab2, double* n_sorted, double* et_part,
+                          hipStream_t st);
+template <typename T>
+hipError_t launch_hs(const DeviceView& dv, const TileItem* items, int n_items, const T* slab1,
+                     const T* slab2, double* out, hipStream_t st);
+hipError_t launch_density_finish(const DeviceView& dv, const double* n_sorted, const double* v,
+                                 double* n_out, double* part, int nblk, const double* et_part,
+                                 double* sums_out, hipStream_t st);
+
+}  // namespace aims

@@ -1,0 +1,250 @@
+"""Python front of the HIP library: ``AimsGrid`` (one handle, device tensors in and out) and
+``AimsEnergy`` (a ``torch.autograd.Function`` whose backward is the library's backward kernel).
+
+PyTorch is used only for device memory and the stream; every step of the computation runs in
+the library's kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+from ctypes import POINTER, byref, c_double, c_int32, c_int64, c_void_p
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import PRECISION, AimsError, AimsSystem, AimsTuning
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if t.dtype != torch.float64:
+        raise TypeError("expected a float64 tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return c_void_p(t.data_ptr())
+
+
+def _np_ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(POINTER(ctype))
+
+
+class AimsGrid:
+    """One library handle over one or several systems.
+
+    ``systems``: objects with the fields atom_xyz, atom_species, species_nshell, shell_l, n_log,
+    r0, rc, shell_R, shell_K, pt_xyz, pt_w, max_batch (e.g. ``synth.Instance``)."""
+
+    def __init__(self, systems, device: int = 0, stream: Optional[torch.cuda.Stream] = None,
+                 screen_margin: float = 1e-2):
+        if not isinstance(systems, (list, tuple)):
+            systems = [systems]
+        self._L = _lib.load()
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        keep = []
+        arr = (AimsSystem * len(systems))()
+        for k, s in enumerate(systems):
+            f64 = lambda x: np.ascontiguousarray(x, dtype=np.float64)
+            i32 = lambda x: np.ascontiguousarray(x, dtype=np.int32)
+            fields = dict(atom_xyz=f64(s.atom_xyz), atom_species=i32(s.atom_species),
+                          species_nshell=i32(s.species_nshell), shell_l=i32(s.shell_l),
+                          shell_R=f64(s.shell_R), shell_K=f64(s.shell_K), pt_xyz=f64(s.pt_xyz),
+                          pt_w=f64(s.pt_w))
+            keep.append(fields)
+            a = arr[k]
+            a.n_atoms = fields["atom_xyz"].shape[0]
+            a.atom_xyz = _np_ptr(fields["atom_xyz"], c_double)
+            a.atom_species = _np_ptr(fields["atom_species"], c_int32)
+            a.n_species = fields["species_nshell"].shape[0]
+            a.species_nshell = _np_ptr(fields["species_nshell"], c_int32)
+            a.shell_l = _np_ptr(fields["shell_l"], c_int32)
+            a.n_log = int(s.n_log)
+            a.r0 = float(s.r0)
+            a.rc = float(s.rc)
+            a.shell_R = _np_ptr(fields["shell_R"], c_double)
+            a.shell_K = _np_ptr(fields["shell_K"], c_double)
+            a.n_points = fields["pt_xyz"].shape[0]
+            a.pt_xyz = _np_ptr(fields["pt_xyz"], c_double)
+            a.pt_w = _np_ptr(fields["pt_w"], c_double)
+            a.max_batch = int(s.max_batch)
+            a.screen_margin = float(screen_margin)
+        h = c_void_p()
+        with torch.cuda.device(self.device):
+            st = self._L.aims_grid_setup_many(arr, len(systems), device,
+                                              c_void_p(self.stream.cuda_stream), byref(h))
+        if st != 0:
+            raise AimsError(st, self._L.aims_last_error(None).decode())
+        self._h = h
+        self.n_sys = len(systems)
+        self.nb_sys = [self._nb_of(s) for s in systems]
+        self.n_basis = int(self._L.aims_n_basis(h))
+        self.n_points = int(self._L.aims_n_points(h))
+        self.n_atoms = int(self._L.aims_n_atoms(h))
+        self.mat_elems = int(sum(nb * nb for nb in self.nb_sys))
+
+    @staticmethod
+    def _nb_of(s) -> int:
+        off = np.concatenate([[0], np.cumsum(s.species_nshell)]).astype(int)
+        sl = np.asarray(s.shell_l)
+        nfn = [int(np.sum(2 * sl[off[i]:off[i + 1]] + 1)) for i in range(len(s.species_nshell))]
+        return int(sum(nfn[int(sp)] for sp in np.asarray(s.atom_species)))
+
+    # ------------------------------------------------------------------------------------------
+    def _check(self, st):
+        if st != 0:
+            raise AimsError(st, self._L.aims_last_error(self._h).decode())
+
+    def _new(self, *shape):
+        return torch.empty(*shape, dtype=torch.float64, device=self.device)
+
+    def update_density(self, P: torch.Tensor, v: Optional[torch.Tensor] = None,
+                       prec: str = "fp64", atom_xyz=None, n_out=None, sums_out=None):
+        """n [n_points] (caller order) and sums [n_sys, 3] = (N, E_V, E_T)."""
+        n = self._new(self.n_points) if n_out is None else n_out
+        sums = self._new(self.n_sys, 3) if sums_out is None else sums_out
+        with torch.cuda.device(self.device):
+            self._check(self._L.aims_update_density(self._h, PRECISION[prec], self._xyz(atom_xyz),
+                                                    _ptr(P), _ptr(v), _ptr(n), _ptr(sums)))
+        return n, sums
+
+    def integrate_h(self, v: torch.Tensor, prec: str = "fp64", want_S: bool = False,
+                    atom_xyz=None, H_out=None, S_out=None):
+        """Flat H (and S) buffers of mat_elems entries; use ``blocks`` to view per system."""
+        H = self._new(self.mat_elems) if H_out is None else H_out
+        S = (self._new(self.mat_elems) if S_out is None else S_out) if want_S else None
+        with torch.cuda.device(self.device):
+            self._check(self._L.aims_integrate_h(self._h, PRECISION[prec], self._xyz(atom_xyz),
+                                                 _ptr(v), _ptr(H), _ptr(S)))
+        return H, S
+
+    def backward(self, P, v, gE, prec: str = "fp64", atom_xyz=None, want=("P", "v", "R")):
+        dP = self._new(self.mat_elems) if "P" in want else None
+        dv = self._new(self.n_points) if "v" in want else None
+        dR = self._new(self.n_atoms, 3) if "R" in want else None
+        with torch.cuda.device(self.device):
+            self._check(self._L.aims_integrate_h_backward(
+                self._h, PRECISION[prec], self._xyz(atom_xyz), _ptr(P), _ptr(v), _ptr(gE),
+                _ptr(dP), _ptr(dv), _ptr(dR)))
+        return dP, dv, dR
+
+    def blocks(self, flat: torch.Tensor):
+        """Views of a flat matrix buffer as one nb_s x nb_s matrix per system."""
+        out, off = [], 0
+        for nb in self.nb_sys:
+            out.append(flat[off:off + nb * nb].view(nb, nb))
+            off += nb * nb
+        return out
+
+    def work_stats(self):
+        nbt = c_int64()
+        s1 = c_double()
+        s2 = c_double()
+        self._check(self._L.aims_work_stats(self._h, byref(nbt), byref(s1), byref(s2)))
+        return {"n_batches": nbt.value, "sum_np_nb2": s1.value, "sum_nb2": s2.value,
+                "flops_per_step": 4.0 * s1.value}
+
+    def get_tuning(self, prec="fp64"):
+        t = AimsTuning()
+        self._check(self._L.aims_get_tuning(self._h, PRECISION[prec], byref(t)))
+        return {"nb_edges": list(t.nb_edges[:t.n_buckets]), "variant": list(t.variant[:t.n_buckets])}
+
+    def set_tuning(self, nb_edges: Sequence[int], variant: Sequence[int], prec="fp64"):
+        t = AimsTuning()
+        t.n_buckets = len(nb_edges)
+        for k, (e, v) in enumerate(zip(nb_edges, variant)):
+            t.nb_edges[k] = int(e)
+            t.variant[k] = int(v)
+        self._check(self._L.aims_set_tuning(self._h, PRECISION[prec], byref(t)))
+
+    def n_variants(self, prec="fp64"):
+        return int(self._L.aims_n_variants(PRECISION[prec]))
+
+    def profile(self, on: bool = True):
+        self._check(self._L.aims_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self, kernel: str):
+        """(launches, total_ms, algorithmic flops) of one kernel family since profiling began."""
+        n = c_int64()
+        ms = c_double()
+        w = c_double()
+        self._check(self._L.aims_profile_read(self._h, kernel.encode(), byref(n), byref(ms), byref(w)))
+        return n.value, ms.value, w.value
+
+    def step_graph(self, P, v, n_out, sums_out, H_out, prec="fp64"):
+        return StepGraph(self, P, v, n_out, sums_out, H_out, prec)
+
+    def _xyz(self, atom_xyz):
+        if atom_xyz is None:
+            return None
+        if isinstance(atom_xyz, torch.Tensor):
+            if atom_xyz.is_cuda:
+                return _ptr(atom_xyz.contiguous())
+            atom_xyz = atom_xyz.numpy()
+        self._xyz_keep = np.ascontiguousarray(atom_xyz, dtype=np.float64)
+        return c_void_p(self._xyz_keep.ctypes.data)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.aims_grid_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class StepGraph:
+    """One s.c.f. step (density update + H integration) captured in a HIP graph."""
+
+    def __init__(self, grid: AimsGrid, P, v, n_out, sums_out, H_out, prec="fp64"):
+        self.grid = grid
+        self._keep = (P, v, n_out, sums_out, H_out)
+        h = c_void_p()
+        with torch.cuda.device(grid.device):
+            grid._check(grid._L.aims_step_graph_create(grid._h, PRECISION[prec], _ptr(P), _ptr(v),
+                                                       _ptr(n_out), _ptr(sums_out), _ptr(H_out),
+                                                       byref(h)))
+        self._g = h
+
+    def launch(self):
+        st = self.grid._L.aims_step_graph_launch(self._g)
+        if st != 0:
+            raise AimsError(st, "graph launch failed")
+
+    def __del__(self):
+        try:
+            if self._g:
+                self.grid._L.aims_step_graph_destroy(self._g)
+        except Exception:
+            pass
+
+
+class AimsEnergy(torch.autograd.Function):
+    """E(P, v, R) = sum_p w_p v_p n(p) + sum_p w_p sum_ij P_ij phi_i tphi_j through the library.
+
+    forward(grid, P_flat, v, R, prec) -> E (0-d float64 tensor, single system);
+    backward returns dE/dP, dE/dv and dE/dR from the library's backward kernels."""
+
+    @staticmethod
+    def forward(ctx, grid: AimsGrid, P, v, R, prec="fp64"):
+        if grid.n_sys != 1:
+            raise ValueError("AimsEnergy handles one system per handle")
+        _, sums = grid.update_density(P.detach().contiguous(), v.detach().contiguous(), prec=prec,
+                                      atom_xyz=R.detach())
+        ctx.grid, ctx.prec = grid, prec
+        ctx.save_for_backward(P, v, R)
+        return sums[0, 1] + sums[0, 2]
+
+    @staticmethod
+    def backward(ctx, gE):
+        P, v, R = ctx.saved_tensors
+        grid = ctx.grid
+        gE = gE.detach().reshape(1).to(torch.float64).contiguous()
+        dP, dv, dR = grid.backward(P.detach().contiguous(), v.detach().contiguous(), gE,
+                                   prec=ctx.prec, atom_xyz=R.detach())
+        return None, dP.view_as(P), dv.view_as(v), dR.view_as(R), None

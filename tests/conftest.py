@@ -23,3 +23,23 @@ def c1():
 def c1_oracle(c1):
     from oracle import GridOracle
     return GridOracle(c1)
+
+
+@pytest.fixture(scope="session")
+def gpu():
+    """The HIP library on cuda:0.  GPU tests fail (they do not skip) when either is missing."""
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    from paper_2208_12335_amd import _lib
+    _lib.load()
+    return torch.device("cuda", 0)
+
+
+def relerr(x, ref):
+    """Norm-wise relative error max|x - ref| / max|ref| (0 when both are zero)."""
+    import numpy as np
+    x = np.asarray(x, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    den = np.max(np.abs(ref)) if ref.size else 0.0
+    num = np.max(np.abs(x - ref)) if ref.size else 0.0
+    return 0.0 if den == 0 and num == 0 else num / den

@@ -1,0 +1,93 @@
+"""The C-ABI library loads and exports every symbol the header declares; argument validation
+happens on the host before any device work (these calls never reach a GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "aims_grid.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(aims_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2208_12335_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2208_12335_amd.build import build
+        build()
+    return _lib.load()
+
+
+def test_header_symbols_exported(lib):
+    from paper_2208_12335_amd._lib import SIGNATURES
+    names = _declared_symbols()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in SIGNATURES, n
+
+
+def _system(c1, **over):
+    from paper_2208_12335_amd._lib import AimsSystem
+    keep = {}
+    def arr(name, dt, v):
+        keep[name] = np.ascontiguousarray(v, dtype=dt)
+        return keep[name].ctypes.data_as(ctypes.POINTER(ctypes.c_double if dt == np.float64 else ctypes.c_int32))
+    s = AimsSystem()
+    s.n_atoms = c1.n_atoms
+    s.atom_xyz = arr("xyz", np.float64, c1.atom_xyz)
+    s.atom_species = arr("sp", np.int32, c1.atom_species)
+    s.n_species = len(c1.species_nshell)
+    s.species_nshell = arr("ns", np.int32, c1.species_nshell)
+    s.shell_l = arr("l", np.int32, over.pop("shell_l", c1.shell_l))
+    s.n_log = over.pop("n_log", c1.n_log)
+    s.r0, s.rc = over.pop("r0", c1.r0), c1.rc
+    s.shell_R = arr("R", np.float64, c1.shell_R)
+    s.shell_K = arr("K", np.float64, c1.shell_K)
+    s.n_points = c1.n_points
+    s.pt_xyz = arr("p", np.float64, c1.pt_xyz)
+    s.pt_w = arr("w", np.float64, c1.pt_w)
+    s.max_batch = over.pop("max_batch", c1.max_batch)
+    s.screen_margin = 0.01
+    return s, keep
+
+
+@pytest.mark.parametrize("over,status", [
+    ({"shell_l": None}, -5),          # l = 4 -> unsupported
+    ({"n_log": 3}, -1),
+    ({"r0": 20.0}, -1),               # r0 >= rc
+    ({"max_batch": 0}, -5),
+    ({"max_batch": 100000}, -5),
+])
+def test_setup_validation_errors(lib, c1, over, status):
+    if "shell_l" in over:
+        l = np.array(c1.shell_l)
+        l[0] = 4
+        over = {"shell_l": l}
+    s, keep = _system(c1, **over)
+    h = ctypes.c_void_p()
+    st = lib.aims_grid_setup(ctypes.byref(s), 0, None, ctypes.byref(h))
+    assert st == status
+    assert h.value is None
+    msg = lib.aims_last_error(None).decode()
+    assert len(msg) > 5 and msg != "no error"
+
+
+def test_null_arguments(lib, c1):
+    h = ctypes.c_void_p()
+    assert lib.aims_grid_setup(None, 0, None, ctypes.byref(h)) == -1
+    assert lib.aims_grid_setup_many(None, 0, 0, None, ctypes.byref(h)) == -1
+    assert lib.aims_update_density(None, 0, None, None, None, None, None) == -1
+    assert lib.aims_integrate_h(None, 0, None, None, None, None) == -1
+    assert lib.aims_work_stats(None, None, None, None) == -1
+    assert lib.aims_n_basis(None) == -1
+    assert lib.aims_step_graph_launch(None) == -1
+    lib.aims_grid_destroy(None)
+    lib.aims_step_graph_destroy(None)
