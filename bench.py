@@ -52,7 +52,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mixed", default="fp32", choices=["fp32", "bf16x3"])
+    ap.add_argument("--forms", default="fp64,fp32,bf16x3",
+                    help="precision forms to time (fp64 is always included)")
     ap.add_argument("--cpu-chunks", type=int, default=10,
                     help="point chunks of the oracle's CPU baseline sample (0 = skip)")
     args = ap.parse_args()
@@ -88,8 +89,9 @@ def main():
         g.update_density(P, v, prec=prec, n_out=n, sums_out=sums)
         g.integrate_h(v, prec=prec, H_out=H)
 
+    forms = ["fp64"] + [f for f in args.forms.split(",") if f and f != "fp64"]
     res = {}
-    for prec in ("fp64", args.mixed):
+    for prec in forms:
         for _ in range(args.warmup):
             step(prec)
         torch.cuda.synchronize()
@@ -113,37 +115,48 @@ def main():
         s = sums.cpu().numpy()[0]
         res[prec] = {"ms_per_step": ms, "wall_ms_per_step": wall, "gflops": F / (ms * 1e-3) / 1e9,
                      "N": float(s[0]), "E": float(s[1] + s[2]), "kernels": kern,
-                     "H_fro": float(torch.linalg.norm(H).item())}
+                     "H_fro": float(torch.linalg.norm(H).item()),
+                     "h_merge": g.get_tuning(prec)["h_merge"]}
         print(f"[bench] {prec}: {ms:.3f} ms/step, {res[prec]['gflops']:.1f} GFLOP/s", file=sys.stderr,
               flush=True)
 
-    mixed = res[args.mixed]
-    dE = abs(mixed["E"] - res["fp64"]["E"])
-    # dominant kernel of the mixed form: the MFMA kernel with the most time per step
-    dom = max(("density", "hs"), key=lambda k: mixed["kernels"][k]["ms_per_step"])
-    kd = mixed["kernels"][dom]
+    ref = res["fp64"]
+    for prec, r in res.items():
+        r["abs_dE_Ha_vs_fp64"] = abs(r["E"] - ref["E"])
+        r["rel_dN_vs_fp64"] = abs(r["N"] - ref["N"]) / abs(ref["N"])
+        r["rel_dHfro_vs_fp64"] = abs(r["H_fro"] - ref["H_fro"]) / ref["H_fro"]
+        r["meets_1e-6_Ha"] = bool(r["abs_dE_Ha_vs_fp64"] <= 1e-6)
+    # headline: the fastest form that holds the total energy within 1e-6 Ha of the FP64 form
+    ok = [p for p in res if res[p]["meets_1e-6_Ha"]]
+    head = min(ok, key=lambda p: res[p]["ms_per_step"])
+    hr = res[head]
+    dom = max(("density", "hs"), key=lambda k: hr["kernels"][k]["ms_per_step"])
+    kd = hr["kernels"][dom]
     achieved = kd["work_flop"] / (kd["ms_per_step"] * args.steps * 1e-3) / 1e12 if kd["ms_per_step"] else 0.0
-    roof = {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[args.mixed],
-            "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[args.mixed], "traffic": None,
+    roof = {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[head],
+            "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[head], "traffic": None,
             "avg_launch_ms": kd["avg_launch_ms"], "launches_per_step": kd["launches"] / args.steps}
+    fastest = min(res, key=lambda p: res[p]["ms_per_step"])
     line = {
-        "metric": "H+density integration GFLOP/s (mixed precision, FP32 MFMA per batch, FP64 reduce)",
-        "value": mixed["gflops"], "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": mixed["ms_per_step"], "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if args.mixed == "fp32" else "bf16x3",
-        "data": "synthetic",
+        "metric": "H+density integration GFLOP/s and ms per SCF step (fastest form within 1e-6 Ha "
+                  "of FP64; mixed forms reported beside it)",
+        "value": hr["gflops"], "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": hr["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[head],
+        "data": "synthetic", "headline_form": head,
         "config": {"workload": "64-atom random cluster (Z in {1,6,8}, box 20 bohr), l<=3 NAO basis "
                                f"({inst.n_basis} functions), 75x302 grid ({inst.n_points} points), "
                                "batches <= 256 points; one step = density update + H integration",
                    "n_points": inst.n_points, "n_basis": inst.n_basis,
-                   "n_batches": ws["n_batches"], "flop_per_step": F, "parallelism": "single GPU"},
-        "fp64": {"ms_per_step": res["fp64"]["ms_per_step"], "gflops": res["fp64"]["gflops"],
-                 "frac_of_fp64_peak": res["fp64"]["gflops"] / 1e3 / PEAK_TFLOPS["fp64"]},
-        "mixed_vs_fp64": {"speedup": res["fp64"]["ms_per_step"] / mixed["ms_per_step"],
-                          "abs_dE_Ha": dE, "E_fp64": res["fp64"]["E"], "E_mixed": mixed["E"],
-                          "meets_1e-6_Ha": bool(dE <= 1e-6),
-                          "rel_dN": abs(mixed["N"] - res["fp64"]["N"]) / abs(res["fp64"]["N"]),
-                          "rel_dH_fro": abs(mixed["H_fro"] - res["fp64"]["H_fro"]) / res["fp64"]["H_fro"]},
+                   "n_batches": ws["n_batches"], "flop_per_step": F, "sum_nb2": ws["sum_nb2"],
+                   "parallelism": "single GPU"},
+        "forms": {p: {k: r[k] for k in ("ms_per_step", "gflops", "abs_dE_Ha_vs_fp64", "meets_1e-6_Ha",
+                                         "rel_dN_vs_fp64", "rel_dHfro_vs_fp64", "h_merge", "E", "N")}
+                  for p, r in res.items()},
+        "fastest_form": {"form": fastest, "ms_per_step": res[fastest]["ms_per_step"],
+                         "gflops": res[fastest]["gflops"],
+                         "speedup_vs_fp64": ref["ms_per_step"] / res[fastest]["ms_per_step"]},
         "kernels": {p: r["kernels"] for p, r in res.items()},
         "roofline": roof,
     }

@@ -140,11 +140,18 @@ aims_status aims_step_graph_create(aims_grid *g, aims_precision prec, const doub
 aims_status aims_step_graph_launch(aims_step_graph *graph);
 void aims_step_graph_destroy(aims_step_graph *graph);
 
-/* Kernel tile configuration chosen per (points, basis) bucket; see aims_tune_*. */
+/* Tunable execution parameters of one precision (chosen by the project's autotuner, which
+ * times the candidates on the live device; see paper_2208_12335_amd.autotune).
+ *   h_merge  the H/S pass uses batches of up to max_batch << h_merge points (the same bisection
+ *            stopped h_merge levels earlier): fewer FP64 scatter-adds into H for slightly more
+ *            flops.  0..4.  Changing it builds that partition once (device allocation).
+ *   variant  MFMA kernel variant per basis-size bucket: batches with nb <= nb_edges[k] (the
+ *            first such k) use variant[k]; 0 <= variant < aims_n_variants(). */
 typedef struct {
-  int32_t n_buckets;            /* number of buckets, <= 16                                 */
-  int32_t nb_edges[16];         /* bucket k holds batches with nb <= nb_edges[k] (ascending) */
-  int32_t variant[16];          /* kernel variant per bucket (0 .. aims_n_variants()-1)      */
+  int32_t h_merge;
+  int32_t n_buckets;            /* 1..8                                                     */
+  int32_t nb_edges[8];          /* ascending; the last bucket takes every larger batch      */
+  int32_t variant[8];
 } aims_tuning;
 int32_t aims_n_variants(aims_precision prec);
 aims_status aims_get_tuning(const aims_grid *g, aims_precision prec, aims_tuning *out);

@@ -37,7 +37,8 @@ class AimsSystem(ctypes.Structure):
 
 
 class AimsTuning(ctypes.Structure):
-    _fields_ = [("n_buckets", c_int32), ("nb_edges", c_int32 * 16), ("variant", c_int32 * 16)]
+    _fields_ = [("h_merge", c_int32), ("n_buckets", c_int32), ("nb_edges", c_int32 * 8),
+                ("variant", c_int32 * 8)]
 
 
 # every symbol the header declares, with its signature

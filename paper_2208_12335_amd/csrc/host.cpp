@@ -133,8 +133,33 @@ bool is_device_ptr(const void* p) {
 }  // namespace
 
 // -------------------------------------------------------------------------------------------------
-// the handle
+// batch sets and the handle
 // -------------------------------------------------------------------------------------------------
+// One partition of the (batch-ordered) points into batches, with per-batch screening, the groups
+// of batches that share the scratch slabs, and the MFMA tile work list.  The density pass uses
+// the partition at max_batch; the H/S pass may use a coarser one (max_batch << merge, i.e. the
+// bisection stopped `merge` levels earlier), which trades a few more flops for fewer FP64
+// scatter-adds into H.
+struct BatchSet {
+  int merge = 0;
+  bool density = false;            // tile list for the density kernel (else for the H kernel)
+  std::vector<BatchDesc> batches;
+  std::vector<int32_t> batch_atoms, batch_acol, batch_cols;
+  struct Group {
+    int b0, b1;                    // batches
+    int64_t i0, i1;                // tile items
+    double flops;                  // sum over the group's batches of 2 n_p n_b^2
+  };
+  std::vector<Group> groups;
+  std::vector<TileItem> items;
+  std::vector<int64_t> sys_item_range;
+  size_t slab_elems = 0;
+  double sum_np_nb2 = 0, sum_nb2 = 0;
+  // device copies
+  DeviceView dv{};
+  TileItem* d_items = nullptr;
+};
+
 struct aims_grid {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -151,19 +176,15 @@ struct aims_grid {
   std::vector<double> atom_xyz0;      // setup positions
   bool moved = false;                 // device positions differ from the setup positions
   std::vector<SystemDesc> systems;
-  std::vector<BatchDesc> batches;
-  std::vector<int64_t> sys_pt_range, sys_item_range, sys_atom_range;
+  std::vector<int64_t> sys_pt_range, sys_atom_range;
+  std::vector<int> sys_max_batch;
+  std::vector<std::vector<int>> atom_nfn;     // per system, per atom
+  std::vector<std::vector<int>> atom_col0;    // per system, per atom: first basis index
+  std::vector<double4> pts_sorted;            // host copy of the batch-ordered points
 
-  struct Group {
-    int b0, b1;
-    int64_t d0, d1;   // density items
-    int64_t h0, h1;   // H items
-    double flops;     // sum over the group's batches of 2 n_p n_b^2
-  };
-  std::vector<Group> groups;
-  int64_t n_ditems = 0, n_hitems = 0;
-  size_t slab_elems = 0;
-  double sum_np_nb2 = 0, sum_nb2 = 0;
+  BatchSet dens;                              // density partition (merge 0)
+  std::vector<std::unique_ptr<BatchSet>> hsets;  // H partitions by merge level (built on demand)
+  int h_merge[3] = {1, 2, 2};                 // per precision
   int nblk_finish = 64;
 
   // profiling
@@ -179,9 +200,7 @@ struct aims_grid {
   double prof_work[5] = {0, 0, 0, 0, 0};
 
   std::vector<void*> owned;           // device allocations
-  DeviceView dv{};
-  TileItem* d_ditems = nullptr;
-  TileItem* d_hitems = nullptr;
+  DeviceView common{};                // device pointers shared by every batch set
   double* d_atom_xyz = nullptr;
   double* d_n_sorted = nullptr;
   double* d_part = nullptr;
@@ -189,6 +208,7 @@ struct aims_grid {
   float* d_P32 = nullptr;
   void* d_slab1 = nullptr;
   void* d_slab2 = nullptr;
+  size_t slab_cap = 0;                // elements per slab currently allocated
 
   ~aims_grid() {
     if (!owned.empty()) {
@@ -209,6 +229,13 @@ struct aims_grid {
     }
     owned.push_back(p);
     return p;
+  }
+  void release(void* p) {
+    auto it = std::find(owned.begin(), owned.end(), p);
+    if (it != owned.end()) {
+      (void)hipFree(p);
+      owned.erase(it);
+    }
   }
   template <typename T>
   T* upload(const std::vector<T>& v) {
@@ -266,6 +293,156 @@ size_t scratch_budget_elems() {
   return (size_t)(mb * 1024.0 * 1024.0 / 16.0);
 }
 
+// Segments of the batch-ordered points of one system at a given batch size: the same median
+// splits as the set-up bisection (mid = lo + (hi - lo) / 2), stopped once a segment holds at
+// most maxb points.  Because the set-up bisection already ordered the points, every segment is
+// a contiguous range.
+void segments(int64_t lo, int64_t hi, int64_t maxb, std::vector<std::pair<int64_t, int64_t>>& out) {
+  if (hi - lo <= maxb) {
+    if (hi > lo) out.emplace_back(lo, hi);
+    return;
+  }
+  const int64_t mid = lo + (hi - lo) / 2;
+  segments(lo, mid, maxb, out);
+  segments(mid, hi, maxb, out);
+}
+
+void build_set(aims_grid* g, BatchSet& bs, int merge, bool density) {
+  bs.merge = merge;
+  bs.density = density;
+  const double reach = g->rg.rc + g->margin;
+  for (int k = 0; k < g->n_sys; ++k) {
+    const int64_t base = g->sys_pt_range[2 * k], end = g->sys_pt_range[2 * k + 1];
+    std::vector<std::pair<int64_t, int64_t>> segs;
+    segments(base, end, (int64_t)g->sys_max_batch[k] << merge, segs);
+    const int nseg = (int)segs.size();
+    const int a0 = g->systems[k].atom_off;
+    const int na = (int)g->atom_nfn[k].size();
+    std::vector<std::vector<int32_t>> rel(nseg);
+    parallel_for(nseg, [&](int64_t b) {
+      const int64_t lo = segs[b].first, hi = segs[b].second;
+      double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+      for (int64_t i = lo; i < hi; ++i) {
+        const double4& p = g->pts_sorted[i];
+        const double c3[3] = {p.x, p.y, p.z};
+        for (int c = 0; c < 3; ++c) {
+          mn[c] = std::min(mn[c], c3[c]);
+          mx[c] = std::max(mx[c], c3[c]);
+        }
+      }
+      double cen[3], rad2 = 0;
+      for (int c = 0; c < 3; ++c) {
+        cen[c] = 0.5 * (mn[c] + mx[c]);
+        rad2 += 0.25 * (mx[c] - mn[c]) * (mx[c] - mn[c]);
+      }
+      const double rad = std::sqrt(rad2);
+      for (int a = 0; a < na; ++a) {
+        const double* A = g->atom_xyz0.data() + 3 * (size_t)(a0 + a);
+        const double dc = std::sqrt((A[0] - cen[0]) * (A[0] - cen[0]) + (A[1] - cen[1]) * (A[1] - cen[1]) +
+                                    (A[2] - cen[2]) * (A[2] - cen[2]));
+        if (dc - rad >= reach) continue;
+        bool hit = false;
+        for (int64_t i = lo; i < hi && !hit; ++i) {
+          const double4& p = g->pts_sorted[i];
+          const double d2 = (p.x - A[0]) * (p.x - A[0]) + (p.y - A[1]) * (p.y - A[1]) +
+                            (p.z - A[2]) * (p.z - A[2]);
+          hit = d2 < reach * reach;
+        }
+        if (hit) rel[b].push_back(a);
+      }
+    });
+    for (int b = 0; b < nseg; ++b) {
+      BatchDesc d{};
+      d.pt_off = (int32_t)segs[b].first;
+      d.n_p = (int32_t)(segs[b].second - segs[b].first);
+      d.atom_off = (int32_t)bs.batch_atoms.size();
+      d.n_atoms = (int32_t)rel[b].size();
+      d.col_off = (int32_t)bs.batch_cols.size();
+      d.sys = k;
+      d.ldp = round_up(d.n_p, kPad);
+      int col = 0;
+      for (int a : rel[b]) {
+        bs.batch_atoms.push_back(a0 + a);
+        bs.batch_acol.push_back(col);
+        for (int f = 0; f < g->atom_nfn[k][a]; ++f) bs.batch_cols.push_back(g->atom_col0[k][a] + f);
+        col += g->atom_nfn[k][a];
+      }
+      d.n_b = col;
+      bs.batches.push_back(d);
+      bs.sum_np_nb2 += (double)d.n_p * d.n_b * d.n_b;
+      bs.sum_nb2 += (double)d.n_b * d.n_b;
+    }
+  }
+  if ((int64_t)bs.batch_cols.size() > (int64_t)INT32_MAX) fail(AIMS_ERR_UNSUPPORTED, "too many batch columns");
+
+  // groups of batches sharing the scratch, and the tile work list
+  const size_t budget = scratch_budget_elems();
+  BatchSet::Group cur{0, 0, 0, 0, 0.0};
+  size_t used = 0;
+  const int nB = (int)bs.batches.size();
+  for (int b = 0; b < nB; ++b) {
+    BatchDesc& d = bs.batches[b];
+    const size_t need = (size_t)round_up(d.n_b, 32) * d.ldp;
+    if (used > 0 && used + need > budget) {
+      cur.b1 = b;
+      cur.i1 = (int64_t)bs.items.size();
+      bs.groups.push_back(cur);
+      cur = BatchSet::Group{b, b, (int64_t)bs.items.size(), 0, 0.0};
+      used = 0;
+    }
+    cur.flops += 2.0 * d.n_p * (double)d.n_b * d.n_b;
+    d.slab_off = (int64_t)used;
+    used += need;
+    bs.slab_elems = std::max(bs.slab_elems, used);
+    const int tb = (d.n_b + kTile - 1) / kTile, tp = (d.n_p + kTile - 1) / kTile;
+    for (int ti = 0; ti < tb; ++ti)
+      for (int tj = 0; tj < (density ? tp : tb); ++tj) bs.items.push_back(TileItem{b, (int16_t)ti, (int16_t)tj});
+  }
+  cur.b1 = nB;
+  cur.i1 = (int64_t)bs.items.size();
+  if (cur.b1 > cur.b0) bs.groups.push_back(cur);
+  if ((int64_t)bs.items.size() > INT32_MAX) fail(AIMS_ERR_UNSUPPORTED, "too many tiles");
+  // item range of each system (items are in batch order, batches in system order)
+  bs.sys_item_range.assign(2 * (size_t)g->n_sys, 0);
+  std::vector<int64_t> first(g->n_sys, -1), last(g->n_sys, -1);
+  for (int64_t i = 0; i < (int64_t)bs.items.size(); ++i) {
+    const int s = bs.batches[bs.items[i].batch].sys;
+    if (first[s] < 0) first[s] = i;
+    last[s] = i + 1;
+  }
+  for (int s = 0; s < g->n_sys; ++s) {
+    bs.sys_item_range[2 * s] = first[s] < 0 ? 0 : first[s];
+    bs.sys_item_range[2 * s + 1] = first[s] < 0 ? 0 : last[s];
+  }
+
+  // upload
+  bs.dv = g->common;
+  bs.dv.batches = g->upload(bs.batches);
+  bs.dv.batch_atoms = g->upload(bs.batch_atoms);
+  bs.dv.batch_acol = g->upload(bs.batch_acol);
+  bs.dv.batch_cols = g->upload(bs.batch_cols);
+  bs.dv.sys_item_range = g->upload(bs.sys_item_range);
+  bs.d_items = g->upload(bs.items);
+  if (bs.slab_elems > g->slab_cap) {
+    if (g->d_slab1) g->release(g->d_slab1);
+    if (g->d_slab2) g->release(g->d_slab2);
+    g->d_slab1 = g->d_slab2 = nullptr;
+    g->slab_cap = 0;
+    g->d_slab1 = g->alloc(bs.slab_elems * sizeof(double));
+    g->d_slab2 = g->alloc(bs.slab_elems * sizeof(double));
+    g->slab_cap = bs.slab_elems;
+  }
+}
+
+BatchSet& hset(aims_grid* g, int merge) {
+  for (auto& p : g->hsets)
+    if (p->merge == merge) return *p;
+  std::unique_ptr<BatchSet> bs(new BatchSet());
+  build_set(g, *bs, merge, false);
+  g->hsets.push_back(std::move(bs));
+  return *g->hsets.back();
+}
+
 aims_grid* build(const aims_system* sys, int n_sys, int device, void* stream) {
   if (n_sys < 1) fail(AIMS_ERR_ARG, "n_sys must be >= 1");
   if (!sys) fail(AIMS_ERR_ARG, "null system array");
@@ -285,14 +462,18 @@ aims_grid* build(const aims_system* sys, int n_sys, int device, void* stream) {
   g->rg.inv_h = 1.0 / g->rg.h;
   g->rg.rc = sys[0].rc;
   g->rg.n_log = n_log;
-  const double reach = sys[0].rc + g->margin;
+  if (const char* e = getenv("AIMS_H_MERGE")) {
+    const int m = std::max(0, std::min(4, atoi(e)));
+    for (int p = 0; p < 3; ++p) g->h_merge[p] = m;
+  }
 
   // ---- species, splines, atoms ----------------------------------------------------------
   std::vector<SpeciesDesc> species;
   std::vector<int32_t> shell_l;
   std::vector<double> spline64;
-  std::vector<int32_t> atom_species, atom_sys, species_nfn_all;
-  std::vector<std::vector<int>> atom_nfn(n_sys);
+  std::vector<int32_t> atom_species, atom_sys;
+  g->atom_nfn.resize(n_sys);
+  g->atom_col0.resize(n_sys);
   for (int k = 0; k < n_sys; ++k) {
     const aims_system& s = sys[k];
     const int sp_base = (int)species.size();
@@ -325,7 +506,6 @@ aims_grid* build(const aims_system* sys, int n_sys, int device, void* stream) {
           }
       }
       species.push_back(sd);
-      species_nfn_all.push_back(nfn);
       sh_off += sd.nshell;
     }
     SystemDesc sdsc{};
@@ -336,7 +516,8 @@ aims_grid* build(const aims_system* sys, int n_sys, int device, void* stream) {
       const int gs = sp_base + s.atom_species[a];
       atom_species.push_back(gs);
       atom_sys.push_back(k);
-      atom_nfn[k].push_back(species[gs].nfn);
+      g->atom_col0[k].push_back(nb);
+      g->atom_nfn[k].push_back(species[gs].nfn);
       nb += species[gs].nfn;
       for (int c = 0; c < 3; ++c) g->atom_xyz0.push_back(s.atom_xyz[3 * a + c]);
     }
@@ -345,15 +526,14 @@ aims_grid* build(const aims_system* sys, int n_sys, int device, void* stream) {
     g->sys_atom_range.push_back(g->n_atoms);
     g->n_atoms += s.n_atoms;
     g->sys_atom_range.push_back(g->n_atoms);
+    g->sys_max_batch.push_back(s.max_batch);
     g->nb_total += nb;
     g->mat_total += (int64_t)nb * nb;
   }
   std::vector<float> spline32(spline64.begin(), spline64.end());
 
-  // ---- points: batching and screening --------------------------------------------------
-  std::vector<double4> pts_sorted;
+  // ---- points: batch order from the recursive bisection -----------------------------------
   std::vector<int32_t> perm;
-  std::vector<int32_t> batch_atoms, batch_acol, batch_cols;
   int64_t caller_base = 0;
   for (int k = 0; k < n_sys; ++k) {
     const aims_system& s = sys[k];
@@ -361,135 +541,23 @@ aims_grid* build(const aims_system* sys, int n_sys, int device, void* stream) {
     for (int64_t i = 0; i < s.n_points; ++i) idx[i] = (int32_t)i;
     std::vector<std::pair<int64_t, int64_t>> segs;
     bisect(s.pt_xyz, idx, 0, s.n_points, s.max_batch, segs);
-    const int64_t sorted_base = (int64_t)pts_sorted.size();
-    g->sys_pt_range.push_back(sorted_base);
+    g->sys_pt_range.push_back((int64_t)g->pts_sorted.size());
     for (int64_t i = 0; i < s.n_points; ++i) {
       const int32_t q = idx[i];
-      pts_sorted.push_back(make_double4(s.pt_xyz[3 * q], s.pt_xyz[3 * q + 1], s.pt_xyz[3 * q + 2], s.pt_w[q]));
+      g->pts_sorted.push_back(make_double4(s.pt_xyz[3 * q], s.pt_xyz[3 * q + 1], s.pt_xyz[3 * q + 2], s.pt_w[q]));
       perm.push_back((int32_t)(caller_base + q));
     }
-    g->sys_pt_range.push_back((int64_t)pts_sorted.size());
-    // per-batch relevant atoms (parallel), then concatenate in batch order
-    const int nseg = (int)segs.size();
-    std::vector<std::vector<int32_t>> rel(nseg);
-    std::vector<int> atom_col0(s.n_atoms + 1, 0);
-    for (int a = 0; a < s.n_atoms; ++a) atom_col0[a + 1] = atom_col0[a] + atom_nfn[k][a];
-    parallel_for(nseg, [&](int64_t b) {
-      const int64_t lo = segs[b].first, hi = segs[b].second;
-      double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
-      for (int64_t i = lo; i < hi; ++i)
-        for (int c = 0; c < 3; ++c) {
-          mn[c] = std::min(mn[c], s.pt_xyz[3 * (int64_t)idx[i] + c]);
-          mx[c] = std::max(mx[c], s.pt_xyz[3 * (int64_t)idx[i] + c]);
-        }
-      double cen[3], rad2 = 0;
-      for (int c = 0; c < 3; ++c) {
-        cen[c] = 0.5 * (mn[c] + mx[c]);
-        rad2 += 0.25 * (mx[c] - mn[c]) * (mx[c] - mn[c]);
-      }
-      const double rad = std::sqrt(rad2);
-      for (int a = 0; a < s.n_atoms; ++a) {
-        const double* A = s.atom_xyz + 3 * a;
-        const double dc = std::sqrt((A[0] - cen[0]) * (A[0] - cen[0]) + (A[1] - cen[1]) * (A[1] - cen[1]) +
-                                    (A[2] - cen[2]) * (A[2] - cen[2]));
-        if (dc - rad >= reach) continue;
-        bool hit = false;
-        for (int64_t i = lo; i < hi && !hit; ++i) {
-          const double* p = s.pt_xyz + 3 * (int64_t)idx[i];
-          const double d2 = (p[0] - A[0]) * (p[0] - A[0]) + (p[1] - A[1]) * (p[1] - A[1]) +
-                            (p[2] - A[2]) * (p[2] - A[2]);
-          hit = d2 < reach * reach;
-        }
-        if (hit) rel[b].push_back(a);
-      }
-    });
-    for (int b = 0; b < nseg; ++b) {
-      BatchDesc d{};
-      d.pt_off = (int32_t)(sorted_base + segs[b].first);
-      d.n_p = (int32_t)(segs[b].second - segs[b].first);
-      d.atom_off = (int32_t)batch_atoms.size();
-      d.n_atoms = (int32_t)rel[b].size();
-      d.col_off = (int32_t)batch_cols.size();
-      d.sys = k;
-      d.ldp = round_up(d.n_p, kPad);
-      int col = 0;
-      for (int a : rel[b]) {
-        batch_atoms.push_back(g->systems[k].atom_off + a);
-        batch_acol.push_back(col);
-        for (int f = 0; f < atom_nfn[k][a]; ++f) batch_cols.push_back(atom_col0[a] + f);
-        col += atom_nfn[k][a];
-      }
-      d.n_b = col;
-      g->batches.push_back(d);
-      g->sum_np_nb2 += (double)d.n_p * d.n_b * d.n_b;
-      g->sum_nb2 += (double)d.n_b * d.n_b;
-    }
+    g->sys_pt_range.push_back((int64_t)g->pts_sorted.size());
     caller_base += s.n_points;
   }
-  g->n_points = (int64_t)pts_sorted.size();
-  if ((int64_t)batch_cols.size() > (int64_t)INT32_MAX) fail(AIMS_ERR_UNSUPPORTED, "too many batch columns");
+  g->n_points = (int64_t)g->pts_sorted.size();
 
-  // ---- groups of batches sharing the scratch, and the tile work lists -------------------
-  const size_t budget = scratch_budget_elems();
-  std::vector<TileItem> ditems, hitems;
-  {
-    aims_grid::Group cur{0, 0, 0, 0, 0, 0, 0.0};
-    size_t used = 0;
-    const int nB = (int)g->batches.size();
-    for (int b = 0; b < nB; ++b) {
-      BatchDesc& d = g->batches[b];
-      const size_t need = (size_t)d.n_b * d.ldp;
-      if (used > 0 && used + need > budget) {
-        cur.b1 = b;
-        cur.d1 = (int64_t)ditems.size();
-        cur.h1 = (int64_t)hitems.size();
-        g->groups.push_back(cur);
-        cur = aims_grid::Group{b, b, (int64_t)ditems.size(), 0, (int64_t)hitems.size(), 0, 0.0};
-        used = 0;
-      }
-      cur.flops += 2.0 * d.n_p * (double)d.n_b * d.n_b;
-      d.slab_off = (int64_t)used;
-      used += need;
-      g->slab_elems = std::max(g->slab_elems, used);
-      const int tb = (d.n_b + kTile - 1) / kTile, tp = (d.n_p + kTile - 1) / kTile;
-      for (int ti = 0; ti < tb; ++ti) {
-        for (int tj = 0; tj < tp; ++tj) ditems.push_back(TileItem{b, (int16_t)ti, (int16_t)tj});
-        for (int tj = 0; tj < tb; ++tj) hitems.push_back(TileItem{b, (int16_t)ti, (int16_t)tj});
-      }
-    }
-    cur.b1 = nB;
-    cur.d1 = (int64_t)ditems.size();
-    cur.h1 = (int64_t)hitems.size();
-    if (cur.b1 > cur.b0) g->groups.push_back(cur);
-  }
-  g->n_ditems = (int64_t)ditems.size();
-  g->n_hitems = (int64_t)hitems.size();
-  if (g->n_ditems > INT32_MAX || g->n_hitems > INT32_MAX) fail(AIMS_ERR_UNSUPPORTED, "too many tiles");
-  // density-item range of each system (items are in batch order, batches in system order)
-  g->sys_item_range.assign(2 * (size_t)n_sys, 0);
-  {
-    std::vector<int64_t> first(n_sys, -1), last(n_sys, -1);
-    for (int64_t i = 0; i < g->n_ditems; ++i) {
-      const int s = g->batches[ditems[i].batch].sys;
-      if (first[s] < 0) first[s] = i;
-      last[s] = i + 1;
-    }
-    for (int s = 0; s < n_sys; ++s) {
-      g->sys_item_range[2 * s] = first[s] < 0 ? 0 : first[s];
-      g->sys_item_range[2 * s + 1] = first[s] < 0 ? 0 : last[s];
-    }
-  }
-
-  // ---- upload ---------------------------------------------------------------------------
+  // ---- upload of the shared state, then the density partition ---------------------------
   hipchk(hipSetDevice(device), "hipSetDevice");
-  DeviceView& dv = g->dv;
-  dv.batches = g->upload(g->batches);
+  DeviceView& dv = g->common;
   dv.systems = g->upload(g->systems);
-  dv.pts = g->upload(pts_sorted);
+  dv.pts = g->upload(g->pts_sorted);
   dv.perm = g->upload(perm);
-  dv.batch_atoms = g->upload(batch_atoms);
-  dv.batch_acol = g->upload(batch_acol);
-  dv.batch_cols = g->upload(batch_cols);
   g->d_atom_xyz = g->upload(g->atom_xyz0);
   dv.atom_xyz = g->d_atom_xyz;
   dv.atom_species = g->upload(atom_species);
@@ -499,17 +567,15 @@ aims_grid* build(const aims_system* sys, int n_sys, int device, void* stream) {
   dv.spline64 = g->upload(spline64);
   dv.spline32 = g->upload(spline32);
   dv.sys_pt_range = g->upload(g->sys_pt_range);
-  dv.sys_item_range = g->upload(g->sys_item_range);
   dv.rg = g->rg;
   dv.n_sys = n_sys;
-  g->d_ditems = g->upload(ditems);
-  g->d_hitems = g->upload(hitems);
+  build_set(g.get(), g->dens, 0, true);
   g->d_n_sorted = (double*)g->alloc(std::max<int64_t>(1, g->n_points) * sizeof(double));
   g->d_part = (double*)g->alloc((size_t)n_sys * g->nblk_finish * 2 * sizeof(double));
-  g->d_et_part = (double*)g->alloc(std::max<int64_t>(1, g->n_ditems) * sizeof(double));
+  g->d_et_part = (double*)g->alloc(std::max<size_t>(1, g->dens.items.size()) * sizeof(double));
   g->d_P32 = (float*)g->alloc(std::max<int64_t>(1, g->mat_total) * sizeof(float));
-  g->d_slab1 = g->alloc(std::max<size_t>(1, g->slab_elems) * sizeof(double));
-  g->d_slab2 = g->alloc(std::max<size_t>(1, g->slab_elems) * sizeof(double));
+  // the H partitions of the default merge levels
+  for (int p = 0; p < 3; ++p) hset(g.get(), g->h_merge[p]);
   return g.release();
 }
 
@@ -525,7 +591,6 @@ void require_device(const void* p, const char* name, bool nonempty = true) {
 void check_prec(aims_precision p) {
   if (p != AIMS_FP64 && p != AIMS_FP32 && p != AIMS_BF16X3)
     fail(AIMS_ERR_ARG, "unknown precision %d", (int)p);
-  if (p == AIMS_BF16X3) fail(AIMS_ERR_UNSUPPORTED, "BF16x3 precision is not available in this build");
 }
 
 // Positions for this call: NULL = setup positions.  A given array (host or device) is read
@@ -597,41 +662,83 @@ void prof_collect(aims_grid* g) {
   g->prof_pending.clear();
 }
 
+// Density update with basis values of precision T (double / float) on the MFMA type of T,
+// or, with bf16x3, FP32 basis values split into bf16 hi/lo pairs.
 template <typename T>
-void run_density(aims_grid* g, const T* P, const double* v, double* n_out, double* sums_out) {
+void run_density(aims_grid* g, aims_precision prec, const T* P, const double* v, double* n_out,
+                 double* sums_out) {
   hipStream_t st = g->stream;
-  T* s1 = (T*)g->d_slab1;
-  T* s2 = (T*)g->d_slab2;
+  const BatchSet& bs = g->dens;
   hipchk(launch_fill(g->d_n_sorted, (size_t)g->n_points, 0.0, st), "fill n");
-  for (const auto& gr : g->groups) {
-    timed(g, kProfPhi, 0.0, "phi_eval", [&] {
-      return launch_phi_eval<T>(g->dv, gr.b0, gr.b1 - gr.b0, kModeDensity, nullptr, s1, s2, st);
-    });
-    timed(g, kProfDensity, gr.flops, "density", [&] {
-      return launch_density<T>(g->dv, g->d_ditems + gr.d0, (int)(gr.d1 - gr.d0), P, s1, s2,
-                               g->d_n_sorted, g->d_et_part + gr.d0, st);
-    });
+  for (const auto& gr : bs.groups) {
+    const int nbt = gr.b1 - gr.b0, nit = (int)(gr.i1 - gr.i0);
+    if (prec == AIMS_BF16X3) {
+      timed(g, kProfPhi, 0.0, "phi_eval", [&] {
+        return launch_phi_eval_bf16(bs.dv, gr.b0, nbt, kModeDensity, true, nullptr, g->d_slab1, g->d_slab2, st);
+      });
+      timed(g, kProfDensity, gr.flops, "density", [&] {
+        return launch_density_bf16(bs.dv, bs.d_items + gr.i0, nit, (const float*)P, g->d_slab1,
+                                   g->d_slab2, g->d_n_sorted, g->d_et_part + gr.i0, st);
+      });
+    } else {
+      T* s1 = (T*)g->d_slab1;
+      T* s2 = (T*)g->d_slab2;
+      timed(g, kProfPhi, 0.0, "phi_eval", [&] {
+        return launch_phi_eval<T>(bs.dv, gr.b0, nbt, kModeDensity, nullptr, s1, s2, st);
+      });
+      timed(g, kProfDensity, gr.flops, "density", [&] {
+        return launch_density<T>(bs.dv, bs.d_items + gr.i0, nit, P, s1, s2, g->d_n_sorted,
+                                 g->d_et_part + gr.i0, st);
+      });
+    }
   }
   timed(g, kProfFinish, 0.0, "density_finish", [&] {
-    return launch_density_finish(g->dv, g->d_n_sorted, v, n_out, g->d_part, g->nblk_finish,
+    return launch_density_finish(bs.dv, g->d_n_sorted, v, n_out, g->d_part, g->nblk_finish,
                                  g->d_et_part, sums_out, st);
   });
 }
 
 template <typename T>
-void run_hs(aims_grid* g, int mode, const double* v, double* out) {
+void run_hs(aims_grid* g, aims_precision prec, int mode, const double* v, double* out) {
   hipStream_t st = g->stream;
-  T* s1 = (T*)g->d_slab1;
-  T* s2 = (T*)g->d_slab2;
+  const BatchSet& bs = hset(g, g->h_merge[prec]);
   hipchk(launch_fill(out, (size_t)g->mat_total, 0.0, st), "fill H");
-  for (const auto& gr : g->groups) {
-    timed(g, kProfPhi, 0.0, "phi_eval", [&] {
-      return launch_phi_eval<T>(g->dv, gr.b0, gr.b1 - gr.b0, mode, v, s1, s2, st);
-    });
-    timed(g, kProfHS, gr.flops, "hs", [&] {
-      return launch_hs<T>(g->dv, g->d_hitems + gr.h0, (int)(gr.h1 - gr.h0), s1, s2, out, st);
-    });
+  for (const auto& gr : bs.groups) {
+    const int nbt = gr.b1 - gr.b0, nit = (int)(gr.i1 - gr.i0);
+    if (prec == AIMS_BF16X3) {
+      timed(g, kProfPhi, 0.0, "phi_eval", [&] {
+        return launch_phi_eval_bf16(bs.dv, gr.b0, nbt, mode, false, v, g->d_slab1, g->d_slab2, st);
+      });
+      timed(g, kProfHS, gr.flops, "hs", [&] {
+        return launch_hs_bf16(bs.dv, bs.d_items + gr.i0, nit, g->d_slab1, g->d_slab2, out, st);
+      });
+    } else {
+      T* s1 = (T*)g->d_slab1;
+      T* s2 = (T*)g->d_slab2;
+      timed(g, kProfPhi, 0.0, "phi_eval", [&] {
+        return launch_phi_eval<T>(bs.dv, gr.b0, nbt, mode, v, s1, s2, st);
+      });
+      timed(g, kProfHS, gr.flops, "hs", [&] {
+        return launch_hs<T>(bs.dv, bs.d_items + gr.i0, nit, s1, s2, out, st);
+      });
+    }
   }
+}
+
+// One precision-dispatched density update (P converted to FP32 for the mixed forms).
+void density_call(aims_grid* g, aims_precision prec, const double* P, const double* v, double* n_out,
+                  double* sums_out) {
+  if (prec == AIMS_FP64) {
+    run_density<double>(g, prec, P, v, n_out, sums_out);
+  } else {
+    hipchk(launch_convert_f32(P, g->d_P32, (size_t)g->mat_total, g->stream), "convert P");
+    run_density<float>(g, prec, g->d_P32, v, n_out, sums_out);
+  }
+}
+
+void hs_call(aims_grid* g, aims_precision prec, int mode, const double* v, double* out) {
+  if (prec == AIMS_FP64) run_hs<double>(g, prec, mode, v, out);
+  else run_hs<float>(g, prec, mode, v, out);
 }
 
 template <typename F>
@@ -688,12 +795,7 @@ aims_status aims_update_density(aims_grid* g, aims_precision prec, const double*
     require_device(sums_out, "sums_out");
     if (v_or_null) require_device(v_or_null, "v", g->n_points > 0);
     set_positions(g, atom_xyz);
-    if (prec == AIMS_FP64) {
-      run_density<double>(g, P, v_or_null, n_out, sums_out);
-    } else {
-      hipchk(launch_convert_f32(P, g->d_P32, (size_t)g->mat_total, g->stream), "convert P");
-      run_density<float>(g, g->d_P32, v_or_null, n_out, sums_out);
-    }
+    density_call(g, prec, P, v_or_null, n_out, sums_out);
   });
 }
 
@@ -705,13 +807,8 @@ aims_status aims_integrate_h(aims_grid* g, aims_precision prec, const double* at
     require_device(H, "H");
     if (S_or_null) require_device(S_or_null, "S");
     set_positions(g, atom_xyz);
-    if (prec == AIMS_FP64) {
-      run_hs<double>(g, kModeH, v, H);
-      if (S_or_null) run_hs<double>(g, kModeS, v, S_or_null);
-    } else {
-      run_hs<float>(g, kModeH, v, H);
-      if (S_or_null) run_hs<float>(g, kModeS, v, S_or_null);
-    }
+    hs_call(g, prec, kModeH, v, H);
+    if (S_or_null) hs_call(g, prec, kModeS, v, S_or_null);
   });
 }
 
@@ -750,14 +847,8 @@ aims_status aims_step_graph_create(aims_grid* g, aims_precision prec, const doub
     sg->stream = g->stream;
     hipchk(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal), "begin capture");
     try {
-      if (prec == AIMS_FP64) {
-        run_density<double>(g, P, v, n_out, sums_out);
-        run_hs<double>(g, kModeH, v, H);
-      } else {
-        hipchk(launch_convert_f32(P, g->d_P32, (size_t)g->mat_total, g->stream), "convert P");
-        run_density<float>(g, g->d_P32, v, n_out, sums_out);
-        run_hs<float>(g, kModeH, v, H);
-      }
+      density_call(g, prec, P, v, n_out, sums_out);
+      hs_call(g, prec, kModeH, v, H);
     } catch (...) {
       hipGraph_t junk = nullptr;
       (void)hipStreamEndCapture(g->stream, &junk);
@@ -814,6 +905,7 @@ int32_t aims_n_variants(aims_precision prec) { return (prec >= AIMS_FP64 && prec
 aims_status aims_get_tuning(const aims_grid* g, aims_precision prec, aims_tuning* out) {
   if (!g || !out || aims_n_variants(prec) == 0) return AIMS_ERR_ARG;
   memset(out, 0, sizeof(*out));
+  out->h_merge = g->h_merge[prec];
   out->n_buckets = 1;
   out->nb_edges[0] = INT32_MAX;
   out->variant[0] = 0;
@@ -821,18 +913,24 @@ aims_status aims_get_tuning(const aims_grid* g, aims_precision prec, aims_tuning
 }
 
 aims_status aims_set_tuning(aims_grid* g, aims_precision prec, const aims_tuning* t) {
-  if (!g || !t || aims_n_variants(prec) == 0) return AIMS_ERR_ARG;
-  if (t->n_buckets < 1 || t->n_buckets > 16) return AIMS_ERR_ARG;
-  for (int k = 0; k < t->n_buckets; ++k)
-    if (t->variant[k] < 0 || t->variant[k] >= aims_n_variants(prec)) return AIMS_ERR_ARG;
-  return AIMS_OK;
+  return guarded(g, [&] {
+    if (!t || aims_n_variants(prec) == 0) fail(AIMS_ERR_ARG, "bad tuning arguments");
+    if (t->h_merge < 0 || t->h_merge > 4) fail(AIMS_ERR_ARG, "h_merge must be in 0..4");
+    if (t->n_buckets < 1 || t->n_buckets > 8) fail(AIMS_ERR_ARG, "n_buckets must be in 1..8");
+    for (int k = 0; k < t->n_buckets; ++k) {
+      if (t->variant[k] < 0 || t->variant[k] >= aims_n_variants(prec)) fail(AIMS_ERR_ARG, "bad variant");
+      if (k > 0 && t->nb_edges[k] < t->nb_edges[k - 1]) fail(AIMS_ERR_ARG, "nb_edges must ascend");
+    }
+    hset(g, t->h_merge);
+    g->h_merge[prec] = t->h_merge;
+  });
 }
 
 aims_status aims_work_stats(const aims_grid* g, int64_t* n_batches, double* sum_np_nb2, double* sum_nb2) {
   if (!g) return AIMS_ERR_ARG;
-  if (n_batches) *n_batches = (int64_t)g->batches.size();
-  if (sum_np_nb2) *sum_np_nb2 = g->sum_np_nb2;
-  if (sum_nb2) *sum_nb2 = g->sum_nb2;
+  if (n_batches) *n_batches = (int64_t)g->dens.batches.size();
+  if (sum_np_nb2) *sum_np_nb2 = g->dens.sum_np_nb2;
+  if (sum_nb2) *sum_nb2 = g->dens.sum_nb2;
   return AIMS_OK;
 }
 

@@ -44,6 +44,13 @@ hipError_t launch_density(const DeviceView& dv, const TileItem* items, int n_ite
 template <typename T>
 hipError_t launch_hs(const DeviceView& dv, const TileItem* items, int n_items, const T* slab1,
                      const T* slab2, double* out, hipStream_t st);
+hipError_t launch_phi_eval_bf16(const DeviceView& dv, int b0, int nbatch, int mode, bool point_major,
+                                const double* v, void* slab1, void* slab2, hipStream_t st);
+hipError_t launch_density_bf16(const DeviceView& dv, const TileItem* items, int n_items, const float* P,
+                               const void* slab1, const void* slab2, double* n_sorted, double* et_part,
+                               hipStream_t st);
+hipError_t launch_hs_bf16(const DeviceView& dv, const TileItem* items, int n_items, const void* slab1,
+                          const void* slab2, double* out, hipStream_t st);
 hipError_t launch_density_finish(const DeviceView& dv, const double* n_sorted, const double* v,
                                  double* n_out, double* part, int nblk, const double* et_part,
                                  double* sums_out, hipStream_t st);

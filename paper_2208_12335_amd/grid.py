@@ -149,10 +149,13 @@ class AimsGrid:
     def get_tuning(self, prec="fp64"):
         t = AimsTuning()
         self._check(self._L.aims_get_tuning(self._h, PRECISION[prec], byref(t)))
-        return {"nb_edges": list(t.nb_edges[:t.n_buckets]), "variant": list(t.variant[:t.n_buckets])}
+        return {"h_merge": t.h_merge, "nb_edges": list(t.nb_edges[:t.n_buckets]),
+                "variant": list(t.variant[:t.n_buckets])}
 
-    def set_tuning(self, nb_edges: Sequence[int], variant: Sequence[int], prec="fp64"):
+    def set_tuning(self, h_merge: int, nb_edges: Sequence[int] = (2 ** 31 - 1,),
+                   variant: Sequence[int] = (0,), prec="fp64"):
         t = AimsTuning()
+        t.h_merge = int(h_merge)
         t.n_buckets = len(nb_edges)
         for k, (e, v) in enumerate(zip(nb_edges, variant)):
             t.nb_edges[k] = int(e)

@@ -115,3 +115,19 @@ def test_empty_grid(gpu, c1):
     H, S = g.integrate_h(v, want_S=True)
     assert n.numel() == 0 and torch.count_nonzero(sums).item() == 0
     assert torch.count_nonzero(H).item() == 0 and torch.count_nonzero(S).item() == 0
+
+
+@pytest.mark.parametrize("merge", [0, 1, 2, 3])
+def test_h_merge_levels_same_result(gpu, merge):
+    # coarser H batches (the bisection stopped earlier) change only the rounding order
+    inst = synth.make_instance("c2", n_atoms=10, box=7.0, seed=1)
+    g = AimsGrid(inst, device=gpu.index)
+    g.set_tuning(merge, prec="fp64")
+    assert g.get_tuning("fp64")["h_merge"] == merge
+    v = torch.from_numpy(inst.v).to(gpu)
+    H, S = g.integrate_h(v, want_S=True)
+    torch.cuda.synchronize()
+    nb = inst.n_basis
+    Hr, Sr = GridOracle(inst).integrate_h(inst.v)
+    assert relerr(H.cpu().numpy().reshape(nb, nb), Hr) < TOL
+    assert relerr(S.cpu().numpy().reshape(nb, nb), Sr) < TOL

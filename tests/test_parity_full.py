@@ -1,0 +1,76 @@
+"""Library against the oracle at the full size of the 64-atom cluster workload (the benchmark's
+configuration), on outputs the oracle can compute one by one: n at sampled points, H and S
+blocks of sampled atom pairs.  Properties that hold at any size are checked on everything."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import GridOracle
+from paper_2208_12335_amd import AimsGrid
+from conftest import relerr
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def c2_run(gpu):
+    inst = synth.make_instance("c2", seed=0)
+    print(f"[full] c2: {inst.n_points} points, {inst.n_basis} functions", flush=True)
+    g = AimsGrid(inst, device=gpu.index)
+    P = torch.from_numpy(inst.P).to(gpu).reshape(-1)
+    v = torch.from_numpy(inst.v).to(gpu)
+    n, sums = g.update_density(P, v)
+    H, S = g.integrate_h(v, want_S=True)
+    torch.cuda.synchronize()
+    nb = inst.n_basis
+    out = {"n": n.cpu().numpy(), "sums": sums.cpu().numpy()[0],
+           "H": H.cpu().numpy().reshape(nb, nb), "S": S.cpu().numpy().reshape(nb, nb)}
+    return inst, g, out
+
+
+def _pair_block(o, inst, a, b, v):
+    """H and S block of atoms (a, b) by the oracle, over the points within rc of both."""
+    d = np.linalg.norm(inst.pt_xyz[:, None, :] - inst.atom_xyz[None, [a, b], :], axis=-1)
+    idx = np.nonzero((d[:, 0] < inst.rc) & (d[:, 1] < inst.rc))[0]
+    Pa, Ta, ca = o.basis_values(inst.pt_xyz[idx], atoms=np.array([a]))
+    Pb, Tb, cb = o.basis_values(inst.pt_xyz[idx], atoms=np.array([b]))
+    w = inst.pt_w[idx][:, None]
+    H = Pa.T @ (w * (v[idx][:, None] * Pb + Tb))
+    S = Pa.T @ (w * Pb)
+    return ca, cb, H, S
+
+
+def test_c2_density_sampled_points(c2_run):
+    inst, g, out = c2_run
+    o = GridOracle(inst)
+    rng = np.random.default_rng(11)
+    idx = np.sort(rng.choice(inst.n_points, 3000, replace=False))
+    d = o.density(inst.P, inst.v, points=idx)
+    e = relerr(out["n"][idx], d["n"])
+    print(f"[full] n on 3000 sampled points: {e:.2e}", flush=True)
+    assert e < 1e-10
+
+
+def test_c2_h_and_s_sampled_blocks(c2_run):
+    inst, g, out = c2_run
+    o = GridOracle(inst)
+    rng = np.random.default_rng(12)
+    worst_H = worst_S = 0.0
+    pairs = [(int(a), int(b)) for a, b in rng.integers(0, inst.n_atoms, size=(6, 2))] + [(3, 3)]
+    for a, b in pairs:
+        ca, cb, Hr, Sr = _pair_block(o, inst, a, b, inst.v)
+        worst_H = max(worst_H, relerr(out["H"][np.ix_(ca, cb)], Hr) if np.abs(Hr).max() > 0 else 0)
+        worst_S = max(worst_S, relerr(out["S"][np.ix_(ca, cb)], Sr) if np.abs(Sr).max() > 0 else 0)
+    print(f"[full] sampled H blocks {worst_H:.2e}, S blocks {worst_S:.2e}", flush=True)
+    assert worst_H < 1e-10 and worst_S < 1e-10
+
+
+def test_c2_whole_output_properties(c2_run):
+    inst, g, out = c2_run
+    N, EV, ET = out["sums"]
+    assert abs(N - np.sum(inst.P * out["S"])) < 1e-11 * abs(N)
+    assert abs(EV + ET - np.sum(inst.P * out["H"])) < 1e-10 * abs(EV + ET)
+    S = out["S"]
+    assert np.max(np.abs(S - S.T)) < 1e-13 * np.max(np.abs(S))
+    assert np.all(np.isfinite(out["n"])) and np.all(np.isfinite(out["H"]))
