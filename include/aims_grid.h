@@ -141,19 +141,18 @@ aims_status aims_step_graph_launch(aims_step_graph *graph);
 void aims_step_graph_destroy(aims_step_graph *graph);
 
 /* Tunable execution parameters of one precision (chosen by the project's autotuner, which
- * times the candidates on the live device; see paper_2208_12335_amd.autotune).
- *   h_merge  the H/S pass uses batches of up to max_batch << h_merge points (the same bisection
- *            stopped h_merge levels earlier): fewer FP64 scatter-adds into H for slightly more
- *            flops.  0..4.  Changing it builds that partition once (device allocation).
- *   variant  MFMA kernel variant per basis-size bucket: batches with nb <= nb_edges[k] (the
- *            first such k) use variant[k]; 0 <= variant < aims_n_variants(). */
+ * times candidates on the live device; see paper_2208_12335_amd.autotune).
+ *   h_merge          the H/S pass uses batches of up to max_batch << h_merge points (the same
+ *                    bisection stopped h_merge levels earlier): fewer FP64 scatter-adds into H
+ *                    for slightly more flops.  0..4.
+ *   density_pblocks  a density work tile covers 64 basis rows and up to 32 * density_pblocks
+ *                    points of one batch (2..5); a batch of n_p points is cut into
+ *                    ceil(n_p / (32 density_pblocks)) equal tiles.
+ * Setting a value builds its work lists once (device allocation), later calls reuse them. */
 typedef struct {
   int32_t h_merge;
-  int32_t n_buckets;            /* 1..8                                                     */
-  int32_t nb_edges[8];          /* ascending; the last bucket takes every larger batch      */
-  int32_t variant[8];
+  int32_t density_pblocks;
 } aims_tuning;
-int32_t aims_n_variants(aims_precision prec);
 aims_status aims_get_tuning(const aims_grid *g, aims_precision prec, aims_tuning *out);
 aims_status aims_set_tuning(aims_grid *g, aims_precision prec, const aims_tuning *t);
 

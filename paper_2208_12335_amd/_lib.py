@@ -37,8 +37,7 @@ class AimsSystem(ctypes.Structure):
 
 
 class AimsTuning(ctypes.Structure):
-    _fields_ = [("h_merge", c_int32), ("n_buckets", c_int32), ("nb_edges", c_int32 * 8),
-                ("variant", c_int32 * 8)]
+    _fields_ = [("h_merge", c_int32), ("density_pblocks", c_int32)]
 
 
 # every symbol the header declares, with its signature
@@ -53,7 +52,6 @@ SIGNATURES = {
                                        c_void_p, POINTER(c_void_p)]),
     "aims_step_graph_launch": (c_int, [c_void_p]),
     "aims_step_graph_destroy": (None, [c_void_p]),
-    "aims_n_variants": (c_int32, [c_int]),
     "aims_get_tuning": (c_int, [c_void_p, c_int, POINTER(AimsTuning)]),
     "aims_set_tuning": (c_int, [c_void_p, c_int, POINTER(AimsTuning)]),
     "aims_work_stats": (c_int, [c_void_p, POINTER(c_int64), POINTER(c_double), POINTER(c_double)]),

@@ -28,6 +28,8 @@ def build(verbose: bool = False) -> str:
     flags = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              # packed FP32 instructions are kept out of every kernel
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             # MFMA accumulators stay in VGPRs (no AGPR round trips across branches)
+             "-mllvm", "-amdgpu-mfma-vgpr-form",
              "-I", os.path.join(ROOT, "include"), "-I", CSRC]
     objs = []
     bdir = os.path.join(HERE, "_build")

@@ -140,24 +140,33 @@ bool is_device_ptr(const void* p) {
 // the partition at max_batch; the H/S pass may use a coarser one (max_batch << merge, i.e. the
 // bisection stopped `merge` levels earlier), which trades a few more flops for fewer FP64
 // scatter-adds into H.
+struct ItemList {
+  int pblocks = 0;                 // density: a tile spans up to 32 * pblocks points; 0 = H tiles
+  std::vector<TileItem> items;
+  struct Run {
+    int nbn;                       // point blocks of the kernel variant (density), 0 for H
+    int64_t i0, i1;
+  };
+  std::vector<std::vector<Run>> runs;  // per group of batches
+  TileItem* d_items = nullptr;
+};
+
 struct BatchSet {
   int merge = 0;
-  bool density = false;            // tile list for the density kernel (else for the H kernel)
+  bool density = false;            // tile lists for the density kernel (else for the H kernel)
   std::vector<BatchDesc> batches;
   std::vector<int32_t> batch_atoms, batch_acol, batch_cols;
   struct Group {
     int b0, b1;                    // batches
-    int64_t i0, i1;                // tile items
     double flops;                  // sum over the group's batches of 2 n_p n_b^2
   };
   std::vector<Group> groups;
-  std::vector<TileItem> items;
-  std::vector<int64_t> sys_item_range;
+  std::vector<int64_t> sys_batch_range;
   size_t slab_elems = 0;
   double sum_np_nb2 = 0, sum_nb2 = 0;
+  std::vector<std::unique_ptr<ItemList>> lists;
   // device copies
   DeviceView dv{};
-  TileItem* d_items = nullptr;
 };
 
 struct aims_grid {
@@ -185,6 +194,7 @@ struct aims_grid {
   BatchSet dens;                              // density partition (merge 0)
   std::vector<std::unique_ptr<BatchSet>> hsets;  // H partitions by merge level (built on demand)
   int h_merge[3] = {1, 2, 2};                 // per precision
+  int d_pblocks[3] = {2, 5, 5};               // per precision: density point-tile cap
   int nblk_finish = 64;
 
   // profiling
@@ -204,7 +214,7 @@ struct aims_grid {
   double* d_atom_xyz = nullptr;
   double* d_n_sorted = nullptr;
   double* d_part = nullptr;
-  double* d_et_part = nullptr;
+  double* d_et_batch = nullptr;
   float* d_P32 = nullptr;
   void* d_slab1 = nullptr;
   void* d_slab2 = nullptr;
@@ -375,9 +385,9 @@ void build_set(aims_grid* g, BatchSet& bs, int merge, bool density) {
   }
   if ((int64_t)bs.batch_cols.size() > (int64_t)INT32_MAX) fail(AIMS_ERR_UNSUPPORTED, "too many batch columns");
 
-  // groups of batches sharing the scratch, and the tile work list
+  // groups of batches sharing the scratch
   const size_t budget = scratch_budget_elems();
-  BatchSet::Group cur{0, 0, 0, 0, 0.0};
+  BatchSet::Group cur{0, 0, 0.0};
   size_t used = 0;
   const int nB = (int)bs.batches.size();
   for (int b = 0; b < nB; ++b) {
@@ -385,34 +395,23 @@ void build_set(aims_grid* g, BatchSet& bs, int merge, bool density) {
     const size_t need = (size_t)round_up(d.n_b, 32) * d.ldp;
     if (used > 0 && used + need > budget) {
       cur.b1 = b;
-      cur.i1 = (int64_t)bs.items.size();
       bs.groups.push_back(cur);
-      cur = BatchSet::Group{b, b, (int64_t)bs.items.size(), 0, 0.0};
+      cur = BatchSet::Group{b, b, 0.0};
       used = 0;
     }
     cur.flops += 2.0 * d.n_p * (double)d.n_b * d.n_b;
     d.slab_off = (int64_t)used;
     used += need;
     bs.slab_elems = std::max(bs.slab_elems, used);
-    const int tb = (d.n_b + kTile - 1) / kTile, tp = (d.n_p + kTile - 1) / kTile;
-    for (int ti = 0; ti < tb; ++ti)
-      for (int tj = 0; tj < (density ? tp : tb); ++tj) bs.items.push_back(TileItem{b, (int16_t)ti, (int16_t)tj});
   }
   cur.b1 = nB;
-  cur.i1 = (int64_t)bs.items.size();
   if (cur.b1 > cur.b0) bs.groups.push_back(cur);
-  if ((int64_t)bs.items.size() > INT32_MAX) fail(AIMS_ERR_UNSUPPORTED, "too many tiles");
-  // item range of each system (items are in batch order, batches in system order)
-  bs.sys_item_range.assign(2 * (size_t)g->n_sys, 0);
-  std::vector<int64_t> first(g->n_sys, -1), last(g->n_sys, -1);
-  for (int64_t i = 0; i < (int64_t)bs.items.size(); ++i) {
-    const int s = bs.batches[bs.items[i].batch].sys;
-    if (first[s] < 0) first[s] = i;
-    last[s] = i + 1;
-  }
-  for (int s = 0; s < g->n_sys; ++s) {
-    bs.sys_item_range[2 * s] = first[s] < 0 ? 0 : first[s];
-    bs.sys_item_range[2 * s + 1] = first[s] < 0 ? 0 : last[s];
+  // batch range of each system (batches are in system order)
+  bs.sys_batch_range.assign(2 * (size_t)g->n_sys, 0);
+  for (int s = 0, b = 0; s < g->n_sys; ++s) {
+    bs.sys_batch_range[2 * s] = b;
+    while (b < nB && bs.batches[b].sys == s) ++b;
+    bs.sys_batch_range[2 * s + 1] = b;
   }
 
   // upload
@@ -421,8 +420,7 @@ void build_set(aims_grid* g, BatchSet& bs, int merge, bool density) {
   bs.dv.batch_atoms = g->upload(bs.batch_atoms);
   bs.dv.batch_acol = g->upload(bs.batch_acol);
   bs.dv.batch_cols = g->upload(bs.batch_cols);
-  bs.dv.sys_item_range = g->upload(bs.sys_item_range);
-  bs.d_items = g->upload(bs.items);
+  bs.dv.sys_batch_range = g->upload(bs.sys_batch_range);
   if (bs.slab_elems > g->slab_cap) {
     if (g->d_slab1) g->release(g->d_slab1);
     if (g->d_slab2) g->release(g->d_slab2);
@@ -434,11 +432,57 @@ void build_set(aims_grid* g, BatchSet& bs, int merge, bool density) {
   }
 }
 
+// Point blocks (of 32) of the density tile for a batch of n_p points under a cap: the batch is
+// cut into ceil(n_p / (32 cap)) tiles of equal block count, at least 2 blocks each.
+int density_nbn(int n_p, int cap) {
+  const int blocks = (n_p + 31) / 32;
+  const int tiles = (blocks + cap - 1) / cap;
+  return std::max(2, (blocks + tiles - 1) / tiles);
+}
+
+// Tile work list of a batch set: square 64 x 64 tiles for the H kernel, (64 rows x 32 nbn
+// points) tiles for the density kernel, grouped per kernel variant within each batch group.
+ItemList& items_for(aims_grid* g, BatchSet& bs, int pblocks) {
+  if (!bs.density) pblocks = 0;
+  for (auto& l : bs.lists)
+    if (l->pblocks == pblocks) return *l;
+  std::unique_ptr<ItemList> L(new ItemList());
+  L->pblocks = pblocks;
+  for (const auto& gr : bs.groups) {
+    std::vector<std::vector<TileItem>> per(6);
+    for (int b = gr.b0; b < gr.b1; ++b) {
+      const BatchDesc& d = bs.batches[b];
+      const int tb = (d.n_b + kTile - 1) / kTile;
+      if (!bs.density) {
+        for (int ti = 0; ti < tb; ++ti)
+          for (int tj = 0; tj < tb; ++tj) per[0].push_back(TileItem{b, (int16_t)ti, (int16_t)tj});
+      } else {
+        const int nbn = density_nbn(d.n_p, pblocks);
+        const int tp = (d.n_p + 32 * nbn - 1) / (32 * nbn);
+        for (int ti = 0; ti < tb; ++ti)
+          for (int tj = 0; tj < tp; ++tj) per[nbn].push_back(TileItem{b, (int16_t)ti, (int16_t)tj});
+      }
+    }
+    std::vector<ItemList::Run> runs;
+    for (int v = 0; v < 6; ++v) {
+      if (per[v].empty()) continue;
+      runs.push_back(ItemList::Run{v, (int64_t)L->items.size(), (int64_t)(L->items.size() + per[v].size())});
+      L->items.insert(L->items.end(), per[v].begin(), per[v].end());
+    }
+    L->runs.push_back(runs);
+  }
+  if ((int64_t)L->items.size() > INT32_MAX) fail(AIMS_ERR_UNSUPPORTED, "too many tiles");
+  L->d_items = g->upload(L->items);
+  bs.lists.push_back(std::move(L));
+  return *bs.lists.back();
+}
+
 BatchSet& hset(aims_grid* g, int merge) {
   for (auto& p : g->hsets)
     if (p->merge == merge) return *p;
   std::unique_ptr<BatchSet> bs(new BatchSet());
   build_set(g, *bs, merge, false);
+  items_for(g, *bs, 0);
   g->hsets.push_back(std::move(bs));
   return *g->hsets.back();
 }
@@ -572,7 +616,8 @@ aims_grid* build(const aims_system* sys, int n_sys, int device, void* stream) {
   build_set(g.get(), g->dens, 0, true);
   g->d_n_sorted = (double*)g->alloc(std::max<int64_t>(1, g->n_points) * sizeof(double));
   g->d_part = (double*)g->alloc((size_t)n_sys * g->nblk_finish * 2 * sizeof(double));
-  g->d_et_part = (double*)g->alloc(std::max<size_t>(1, g->dens.items.size()) * sizeof(double));
+  g->d_et_batch = (double*)g->alloc(std::max<size_t>(1, g->dens.batches.size()) * sizeof(double));
+  for (int p = 0; p < 3; ++p) items_for(g.get(), g->dens, g->d_pblocks[p]);
   g->d_P32 = (float*)g->alloc(std::max<int64_t>(1, g->mat_total) * sizeof(float));
   // the H partitions of the default merge levels
   for (int p = 0; p < 3; ++p) hset(g.get(), g->h_merge[p]);
@@ -668,59 +713,74 @@ template <typename T>
 void run_density(aims_grid* g, aims_precision prec, const T* P, const double* v, double* n_out,
                  double* sums_out) {
   hipStream_t st = g->stream;
-  const BatchSet& bs = g->dens;
+  BatchSet& bs = g->dens;
+  const ItemList& L = items_for(g, bs, g->d_pblocks[prec]);
   hipchk(launch_fill(g->d_n_sorted, (size_t)g->n_points, 0.0, st), "fill n");
-  for (const auto& gr : bs.groups) {
-    const int nbt = gr.b1 - gr.b0, nit = (int)(gr.i1 - gr.i0);
+  hipchk(launch_fill(g->d_et_batch, bs.batches.size(), 0.0, st), "fill E_T");
+  for (size_t gi = 0; gi < bs.groups.size(); ++gi) {
+    const auto& gr = bs.groups[gi];
+    const int nbt = gr.b1 - gr.b0;
     if (prec == AIMS_BF16X3) {
       timed(g, kProfPhi, 0.0, "phi_eval", [&] {
-        return launch_phi_eval_bf16(bs.dv, gr.b0, nbt, kModeDensity, true, nullptr, g->d_slab1, g->d_slab2, st);
-      });
-      timed(g, kProfDensity, gr.flops, "density", [&] {
-        return launch_density_bf16(bs.dv, bs.d_items + gr.i0, nit, (const float*)P, g->d_slab1,
-                                   g->d_slab2, g->d_n_sorted, g->d_et_part + gr.i0, st);
+        return launch_phi_eval_bf16(bs.dv, gr.b0, nbt, kModeDensity, nullptr, g->d_slab1, g->d_slab2, st);
       });
     } else {
-      T* s1 = (T*)g->d_slab1;
-      T* s2 = (T*)g->d_slab2;
       timed(g, kProfPhi, 0.0, "phi_eval", [&] {
-        return launch_phi_eval<T>(bs.dv, gr.b0, nbt, kModeDensity, nullptr, s1, s2, st);
+        return launch_phi_eval<T>(bs.dv, gr.b0, nbt, kModeDensity, nullptr, (T*)g->d_slab1,
+                                  (T*)g->d_slab2, st);
       });
-      timed(g, kProfDensity, gr.flops, "density", [&] {
-        return launch_density<T>(bs.dv, bs.d_items + gr.i0, nit, P, s1, s2, g->d_n_sorted,
-                                 g->d_et_part + gr.i0, st);
-      });
+    }
+    for (size_t r = 0; r < L.runs[gi].size(); ++r) {
+      const auto& run = L.runs[gi][r];
+      const double work = r + 1 == L.runs[gi].size() ? gr.flops : 0.0;   // credited once per group
+      const int nit = (int)(run.i1 - run.i0);
+      if (prec == AIMS_BF16X3) {
+        timed(g, kProfDensity, work, "density", [&] {
+          return launch_density_bf16(bs.dv, run.nbn, L.d_items + run.i0, nit, (const float*)P,
+                                     g->d_slab1, g->d_slab2, g->d_n_sorted, g->d_et_batch, st);
+        });
+      } else {
+        timed(g, kProfDensity, work, "density", [&] {
+          return launch_density<T>(bs.dv, run.nbn, L.d_items + run.i0, nit, P, (const T*)g->d_slab1,
+                                   (const T*)g->d_slab2, g->d_n_sorted, g->d_et_batch, st);
+        });
+      }
     }
   }
   timed(g, kProfFinish, 0.0, "density_finish", [&] {
     return launch_density_finish(bs.dv, g->d_n_sorted, v, n_out, g->d_part, g->nblk_finish,
-                                 g->d_et_part, sums_out, st);
+                                 g->d_et_batch, sums_out, st);
   });
 }
 
 template <typename T>
 void run_hs(aims_grid* g, aims_precision prec, int mode, const double* v, double* out) {
   hipStream_t st = g->stream;
-  const BatchSet& bs = hset(g, g->h_merge[prec]);
+  BatchSet& bs = hset(g, g->h_merge[prec]);
+  const ItemList& L = items_for(g, bs, 0);
   hipchk(launch_fill(out, (size_t)g->mat_total, 0.0, st), "fill H");
-  for (const auto& gr : bs.groups) {
-    const int nbt = gr.b1 - gr.b0, nit = (int)(gr.i1 - gr.i0);
-    if (prec == AIMS_BF16X3) {
-      timed(g, kProfPhi, 0.0, "phi_eval", [&] {
-        return launch_phi_eval_bf16(bs.dv, gr.b0, nbt, mode, false, v, g->d_slab1, g->d_slab2, st);
-      });
-      timed(g, kProfHS, gr.flops, "hs", [&] {
-        return launch_hs_bf16(bs.dv, bs.d_items + gr.i0, nit, g->d_slab1, g->d_slab2, out, st);
-      });
-    } else {
-      T* s1 = (T*)g->d_slab1;
-      T* s2 = (T*)g->d_slab2;
-      timed(g, kProfPhi, 0.0, "phi_eval", [&] {
-        return launch_phi_eval<T>(bs.dv, gr.b0, nbt, mode, v, s1, s2, st);
-      });
-      timed(g, kProfHS, gr.flops, "hs", [&] {
-        return launch_hs<T>(bs.dv, bs.d_items + gr.i0, nit, s1, s2, out, st);
-      });
+  for (size_t gi = 0; gi < bs.groups.size(); ++gi) {
+    const auto& gr = bs.groups[gi];
+    const int nbt = gr.b1 - gr.b0;
+    for (const auto& run : L.runs[gi]) {
+      const int nit = (int)(run.i1 - run.i0);
+      if (prec == AIMS_BF16X3) {
+        timed(g, kProfPhi, 0.0, "phi_eval", [&] {
+          return launch_phi_eval_bf16(bs.dv, gr.b0, nbt, mode, v, g->d_slab1, g->d_slab2, st);
+        });
+        timed(g, kProfHS, gr.flops, "hs", [&] {
+          return launch_hs_bf16(bs.dv, L.d_items + run.i0, nit, g->d_slab1, g->d_slab2, out, st);
+        });
+      } else {
+        T* s1 = (T*)g->d_slab1;
+        T* s2 = (T*)g->d_slab2;
+        timed(g, kProfPhi, 0.0, "phi_eval", [&] {
+          return launch_phi_eval<T>(bs.dv, gr.b0, nbt, mode, v, s1, s2, st);
+        });
+        timed(g, kProfHS, gr.flops, "hs", [&] {
+          return launch_hs<T>(bs.dv, L.d_items + run.i0, nit, s1, s2, out, st);
+        });
+      }
     }
   }
 }
@@ -900,29 +960,23 @@ aims_status aims_profile_read(aims_grid* g, const char* kernel, int64_t* launche
   });
 }
 
-int32_t aims_n_variants(aims_precision prec) { return (prec >= AIMS_FP64 && prec <= AIMS_BF16X3) ? 1 : 0; }
-
 aims_status aims_get_tuning(const aims_grid* g, aims_precision prec, aims_tuning* out) {
-  if (!g || !out || aims_n_variants(prec) == 0) return AIMS_ERR_ARG;
+  if (!g || !out || prec < AIMS_FP64 || prec > AIMS_BF16X3) return AIMS_ERR_ARG;
   memset(out, 0, sizeof(*out));
   out->h_merge = g->h_merge[prec];
-  out->n_buckets = 1;
-  out->nb_edges[0] = INT32_MAX;
-  out->variant[0] = 0;
+  out->density_pblocks = g->d_pblocks[prec];
   return AIMS_OK;
 }
 
 aims_status aims_set_tuning(aims_grid* g, aims_precision prec, const aims_tuning* t) {
   return guarded(g, [&] {
-    if (!t || aims_n_variants(prec) == 0) fail(AIMS_ERR_ARG, "bad tuning arguments");
+    if (!t || prec < AIMS_FP64 || prec > AIMS_BF16X3) fail(AIMS_ERR_ARG, "bad tuning arguments");
     if (t->h_merge < 0 || t->h_merge > 4) fail(AIMS_ERR_ARG, "h_merge must be in 0..4");
-    if (t->n_buckets < 1 || t->n_buckets > 8) fail(AIMS_ERR_ARG, "n_buckets must be in 1..8");
-    for (int k = 0; k < t->n_buckets; ++k) {
-      if (t->variant[k] < 0 || t->variant[k] >= aims_n_variants(prec)) fail(AIMS_ERR_ARG, "bad variant");
-      if (k > 0 && t->nb_edges[k] < t->nb_edges[k - 1]) fail(AIMS_ERR_ARG, "nb_edges must ascend");
-    }
+    if (t->density_pblocks < 2 || t->density_pblocks > 5) fail(AIMS_ERR_ARG, "density_pblocks must be in 2..5");
     hset(g, t->h_merge);
+    items_for(g, g->dens, t->density_pblocks);
     g->h_merge[prec] = t->h_merge;
+    g->d_pblocks[prec] = t->density_pblocks;
   });
 }
 

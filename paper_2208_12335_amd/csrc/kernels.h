@@ -26,7 +26,7 @@ struct DeviceView {
   const double* spline64;
   const float* spline32;
   const int64_t* sys_pt_range;     // [n_sys][2] batch-order point range of each system
-  const int64_t* sys_item_range;   // [n_sys][2] density-item range of each system
+  const int64_t* sys_batch_range;  // [n_sys][2] batch range of each system
   RadialGrid rg;
   int n_sys;
 };
@@ -37,22 +37,23 @@ hipError_t launch_convert_f32(const double* x, float* y, size_t n, hipStream_t s
 template <typename T>
 hipError_t launch_phi_eval(const DeviceView& dv, int b0, int nbatch, int mode, const double* v,
                            T* slab1, T* slab2, hipStream_t st);
+hipError_t launch_phi_eval_bf16(const DeviceView& dv, int b0, int nbatch, int mode, const double* v,
+                                void* slab1, void* slab2, hipStream_t st);
+// nbn: point tile = 32 * nbn points (2..5)
 template <typename T>
-hipError_t launch_density(const DeviceView& dv, const TileItem* items, int n_items, const T* P,
-                          const T* slab1, const T* slab2, double* n_sorted, double* et_part,
+hipError_t launch_density(const DeviceView& dv, int nbn, const TileItem* items, int n_items, const T* P,
+                          const T* slab1, const T* slab2, double* n_sorted, double* et_batch,
                           hipStream_t st);
+hipError_t launch_density_bf16(const DeviceView& dv, int nbn, const TileItem* items, int n_items,
+                               const float* P, const void* slab1, const void* slab2, double* n_sorted,
+                               double* et_batch, hipStream_t st);
 template <typename T>
 hipError_t launch_hs(const DeviceView& dv, const TileItem* items, int n_items, const T* slab1,
                      const T* slab2, double* out, hipStream_t st);
-hipError_t launch_phi_eval_bf16(const DeviceView& dv, int b0, int nbatch, int mode, bool point_major,
-                                const double* v, void* slab1, void* slab2, hipStream_t st);
-hipError_t launch_density_bf16(const DeviceView& dv, const TileItem* items, int n_items, const float* P,
-                               const void* slab1, const void* slab2, double* n_sorted, double* et_part,
-                               hipStream_t st);
 hipError_t launch_hs_bf16(const DeviceView& dv, const TileItem* items, int n_items, const void* slab1,
                           const void* slab2, double* out, hipStream_t st);
 hipError_t launch_density_finish(const DeviceView& dv, const double* n_sorted, const double* v,
-                                 double* n_out, double* part, int nblk, const double* et_part,
+                                 double* n_out, double* part, int nblk, const double* et_batch,
                                  double* sums_out, hipStream_t st);
 
 }  // namespace aims

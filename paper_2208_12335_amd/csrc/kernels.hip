@@ -10,8 +10,9 @@
 //   finish kernels    caller-order scatter of n and deterministic FP64 sums N, E_V, E_T
 //
 // Precision policies: FP64 (double slabs, v_mfma_f64_16x16x4f64), FP32 (float slabs,
-// v_mfma_f32_16x16x4f32); both accumulate per tile in the slab type and reduce across batches
-// in FP64.
+// v_mfma_f32_16x16x4f32), BF16x3 (bf16 hi/lo splits of FP32 values, three
+// v_mfma_f32_16x16x32_bf16 products).  Per-tile accumulation is in the MFMA's type; everything
+// that crosses batches (n, H, S, N, E) is accumulated in FP64.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -24,6 +25,8 @@ namespace aims {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16_t;
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 
 template <typename T> struct Acc;
 template <> struct Acc<double> { typedef d4_t type; };
@@ -35,6 +38,9 @@ __device__ __forceinline__ d4_t mfma16(double a, double b, d4_t c) {
 __device__ __forceinline__ f4_t mfma16(float a, float b, f4_t c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ f4_t mfma_bf16(bf16x8_t a, bf16x8_t b, f4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
 
 // Row of the 16 x 16 output block held in accumulator register r of a lane (the column is
 // lane % 16).  Measured on gfx950: the FP64 instruction interleaves the rows of the four lane
@@ -44,21 +50,15 @@ __device__ __forceinline__ int acc_row(int lane, int r) {
   return sizeof(T) == 8 ? 4 * r + (lane >> 4) : 4 * (lane >> 4) + r;
 }
 
-__host__ __device__ __forceinline__ int round_up32(int x) { return (x + 31) & ~31; }
-
 // ------------------------------------------------------------------------------------------
 // basis evaluation into slabs
 //
-// Slab layouts (per batch, inside the group scratch; nbp = n_b rounded up to 32):
+// Slab layouts (per batch, inside the group scratch, n_b rows of ldp points):
 //   kLayoutDense   T values, function-major: [row][ldp], points contiguous
 //   kLayoutBfFn    bf16 hi/lo splits, function-major: row = [ldp hi | ldp lo]
-//   kLayoutBfPt    bf16 hi/lo splits, point-major:    row p = [nbp hi | nbp lo]
 // A split is hi = bf16(x), lo = bf16(x - hi), so that hi + lo carries ~16 significant bits.
 // ------------------------------------------------------------------------------------------
-typedef __bf16 bf16_t;
-typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
-
-enum { kLayoutDense = 0, kLayoutBfFn = 1, kLayoutBfPt = 2 };
+enum { kLayoutDense = 0, kLayoutBfFn = 1 };
 
 __device__ __forceinline__ void split_bf16(float x, bf16_t& hi, bf16_t& lo) {
   hi = (bf16_t)x;
@@ -69,7 +69,7 @@ template <typename T, int LAYOUT>
 struct SlabStore {
   T* o1;
   T* o2;
-  int ldp, nbp;
+  int ldp;
   __device__ __forceinline__ void operator()(int col, int p, T v1, T v2) const {
     o1[(size_t)col * ldp + p] = v1;
     o2[(size_t)col * ldp + p] = v2;
@@ -79,7 +79,7 @@ template <>
 struct SlabStore<float, kLayoutBfFn> {
   bf16_t* o1;
   bf16_t* o2;
-  int ldp, nbp;
+  int ldp;
   __device__ __forceinline__ void operator()(int col, int p, float v1, float v2) const {
     bf16_t h, l;
     const size_t base = (size_t)col * 2 * ldp + p;
@@ -89,22 +89,6 @@ struct SlabStore<float, kLayoutBfFn> {
     split_bf16(v2, h, l);
     o2[base] = h;
     o2[base + ldp] = l;
-  }
-};
-template <>
-struct SlabStore<float, kLayoutBfPt> {
-  bf16_t* o1;
-  bf16_t* o2;
-  int ldp, nbp;
-  __device__ __forceinline__ void operator()(int col, int p, float v1, float v2) const {
-    bf16_t h, l;
-    const size_t base = (size_t)p * 2 * nbp + col;
-    split_bf16(v1, h, l);
-    o1[base] = h;
-    o1[base + nbp] = l;
-    split_bf16(v2, h, l);
-    o2[base] = h;
-    o2[base + nbp] = l;
   }
 };
 
@@ -157,10 +141,10 @@ phi_eval_kernel(const BatchDesc* __restrict__ batches, int b0, const double4* __
                 const double* __restrict__ v, int mode, void* __restrict__ slab1,
                 void* __restrict__ slab2) {
   const BatchDesc d = batches[b0 + blockIdx.x];
-  const int np = d.n_p, na = d.n_atoms, ldp = d.ldp, nbp = round_up32(d.n_b);
+  const int np = d.n_p, na = d.n_atoms, ldp = d.ldp;
   typedef typename std::conditional<LAYOUT == kLayoutDense, T, bf16_t>::type S;
   const int64_t off = (LAYOUT == kLayoutDense ? 1 : 2) * d.slab_off;
-  SlabStore<T, LAYOUT> store{(S*)slab1 + off, (S*)slab2 + off, ldp, nbp};
+  SlabStore<T, LAYOUT> store{(S*)slab1 + off, (S*)slab2 + off, ldp};
   const int pairs = np * na;
   for (int q = threadIdx.x; q < pairs; q += blockDim.x) {
     const int k = q / np;
@@ -175,43 +159,34 @@ phi_eval_kernel(const BatchDesc* __restrict__ batches, int b0, const double4* __
                        P4.z - atom_xyz[3 * atom + 2], sd, shell_l, spline, rg, mode, T(P4.w),
                        T(wv), col0, p, store);
   }
-  // zero the padding so that the K loops may run over whole padded rows
-  if (LAYOUT != kLayoutBfPt) {
-    const int padw = ldp - np;
-    if (padw > 0) {
-      const int tot = d.n_b * padw;
-      for (int q = threadIdx.x; q < tot; q += blockDim.x) {
-        const int row = q / padw;
-        store(row, np + (q - row * padw), T(0), T(0));
-      }
-    }
-  } else {
-    // point-major: columns n_b..nbp of every row, and whole rows n_p..ldp
-    const int padc = nbp - d.n_b;
-    for (int q = threadIdx.x; q < np * padc; q += blockDim.x) {
-      const int p = q / padc;
-      store(d.n_b + (q - p * padc), p, T(0), T(0));
-    }
-    for (int q = threadIdx.x; q < (ldp - np) * nbp; q += blockDim.x) {
-      const int p = np + q / nbp;
-      store(q - (p - np) * nbp, p, T(0), T(0));
+  // zero the padding columns so that the K loops may run over whole padded rows
+  const int padw = ldp - np;
+  if (padw > 0) {
+    const int tot = d.n_b * padw;
+    for (int q = threadIdx.x; q < tot; q += blockDim.x) {
+      const int row = q / padw;
+      store(row, np + (q - row * padw), T(0), T(0));
     }
   }
 }
 
 // ------------------------------------------------------------------------------------------
-// tiled MFMA kernels: 256 threads = 4 waves, 64 x 64 output tile, each wave a 32 x 32 quarter
-// made of 2 x 2 blocks of 16 x 16 MFMA outputs.  K is staged through LDS in chunks of 16 with
-// a two-stage pipeline (global -> registers for chunk c+1 while chunk c is multiplied).
+// Tiled MFMA kernels: 256 threads = 4 waves in a 2 (rows) x 2 (columns) arrangement.  Each
+// wave owns 2 x NBN blocks of 16 x 16 outputs; blocks that lie wholly beyond the batch's rows
+// or points are skipped (a wave-uniform branch).  K is staged through LDS with a two-stage
+// pipeline (global -> registers for chunk c+1 while chunk c is multiplied), one barrier per
+// chunk.
 //
-// LDS layouts are chosen so that neither the staging stores nor the MFMA fragment reads
-// conflict: operands whose K index is contiguous in HBM are kept K-contiguous with an odd row
-// stride (kKC + 1), the point-contiguous slab operand of the density kernel is kept
-// N-contiguous with a row stride of kTile + 16.
+// LDS layouts avoid bank conflicts on both the staging stores and the MFMA fragment reads:
+// operands whose K index is contiguous in HBM stay K-contiguous with an odd row stride
+// (kKC + 1); the point-contiguous slab operand of the density kernel stays N-contiguous with a
+// row stride of (tile width + 16).  The BF16 kernels keep every operand K-contiguous in rows
+// of 32 + 8 bf16 (16-byte aligned for 128-bit fragment reads).
 // ------------------------------------------------------------------------------------------
-constexpr int kKC = 16;
-constexpr int kLdK = kKC + 1;      // K-contiguous rows
-constexpr int kLdN = kTile + 16;   // N-contiguous rows
+constexpr int kKC = 16;            // K chunk of the FP64/FP32 kernels
+constexpr int kLdK = kKC + 1;      // K-contiguous LDS rows
+constexpr int kKB = 32;            // K chunk of the BF16 kernels
+constexpr int kLdB = kKB + 8;      // their LDS rows (bf16)
 
 // XCD-aware work order: the dispatcher places workgroup g on XCD g % 8, so consecutive work
 // items (tiles of the same batch, which share its slab) are given workgroup ids that differ by
@@ -235,37 +210,50 @@ __device__ __forceinline__ void load4<float>(const float* __restrict__ p, float 
   v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
 }
 
-// One K chunk of MFMAs.  A fragments from a K-contiguous tile, B fragments from either a
-// K-contiguous tile (B_KMAJOR = false: Bs[n][k]) or an N-contiguous tile (Bs[k][n]).
-template <typename T, bool B_NCONTIG>
-__device__ __forceinline__ void mfma_chunk(const T* __restrict__ As, const T* __restrict__ Bs,
-                                           int lane, int wm, int wn,
-                                           typename Acc<T>::type (&acc)[2][2]) {
+// Epilogue of the density kernels: given per-lane column sums sn[ni] (over the lane's rows)
+// and the lane's energy partial se, reduce over the tile's rows and add into n (FP64 atomics,
+// one per point and tile) and into the batch's E_T partial.
+template <int NBN>
+__device__ __forceinline__ void density_epilogue(double (&sn)[NBN], double se, int lane, int wave,
+                                                 int wm, int wn, int p0, int n_p, int pt_off,
+                                                 double (*red_n)[32 * NBN], double* red_e,
+                                                 double* __restrict__ n_sorted,
+                                                 double* __restrict__ et_batch, int batch) {
+  constexpr int PT = 32 * NBN;
 #pragma unroll
-  for (int kk = 0; kk < kKC; kk += 4) {
-    const int kr = kk + (lane >> 4);
-    T a[2], b[2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) a[i] = As[(wm * 32 + i * 16 + (lane & 15)) * kLdK + kr];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int n = wn * 32 + i * 16 + (lane & 15);
-      b[i] = B_NCONTIG ? Bs[kr * kLdN + n] : Bs[n * kLdK + kr];
-    }
-#pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-      for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = mfma16(a[mi], b[ni], acc[mi][ni]);
+  for (int ni = 0; ni < NBN; ++ni) {
+    sn[ni] += __shfl_xor(sn[ni], 16);
+    sn[ni] += __shfl_xor(sn[ni], 32);
   }
+  for (int off = 32; off > 0; off >>= 1) se += __shfl_xor(se, off);
+  if (lane < 16) {
+#pragma unroll
+    for (int ni = 0; ni < NBN; ++ni) red_n[wm][wn * 16 * NBN + ni * 16 + lane] = sn[ni];
+  }
+  if (lane == 0) red_e[wave] = se;
+  __syncthreads();
+  for (int t = threadIdx.x; t < PT; t += blockDim.x) {
+    const int p = p0 + t;
+    if (p < n_p) unsafeAtomicAdd(n_sorted + pt_off + p, red_n[0][t] + red_n[1][t]);
+  }
+  if (threadIdx.x == 0)
+    unsafeAtomicAdd(et_batch + batch, (red_e[0] + red_e[1]) + (red_e[2] + red_e[3]));
 }
 
-template <typename T>
+// Density, FP64 / FP32: X^T[j][p] = sum_i P_b[j][i] Phi^T[i][p] for 64 basis rows j and
+// 32 * NBN points p of one batch.
+template <typename T, int NBN>
 __global__ void __launch_bounds__(256)
 density_kernel(const TileItem* __restrict__ items, int n_items, const BatchDesc* __restrict__ batches,
                const SystemDesc* __restrict__ systems, const double4* __restrict__ pts,
                const int32_t* __restrict__ batch_cols, const T* __restrict__ Pmat,
                const T* __restrict__ slab1, const T* __restrict__ slab2,
-               double* __restrict__ n_sorted, double* __restrict__ et_part) {
+               double* __restrict__ n_sorted, double* __restrict__ et_batch) {
+  constexpr int PT = 32 * NBN;          // points per tile
+  constexpr int LDN = PT + 16;          // N-contiguous LDS rows
+  constexpr int BW = PT / 4;            // 4-element units per B row
+  constexpr int BU = kKC * BW;          // units of the B tile
+  constexpr int BQ = (BU + 255) / 256;  // units per thread
   const int item = xcd_item(blockIdx.x, n_items);
   if (item >= n_items) return;
   const TileItem it = items[item];
@@ -273,59 +261,101 @@ density_kernel(const TileItem* __restrict__ items, int n_items, const BatchDesc*
   const SystemDesc sys = systems[d.sys];
   const int nb = d.n_b, ldp = d.ldp;
   const int j0 = it.ti * kTile;       // rows of X^T: basis functions
-  const int p0 = it.tj * kTile;       // columns: points
+  const int p0 = it.tj * PT;          // columns: points
   const int* cols = batch_cols + d.col_off;
   const T* S1 = slab1 + d.slab_off;
   const T* S2 = slab2 + d.slab_off;
   const T* Pm = Pmat + sys.mat_off;
 
   __shared__ T As[2][kTile * kLdK];   // P_b[j][i], i contiguous
-  __shared__ T Bs[2][kKC * kLdN];     // Phi^T[i][p], p contiguous
-  __shared__ double red_n[2][kTile];
+  __shared__ T Bs[2][kKC * LDN];      // Phi^T[i][p], p contiguous
+  __shared__ double red_n[2][PT];
   __shared__ double red_e[4];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
+  const int mrows = nb - (j0 + wm * 32);           // block mi is live if 16 mi < mrows
+  const int ncols = d.n_p - (p0 + wn * 16 * NBN);  // block ni is live if 16 ni < ncols
   typedef typename Acc<T>::type acc_t;
-  acc_t acc[2][2];
+  acc_t acc[2][NBN];
 #pragma unroll
   for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = acc_t{0, 0, 0, 0};
+    for (int ni = 0; ni < NBN; ++ni) acc[mi][ni] = acc_t{0, 0, 0, 0};
 
-  // staging roles: A row ra (4 consecutive k at 4*sa), B row kb (4 consecutive p at 4*nbq)
+  // A staging: row ra, 4 consecutive k at 4 sa; column indices loaded one chunk ahead
   const int ra = tid >> 2, sa = tid & 3;
-  const int kb = tid >> 4, nbq = tid & 15;
   const int grow = (j0 + ra < nb) ? cols[j0 + ra] : -1;
   const T* Prow = Pm + (size_t)(grow < 0 ? 0 : grow) * sys.nb;
-  const bool bcol_ok = p0 + 4 * nbq < ldp;
-  const bool wave_live = (j0 + wm * 32 < nb) && (p0 + wn * 32 < d.n_p);
-
-  T ra_v[4], rb_v[4];
-  // column indices of P_b are loaded one chunk ahead of the P values that need them
   int cidx[4];
-  auto load_cols = [&](int kc) {
+  T av[4], bv[BQ][4];
+  bool kval[4];
+  auto load_cols = [&](int kc) {     // unconditional load of a clamped index (no branch)
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int k = kc + 4 * sa + c;
-      cidx[c] = (k < nb) ? cols[k] : -1;
+      kval[c] = k < nb;
+      cidx[c] = cols[k < nb ? k : nb - 1];
     }
   };
+  // loads are issued unconditionally from clamped addresses (no branch, so they stay in flight
+  // across the multiply of the current chunk); invalid elements are zeroed when stashed
+  bool aok[4], bok[BQ];
   auto fetch = [&](int kc) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) ra_v[c] = (grow >= 0 && cidx[c] >= 0) ? Prow[cidx[c]] : T(0);
-    if (kc + kb < nb && bcol_ok) {
-      load4<T>(S1 + (size_t)(kc + kb) * ldp + p0 + 4 * nbq, rb_v);
-    } else {
+    for (int c = 0; c < 4; ++c) {
+      aok[c] = grow >= 0 && kval[c];
+      av[c] = Prow[cidx[c]];
+    }
 #pragma unroll
-      for (int c = 0; c < 4; ++c) rb_v[c] = T(0);
+    for (int q = 0; q < BQ; ++q) {
+      const int u = tid + 256 * q;
+      const int k = u / BW, n4 = u - k * BW;
+      bok[q] = u < BU && kc + k < nb && p0 + 4 * n4 < ldp;
+      load4<T>(S1 + (bok[q] ? (size_t)(kc + k) * ldp + p0 + 4 * n4 : 0), bv[q]);
     }
   };
   auto stash = [&](int buf) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      As[buf][ra * kLdK + 4 * sa + c] = ra_v[c];
-      Bs[buf][kb * kLdN + 4 * nbq + c] = rb_v[c];
+    for (int c = 0; c < 4; ++c) As[buf][ra * kLdK + 4 * sa + c] = aok[c] ? av[c] : T(0);
+#pragma unroll
+    for (int q = 0; q < BQ; ++q) {
+      const int u = tid + 256 * q;
+      if (u < BU) {
+        const int k = u / BW, n4 = u - k * BW;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Bs[buf][k * LDN + 4 * n4 + c] = bok[q] ? bv[q][c] : T(0);
+      }
+    }
+  };
+  const bool full = mrows >= 32 && ncols >= 16 * NBN;
+  auto multiply = [&](int buf) {
+    T a[4][2], b[4][NBN];
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int kr = 4 * s4 + (lane >> 4);
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi) a[s4][mi] = As[buf][(wm * 32 + mi * 16 + (lane & 15)) * kLdK + kr];
+#pragma unroll
+      for (int ni = 0; ni < NBN; ++ni) b[s4][ni] = Bs[buf][kr * LDN + wn * 16 * NBN + ni * 16 + (lane & 15)];
+    }
+    if (full) {
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+          for (int ni = 0; ni < NBN; ++ni) acc[mi][ni] = mfma16(a[s4][mi], b[s4][ni], acc[mi][ni]);
+    } else {
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi) {
+          if (16 * mi >= mrows) continue;
+#pragma unroll
+          for (int ni = 0; ni < NBN; ++ni)
+            if (16 * ni < ncols) acc[mi][ni] = mfma16(a[s4][mi], b[s4][ni], acc[mi][ni]);
+        }
     }
   };
 
@@ -341,16 +371,16 @@ density_kernel(const TileItem* __restrict__ items, int n_items, const BatchDesc*
       fetch((c + 1) * kKC);
       load_cols((c + 2) * kKC);
     }
-    if (wave_live) mfma_chunk<T, true>(As[buf], Bs[buf], lane, wm, wn, acc);
+    multiply(buf);
     if (c + 1 < nchunk) stash(buf ^ 1);
     __syncthreads();
   }
 
   // epilogue: column sums of X^T o Phi^T (density) and of w X^T o tPhi^T (kinetic energy)
-  double sn[2] = {0.0, 0.0}, se = 0.0;
+  double sn[NBN], se = 0.0;
 #pragma unroll
-  for (int ni = 0; ni < 2; ++ni) {
-    const int p = p0 + wn * 32 + ni * 16 + (lane & 15);
+  for (int ni = 0; ni < NBN; ++ni) {
+    const int p = p0 + wn * 16 * NBN + ni * 16 + (lane & 15);
     double accn = 0.0, acce = 0.0;
     if (p < d.n_p) {
 #pragma unroll
@@ -366,25 +396,15 @@ density_kernel(const TileItem* __restrict__ items, int n_items, const BatchDesc*
         }
       acce *= pts[d.pt_off + p].w;
     }
-    accn += __shfl_xor(accn, 16);
-    accn += __shfl_xor(accn, 32);
     sn[ni] = accn;
     se += acce;
   }
-  for (int off = 32; off > 0; off >>= 1) se += __shfl_xor(se, off);
-  if (lane < 16) {
-    red_n[wm][wn * 32 + lane] = sn[0];
-    red_n[wm][wn * 32 + 16 + lane] = sn[1];
-  }
-  if (lane == 0) red_e[wave] = se;
-  __syncthreads();
-  if (tid < kTile) {
-    const int p = p0 + tid;
-    if (p < d.n_p) unsafeAtomicAdd(n_sorted + d.pt_off + p, red_n[0][tid] + red_n[1][tid]);
-  }
-  if (tid == 0) et_part[item] = (red_e[0] + red_e[1]) + (red_e[2] + red_e[3]);
+  density_epilogue<NBN>(sn, se, lane, wave, wm, wn, p0, d.n_p, d.pt_off, red_n, red_e, n_sorted,
+                        et_batch, it.batch);
 }
 
+// H / S, FP64 / FP32: C[i][j] = sum_p slab1[i][p] slab2[j][p] over the batch's points, then a
+// FP64 scatter-add into the dense output.
 template <typename T>
 __global__ void __launch_bounds__(256)
 hs_kernel(const TileItem* __restrict__ items, int n_items, const BatchDesc* __restrict__ batches,
@@ -403,13 +423,13 @@ hs_kernel(const TileItem* __restrict__ items, int n_items, const BatchDesc* __re
   __shared__ T Bs[2][kTile * kLdK];   // second operand [j][p], p contiguous (K)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
+  const int mrows = nb - (i0 + wm * 32), ncols = nb - (jb + wn * 32);
   typedef typename Acc<T>::type acc_t;
   acc_t acc[2][2];
 #pragma unroll
   for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
     for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = acc_t{0, 0, 0, 0};
-  const bool wave_live = (i0 + wm * 32 < nb) && (jb + wn * 32 < nb);
 
   const int row = tid >> 2, seg = tid & 3;
   const bool a_ok = i0 + row < nb, b_ok = jb + row < nb;
@@ -417,16 +437,45 @@ hs_kernel(const TileItem* __restrict__ items, int n_items, const BatchDesc* __re
   const T* Bp = slab2 + d.slab_off + (size_t)(b_ok ? jb + row : 0) * ldp + 4 * seg;
   T av[4], bv[4];
   auto fetch = [&](int kc) {
-    if (a_ok) load4<T>(Ap + kc, av);
-    else for (int c = 0; c < 4; ++c) av[c] = T(0);
-    if (b_ok) load4<T>(Bp + kc, bv);
-    else for (int c = 0; c < 4; ++c) bv[c] = T(0);
+    load4<T>(Ap + kc, av);     // rows beyond n_b read row 0 and are zeroed when stashed
+    load4<T>(Bp + kc, bv);
   };
   auto stash = [&](int buf) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      As[buf][row * kLdK + 4 * seg + c] = av[c];
-      Bs[buf][row * kLdK + 4 * seg + c] = bv[c];
+      As[buf][row * kLdK + 4 * seg + c] = a_ok ? av[c] : T(0);
+      Bs[buf][row * kLdK + 4 * seg + c] = b_ok ? bv[c] : T(0);
+    }
+  };
+  const bool full = mrows >= 32 && ncols >= 32;
+  auto multiply = [&](int buf) {
+    T a[4][2], b[4][2];
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int kr = 4 * s4 + (lane >> 4);
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        a[s4][i] = As[buf][(wm * 32 + i * 16 + (lane & 15)) * kLdK + kr];
+        b[s4][i] = Bs[buf][(wn * 32 + i * 16 + (lane & 15)) * kLdK + kr];
+      }
+    }
+    if (full) {
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+          for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = mfma16(a[s4][mi], b[s4][ni], acc[mi][ni]);
+    } else {
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi) {
+          if (16 * mi >= mrows) continue;
+#pragma unroll
+          for (int ni = 0; ni < 2; ++ni)
+            if (16 * ni < ncols) acc[mi][ni] = mfma16(a[s4][mi], b[s4][ni], acc[mi][ni]);
+        }
     }
   };
   const int nchunk = ldp / kKC;
@@ -436,11 +485,11 @@ hs_kernel(const TileItem* __restrict__ items, int n_items, const BatchDesc* __re
   for (int c = 0; c < nchunk; ++c) {
     const int buf = c & 1;
     if (c + 1 < nchunk) fetch((c + 1) * kKC);
-    if (wave_live) mfma_chunk<T, false>(As[buf], Bs[buf], lane, wm, wn, acc);
+    multiply(buf);
     if (c + 1 < nchunk) stash(buf ^ 1);
     __syncthreads();
   }
-  if (!wave_live) return;
+  if (mrows <= 0 || ncols <= 0) return;
   double* O = out + sys.mat_off;
 #pragma unroll
   for (int ni = 0; ni < 2; ++ni) {
@@ -458,105 +507,92 @@ hs_kernel(const TileItem* __restrict__ items, int n_items, const BatchDesc* __re
 }
 
 // ------------------------------------------------------------------------------------------
-// BF16x3 kernels: per-batch contractions as three bf16 MFMA products of hi/lo splits
-// (a_hi b_hi + a_hi b_lo + a_lo b_hi, v_mfma_f32_16x16x32_bf16, FP32 accumulation), with the
-// same 64 x 64 tiling as above and K staged in chunks of 32 through LDS rows of 32 + 8 bf16.
+// BF16x3 kernels: a_hi b_hi + a_hi b_lo + a_lo b_hi on v_mfma_f32_16x16x32_bf16 (FP32
+// accumulation), K chunks of 32, same 64-row tiles.
 // ------------------------------------------------------------------------------------------
-constexpr int kKB = 32;            // K chunk
-constexpr int kLdB = kKB + 8;      // LDS row length (bf16), keeps 16-byte alignment
-
-__device__ __forceinline__ f4_t mfma_bf16(bf16x8_t a, bf16x8_t b, f4_t c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-
-// A tile rows m (K contiguous), B tile rows n (K contiguous); each a hi and a lo plane.
-__device__ __forceinline__ void mfma_chunk_bf16x3(const bf16_t* __restrict__ Ah, const bf16_t* __restrict__ Al,
-                                                  const bf16_t* __restrict__ Bh, const bf16_t* __restrict__ Bl,
-                                                  int lane, int wm, int wn, f4_t (&acc)[2][2]) {
-  const int kq = 8 * (lane >> 4);
-  bf16x8_t ah[2], al[2], bh[2], bl[2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const int ra = (wm * 32 + i * 16 + (lane & 15)) * kLdB + kq;
-    const int rb = (wn * 32 + i * 16 + (lane & 15)) * kLdB + kq;
-    ah[i] = *reinterpret_cast<const bf16x8_t*>(Ah + ra);
-    al[i] = *reinterpret_cast<const bf16x8_t*>(Al + ra);
-    bh[i] = *reinterpret_cast<const bf16x8_t*>(Bh + rb);
-    bl[i] = *reinterpret_cast<const bf16x8_t*>(Bl + rb);
-  }
-#pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-    for (int ni = 0; ni < 2; ++ni) {
-      acc[mi][ni] = mfma_bf16(al[mi], bh[ni], acc[mi][ni]);
-      acc[mi][ni] = mfma_bf16(ah[mi], bl[ni], acc[mi][ni]);
-      acc[mi][ni] = mfma_bf16(ah[mi], bh[ni], acc[mi][ni]);
-    }
+__device__ __forceinline__ void mfma3(bf16x8_t ah, bf16x8_t al, bf16x8_t bh, bf16x8_t bl, f4_t& acc) {
+  acc = mfma_bf16(al, bh, acc);
+  acc = mfma_bf16(ah, bl, acc);
+  acc = mfma_bf16(ah, bh, acc);
 }
 
 __device__ __forceinline__ float bf_pair(const bf16_t* p, int lo_off) {
   return (float)p[0] + (float)p[lo_off];
 }
 
-// Density: X^T[j][p] = sum_i P_b[j][i] Phi[p][i]; P from the FP32 copy, split while staging;
-// Phi (and t Phi) from point-major bf16 slabs.
+// Density: X^T[j][p] = sum_i P_b[j][i] Phi[p][i].  P comes from its FP32 copy and is split
+// while staged; Phi comes from the function-major bf16 slab and is transposed into
+// K-contiguous LDS rows while staged.
+template <int NBN>
 __global__ void __launch_bounds__(256)
 density_kernel_bf16(const TileItem* __restrict__ items, int n_items, const BatchDesc* __restrict__ batches,
                     const SystemDesc* __restrict__ systems, const double4* __restrict__ pts,
                     const int32_t* __restrict__ batch_cols, const float* __restrict__ Pmat,
                     const bf16_t* __restrict__ slab1, const bf16_t* __restrict__ slab2,
-                    double* __restrict__ n_sorted, double* __restrict__ et_part) {
+                    double* __restrict__ n_sorted, double* __restrict__ et_batch) {
+  constexpr int PT = 32 * NBN;
+  constexpr int BW = PT / 8;            // 8-point units per slab row
+  constexpr int BU = kKB * BW;          // units of the B tile
+  constexpr int BQ = (BU + 255) / 256;
   const int item = xcd_item(blockIdx.x, n_items);
   if (item >= n_items) return;
   const TileItem it = items[item];
   const BatchDesc d = batches[it.batch];
   const SystemDesc sys = systems[d.sys];
-  const int nb = d.n_b, ldp = d.ldp, nbp = round_up32(nb);
-  const int j0 = it.ti * kTile, p0 = it.tj * kTile;
+  const int nb = d.n_b, ldp = d.ldp;
+  const int j0 = it.ti * kTile, p0 = it.tj * PT;
   const int* cols = batch_cols + d.col_off;
   const bf16_t* S1 = slab1 + 2 * d.slab_off;
   const bf16_t* S2 = slab2 + 2 * d.slab_off;
   const float* Pm = Pmat + sys.mat_off;
 
   __shared__ __attribute__((aligned(16))) bf16_t Ah[2][kTile * kLdB], Al[2][kTile * kLdB];
-  __shared__ __attribute__((aligned(16))) bf16_t Bh[2][kTile * kLdB], Bl[2][kTile * kLdB];
-  __shared__ double red_n[2][kTile];
+  __shared__ __attribute__((aligned(16))) bf16_t Bh[2][PT * kLdB], Bl[2][PT * kLdB];
+  __shared__ double red_n[2][PT];
   __shared__ double red_e[4];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
-  f4_t acc[2][2];
+  const int mrows = nb - (j0 + wm * 32);
+  const int ncols = d.n_p - (p0 + wn * 16 * NBN);
+  f4_t acc[2][NBN];
 #pragma unroll
   for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = f4_t{0, 0, 0, 0};
+    for (int ni = 0; ni < NBN; ++ni) acc[mi][ni] = f4_t{0, 0, 0, 0};
 
-  // staging roles: row r = tid / 4 of both tiles, K segment 8 * (tid % 4)
   const int r = tid >> 2, sg = tid & 3;
   const int grow = (j0 + r < nb) ? cols[j0 + r] : -1;
   const float* Prow = Pm + (size_t)(grow < 0 ? 0 : grow) * sys.nb;
-  const bool b_ok = p0 + r < ldp;
-  const bf16_t* Bsrc1 = S1 + (size_t)(b_ok ? p0 + r : 0) * 2 * nbp + 8 * sg;
-  const bool wave_live = (j0 + wm * 32 < nb) && (p0 + wn * 32 < d.n_p);
 
   int cidx[8];
   float pa[8];
-  bf16x8_t bh, bl;
-  auto load_cols = [&](int kc) {
+  bf16x8_t bh[BQ], bl[BQ];
+  const bool full = mrows >= 32 && ncols >= 16 * NBN;
+  bool kval[8];
+  auto load_cols = [&](int kc) {     // unconditional load of a clamped index (no branch)
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const int k = kc + 8 * sg + c;
-      cidx[c] = (k < nb) ? cols[k] : -1;
+      kval[c] = k < nb;
+      cidx[c] = cols[k < nb ? k : nb - 1];
     }
   };
+  bool aok[8], bok[BQ];
   auto fetch = [&](int kc) {
 #pragma unroll
-    for (int c = 0; c < 8; ++c) pa[c] = (grow >= 0 && cidx[c] >= 0) ? Prow[cidx[c]] : 0.f;
-    if (b_ok) {
-      bh = *reinterpret_cast<const bf16x8_t*>(Bsrc1 + kc);
-      bl = *reinterpret_cast<const bf16x8_t*>(Bsrc1 + nbp + kc);
-    } else {
-      for (int c = 0; c < 8; ++c) { bh[c] = (bf16_t)0.f; bl[c] = (bf16_t)0.f; }
+    for (int c = 0; c < 8; ++c) {
+      aok[c] = grow >= 0 && kval[c];
+      pa[c] = Prow[cidx[c]];
+    }
+#pragma unroll
+    for (int q = 0; q < BQ; ++q) {
+      const int u = tid + 256 * q;
+      const int k = u & (kKB - 1), ps = u / kKB;
+      bok[q] = u < BU && kc + k < nb && p0 + 8 * ps < ldp;
+      const bf16_t* src = S1 + (bok[q] ? (size_t)(kc + k) * 2 * ldp + p0 + 8 * ps : 0);
+      bh[q] = *reinterpret_cast<const bf16x8_t*>(src);
+      bl[q] = *reinterpret_cast<const bf16x8_t*>(src + ldp);
     }
   };
   auto stash = [&](int buf) {
@@ -564,14 +600,56 @@ density_kernel_bf16(const TileItem* __restrict__ items, int n_items, const Batch
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       bf16_t hh, ll;
-      split_bf16(pa[c], hh, ll);
+      split_bf16(aok[c] ? pa[c] : 0.f, hh, ll);
       h[c] = hh;
       l[c] = ll;
     }
     *reinterpret_cast<bf16x8_t*>(&Ah[buf][r * kLdB + 8 * sg]) = h;
     *reinterpret_cast<bf16x8_t*>(&Al[buf][r * kLdB + 8 * sg]) = l;
-    *reinterpret_cast<bf16x8_t*>(&Bh[buf][r * kLdB + 8 * sg]) = bh;
-    *reinterpret_cast<bf16x8_t*>(&Bl[buf][r * kLdB + 8 * sg]) = bl;
+    const bf16_t zero = (bf16_t)0.f;
+#pragma unroll
+    for (int q = 0; q < BQ; ++q) {
+      const int u = tid + 256 * q;
+      if (u < BU) {
+        const int k = u & (kKB - 1), ps = u / kKB;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          Bh[buf][(8 * ps + c) * kLdB + k] = bok[q] ? bh[q][c] : zero;
+          Bl[buf][(8 * ps + c) * kLdB + k] = bok[q] ? bl[q][c] : zero;
+        }
+      }
+    }
+  };
+  auto multiply = [&](int buf) {
+    const int kq = 8 * (lane >> 4);
+    bf16x8_t ah[2], al[2];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi) {
+      const int o = (wm * 32 + mi * 16 + (lane & 15)) * kLdB + kq;
+      ah[mi] = *reinterpret_cast<const bf16x8_t*>(&Ah[buf][o]);
+      al[mi] = *reinterpret_cast<const bf16x8_t*>(&Al[buf][o]);
+    }
+    bf16x8_t bhv[NBN], blv[NBN];
+#pragma unroll
+    for (int ni = 0; ni < NBN; ++ni) {
+      const int o = (wn * 16 * NBN + ni * 16 + (lane & 15)) * kLdB + kq;
+      bhv[ni] = *reinterpret_cast<const bf16x8_t*>(&Bh[buf][o]);
+      blv[ni] = *reinterpret_cast<const bf16x8_t*>(&Bl[buf][o]);
+    }
+    if (full) {
+#pragma unroll
+      for (int ni = 0; ni < NBN; ++ni)
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi) mfma3(ah[mi], al[mi], bhv[ni], blv[ni], acc[mi][ni]);
+    } else {
+#pragma unroll
+      for (int ni = 0; ni < NBN; ++ni) {
+        if (16 * ni >= ncols) continue;
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+          if (16 * mi < mrows) mfma3(ah[mi], al[mi], bhv[ni], blv[ni], acc[mi][ni]);
+      }
+    }
   };
 
   const int nchunk = (nb + kKB - 1) / kKB;
@@ -586,15 +664,15 @@ density_kernel_bf16(const TileItem* __restrict__ items, int n_items, const Batch
       fetch((c + 1) * kKB);
       load_cols((c + 2) * kKB);
     }
-    if (wave_live) mfma_chunk_bf16x3(Ah[buf], Al[buf], Bh[buf], Bl[buf], lane, wm, wn, acc);
+    multiply(buf);
     if (c + 1 < nchunk) stash(buf ^ 1);
     __syncthreads();
   }
 
-  double sn[2] = {0.0, 0.0}, se = 0.0;
+  double sn[NBN], se = 0.0;
 #pragma unroll
-  for (int ni = 0; ni < 2; ++ni) {
-    const int p = p0 + wn * 32 + ni * 16 + (lane & 15);
+  for (int ni = 0; ni < NBN; ++ni) {
+    const int p = p0 + wn * 16 * NBN + ni * 16 + (lane & 15);
     double accn = 0.0, acce = 0.0;
     if (p < d.n_p) {
 #pragma unroll
@@ -604,30 +682,18 @@ density_kernel_bf16(const TileItem* __restrict__ items, int n_items, const Batch
           const int j = j0 + wm * 32 + mi * 16 + acc_row<float>(lane, rr);
           if (j < nb) {
             const double x = (double)acc[mi][ni][rr];
-            const size_t o = (size_t)p * 2 * nbp + j;
-            accn += x * (double)bf_pair(S1 + o, nbp);
-            acce += x * (double)bf_pair(S2 + o, nbp);
+            const size_t o = (size_t)j * 2 * ldp + p;
+            accn += x * (double)bf_pair(S1 + o, ldp);
+            acce += x * (double)bf_pair(S2 + o, ldp);
           }
         }
       acce *= pts[d.pt_off + p].w;
     }
-    accn += __shfl_xor(accn, 16);
-    accn += __shfl_xor(accn, 32);
     sn[ni] = accn;
     se += acce;
   }
-  for (int off = 32; off > 0; off >>= 1) se += __shfl_xor(se, off);
-  if (lane < 16) {
-    red_n[wm][wn * 32 + lane] = sn[0];
-    red_n[wm][wn * 32 + 16 + lane] = sn[1];
-  }
-  if (lane == 0) red_e[wave] = se;
-  __syncthreads();
-  if (tid < kTile) {
-    const int p = p0 + tid;
-    if (p < d.n_p) unsafeAtomicAdd(n_sorted + d.pt_off + p, red_n[0][tid] + red_n[1][tid]);
-  }
-  if (tid == 0) et_part[item] = (red_e[0] + red_e[1]) + (red_e[2] + red_e[3]);
+  density_epilogue<NBN>(sn, se, lane, wave, wm, wn, p0, d.n_p, d.pt_off, red_n, red_e, n_sorted,
+                        et_batch, it.batch);
 }
 
 // H/S: C[i][j] = sum_p slab1[i][p] slab2[j][p] from function-major bf16 slabs.
@@ -649,12 +715,12 @@ hs_kernel_bf16(const TileItem* __restrict__ items, int n_items, const BatchDesc*
   __shared__ __attribute__((aligned(16))) bf16_t Bh[2][kTile * kLdB], Bl[2][kTile * kLdB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
+  const int mrows = nb - (i0 + wm * 32), ncols = nb - (jb + wn * 32);
   f4_t acc[2][2];
 #pragma unroll
   for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
     for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = f4_t{0, 0, 0, 0};
-  const bool wave_live = (i0 + wm * 32 < nb) && (jb + wn * 32 < nb);
 
   const int r = tid >> 2, sg = tid & 3;
   const bool a_ok = i0 + r < nb, b_ok = jb + r < nb;
@@ -662,24 +728,45 @@ hs_kernel_bf16(const TileItem* __restrict__ items, int n_items, const BatchDesc*
   const bf16_t* Bp = slab2 + 2 * d.slab_off + (size_t)(b_ok ? jb + r : 0) * 2 * ldp + 8 * sg;
   bf16x8_t ah, al, bh, bl;
   auto fetch = [&](int kc) {
-    if (a_ok) {
-      ah = *reinterpret_cast<const bf16x8_t*>(Ap + kc);
-      al = *reinterpret_cast<const bf16x8_t*>(Ap + ldp + kc);
-    } else {
-      for (int c = 0; c < 8; ++c) { ah[c] = (bf16_t)0.f; al[c] = (bf16_t)0.f; }
-    }
-    if (b_ok) {
-      bh = *reinterpret_cast<const bf16x8_t*>(Bp + kc);
-      bl = *reinterpret_cast<const bf16x8_t*>(Bp + ldp + kc);
-    } else {
-      for (int c = 0; c < 8; ++c) { bh[c] = (bf16_t)0.f; bl[c] = (bf16_t)0.f; }
-    }
+    ah = *reinterpret_cast<const bf16x8_t*>(Ap + kc);   // rows beyond n_b read row 0 and are
+    al = *reinterpret_cast<const bf16x8_t*>(Ap + ldp + kc);   // zeroed when stashed
+    bh = *reinterpret_cast<const bf16x8_t*>(Bp + kc);
+    bl = *reinterpret_cast<const bf16x8_t*>(Bp + ldp + kc);
   };
   auto stash = [&](int buf) {
-    *reinterpret_cast<bf16x8_t*>(&Ah[buf][r * kLdB + 8 * sg]) = ah;
-    *reinterpret_cast<bf16x8_t*>(&Al[buf][r * kLdB + 8 * sg]) = al;
-    *reinterpret_cast<bf16x8_t*>(&Bh[buf][r * kLdB + 8 * sg]) = bh;
-    *reinterpret_cast<bf16x8_t*>(&Bl[buf][r * kLdB + 8 * sg]) = bl;
+    const bf16x8_t z = {};
+    *reinterpret_cast<bf16x8_t*>(&Ah[buf][r * kLdB + 8 * sg]) = a_ok ? ah : z;
+    *reinterpret_cast<bf16x8_t*>(&Al[buf][r * kLdB + 8 * sg]) = a_ok ? al : z;
+    *reinterpret_cast<bf16x8_t*>(&Bh[buf][r * kLdB + 8 * sg]) = b_ok ? bh : z;
+    *reinterpret_cast<bf16x8_t*>(&Bl[buf][r * kLdB + 8 * sg]) = b_ok ? bl : z;
+  };
+  const bool full = mrows >= 32 && ncols >= 32;
+  auto multiply = [&](int buf) {
+    const int kq = 8 * (lane >> 4);
+    bf16x8_t a_h[2], a_l[2], b_h[2], b_l[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int oa = (wm * 32 + i * 16 + (lane & 15)) * kLdB + kq;
+      const int ob = (wn * 32 + i * 16 + (lane & 15)) * kLdB + kq;
+      a_h[i] = *reinterpret_cast<const bf16x8_t*>(&Ah[buf][oa]);
+      a_l[i] = *reinterpret_cast<const bf16x8_t*>(&Al[buf][oa]);
+      b_h[i] = *reinterpret_cast<const bf16x8_t*>(&Bh[buf][ob]);
+      b_l[i] = *reinterpret_cast<const bf16x8_t*>(&Bl[buf][ob]);
+    }
+    if (full) {
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni) mfma3(a_h[mi], a_l[mi], b_h[ni], b_l[ni], acc[mi][ni]);
+    } else {
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi) {
+        if (16 * mi >= mrows) continue;
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+          if (16 * ni < ncols) mfma3(a_h[mi], a_l[mi], b_h[ni], b_l[ni], acc[mi][ni]);
+      }
+    }
   };
   const int nchunk = ldp / kKB;
   fetch(0);
@@ -688,11 +775,11 @@ hs_kernel_bf16(const TileItem* __restrict__ items, int n_items, const BatchDesc*
   for (int c = 0; c < nchunk; ++c) {
     const int buf = c & 1;
     if (c + 1 < nchunk) fetch((c + 1) * kKB);
-    if (wave_live) mfma_chunk_bf16x3(Ah[buf], Al[buf], Bh[buf], Bl[buf], lane, wm, wn, acc);
+    multiply(buf);
     if (c + 1 < nchunk) stash(buf ^ 1);
     __syncthreads();
   }
-  if (!wave_live) return;
+  if (mrows <= 0 || ncols <= 0) return;
   double* O = out + sys.mat_off;
 #pragma unroll
   for (int ni = 0; ni < 2; ++ni) {
@@ -739,7 +826,7 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 }
 
 // Scatter n to caller order and form per-block partial sums of w n and w v n over the points
-// [pt0, pt1) of one system (blockIdx.y = system).
+// of one system (blockIdx.y = system).
 __global__ void __launch_bounds__(256)
 density_finish_kernel(const int64_t* __restrict__ sys_pt_range, const double4* __restrict__ pts,
                       const int32_t* __restrict__ perm, const double* __restrict__ n_sorted,
@@ -768,8 +855,8 @@ density_finish_kernel(const int64_t* __restrict__ sys_pt_range, const double4* _
 
 // One block per system: sums_out[3 s + (0, 1, 2)] = N, E_V, E_T in a fixed order.
 __global__ void __launch_bounds__(256)
-sums_finish_kernel(const double* __restrict__ part, int nblk, const int64_t* __restrict__ sys_item_range,
-                   const double* __restrict__ et_part, double* __restrict__ sums_out) {
+sums_finish_kernel(const double* __restrict__ part, int nblk, const int64_t* __restrict__ sys_batch_range,
+                   const double* __restrict__ et_batch, double* __restrict__ sums_out) {
   __shared__ double sh[4];
   const int s = blockIdx.x;
   double sn = 0.0, sv = 0.0, se = 0.0;
@@ -777,8 +864,8 @@ sums_finish_kernel(const double* __restrict__ part, int nblk, const int64_t* __r
     sn += part[(size_t)s * nblk * 2 + 2 * i];
     sv += part[(size_t)s * nblk * 2 + 2 * i + 1];
   }
-  for (int64_t i = sys_item_range[2 * s] + threadIdx.x; i < sys_item_range[2 * s + 1]; i += blockDim.x)
-    se += et_part[i];
+  for (int64_t i = sys_batch_range[2 * s] + threadIdx.x; i < sys_batch_range[2 * s + 1]; i += blockDim.x)
+    se += et_batch[i];
   sn = block_sum<256>(sn, sh);
   sv = block_sum<256>(sv, sh);
   se = block_sum<256>(se, sh);
@@ -797,6 +884,8 @@ static inline int grid_for(size_t n, int per) {
   if (g > 65536) g = 65536;
   return (int)(g ? g : 1);
 }
+
+static inline int item_grid(int n_items) { return ((n_items + 7) / 8) * 8; }
 
 hipError_t launch_fill(double* x, size_t n, double val, hipStream_t st) {
   if (n == 0) return hipSuccess;
@@ -822,30 +911,37 @@ hipError_t launch_phi_eval(const DeviceView& dv, int b0, int nbatch, int mode, c
   return hipGetLastError();
 }
 
-hipError_t launch_phi_eval_bf16(const DeviceView& dv, int b0, int nbatch, int mode, bool point_major,
-                                const double* v, void* slab1, void* slab2, hipStream_t st) {
+hipError_t launch_phi_eval_bf16(const DeviceView& dv, int b0, int nbatch, int mode, const double* v,
+                                void* slab1, void* slab2, hipStream_t st) {
   if (nbatch == 0) return hipSuccess;
-  if (point_major)
-    hipLaunchKernelGGL((phi_eval_kernel<float, kLayoutBfPt>), dim3(nbatch), dim3(256), 0, st,
-                       dv.batches, b0, dv.pts, dv.perm, dv.batch_atoms, dv.batch_acol, dv.atom_xyz,
-                       dv.atom_species, dv.species, dv.shell_l, dv.spline32, dv.rg, v, mode,
-                       slab1, slab2);
-  else
-    hipLaunchKernelGGL((phi_eval_kernel<float, kLayoutBfFn>), dim3(nbatch), dim3(256), 0, st,
-                       dv.batches, b0, dv.pts, dv.perm, dv.batch_atoms, dv.batch_acol, dv.atom_xyz,
-                       dv.atom_species, dv.species, dv.shell_l, dv.spline32, dv.rg, v, mode,
-                       slab1, slab2);
+  hipLaunchKernelGGL((phi_eval_kernel<float, kLayoutBfFn>), dim3(nbatch), dim3(256), 0, st,
+                     dv.batches, b0, dv.pts, dv.perm, dv.batch_atoms, dv.batch_acol, dv.atom_xyz,
+                     dv.atom_species, dv.species, dv.shell_l, dv.spline32, dv.rg, v, mode,
+                     slab1, slab2);
   return hipGetLastError();
 }
 
+template <typename T, int NBN>
+static void density_launch_nbn(const DeviceView& dv, const TileItem* items, int n_items, const T* P,
+                               const T* slab1, const T* slab2, double* n_sorted, double* et_batch,
+                               hipStream_t st) {
+  hipLaunchKernelGGL((density_kernel<T, NBN>), dim3(item_grid(n_items)), dim3(256), 0, st, items,
+                     n_items, dv.batches, dv.systems, dv.pts, dv.batch_cols, P, slab1, slab2,
+                     n_sorted, et_batch);
+}
+
 template <typename T>
-hipError_t launch_density(const DeviceView& dv, const TileItem* items, int n_items, const T* P,
-                          const T* slab1, const T* slab2, double* n_sorted, double* et_part,
+hipError_t launch_density(const DeviceView& dv, int nbn, const TileItem* items, int n_items, const T* P,
+                          const T* slab1, const T* slab2, double* n_sorted, double* et_batch,
                           hipStream_t st) {
   if (n_items == 0) return hipSuccess;
-  const int grid = ((n_items + 7) / 8) * 8;
-  hipLaunchKernelGGL(density_kernel<T>, dim3(grid), dim3(256), 0, st, items, n_items, dv.batches,
-                     dv.systems, dv.pts, dv.batch_cols, P, slab1, slab2, n_sorted, et_part);
+  switch (nbn) {
+    case 2: density_launch_nbn<T, 2>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, st); break;
+    case 3: density_launch_nbn<T, 3>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, st); break;
+    case 4: density_launch_nbn<T, 4>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, st); break;
+    case 5: density_launch_nbn<T, 5>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, st); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -853,41 +949,52 @@ template <typename T>
 hipError_t launch_hs(const DeviceView& dv, const TileItem* items, int n_items, const T* slab1,
                      const T* slab2, double* out, hipStream_t st) {
   if (n_items == 0) return hipSuccess;
-  const int grid = ((n_items + 7) / 8) * 8;
-  hipLaunchKernelGGL(hs_kernel<T>, dim3(grid), dim3(256), 0, st, items, n_items, dv.batches,
-                     dv.systems, dv.batch_cols, slab1, slab2, out);
+  hipLaunchKernelGGL(hs_kernel<T>, dim3(item_grid(n_items)), dim3(256), 0, st, items, n_items,
+                     dv.batches, dv.systems, dv.batch_cols, slab1, slab2, out);
   return hipGetLastError();
 }
 
-hipError_t launch_density_bf16(const DeviceView& dv, const TileItem* items, int n_items, const float* P,
-                               const void* slab1, const void* slab2, double* n_sorted, double* et_part,
-                               hipStream_t st) {
+template <int NBN>
+static void density_bf16_launch_nbn(const DeviceView& dv, const TileItem* items, int n_items,
+                                    const float* P, const void* slab1, const void* slab2,
+                                    double* n_sorted, double* et_batch, hipStream_t st) {
+  hipLaunchKernelGGL((density_kernel_bf16<NBN>), dim3(item_grid(n_items)), dim3(256), 0, st, items,
+                     n_items, dv.batches, dv.systems, dv.pts, dv.batch_cols, P, (const bf16_t*)slab1,
+                     (const bf16_t*)slab2, n_sorted, et_batch);
+}
+
+hipError_t launch_density_bf16(const DeviceView& dv, int nbn, const TileItem* items, int n_items,
+                               const float* P, const void* slab1, const void* slab2, double* n_sorted,
+                               double* et_batch, hipStream_t st) {
   if (n_items == 0) return hipSuccess;
-  const int grid = ((n_items + 7) / 8) * 8;
-  hipLaunchKernelGGL(density_kernel_bf16, dim3(grid), dim3(256), 0, st, items, n_items, dv.batches,
-                     dv.systems, dv.pts, dv.batch_cols, P, (const bf16_t*)slab1, (const bf16_t*)slab2,
-                     n_sorted, et_part);
+  switch (nbn) {
+    case 2: density_bf16_launch_nbn<2>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, st); break;
+    case 3: density_bf16_launch_nbn<3>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, st); break;
+    case 4: density_bf16_launch_nbn<4>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, st); break;
+    case 5: density_bf16_launch_nbn<5>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, st); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_hs_bf16(const DeviceView& dv, const TileItem* items, int n_items, const void* slab1,
                           const void* slab2, double* out, hipStream_t st) {
   if (n_items == 0) return hipSuccess;
-  const int grid = ((n_items + 7) / 8) * 8;
-  hipLaunchKernelGGL(hs_kernel_bf16, dim3(grid), dim3(256), 0, st, items, n_items, dv.batches,
-                     dv.systems, dv.batch_cols, (const bf16_t*)slab1, (const bf16_t*)slab2, out);
+  hipLaunchKernelGGL(hs_kernel_bf16, dim3(item_grid(n_items)), dim3(256), 0, st, items, n_items,
+                     dv.batches, dv.systems, dv.batch_cols, (const bf16_t*)slab1, (const bf16_t*)slab2,
+                     out);
   return hipGetLastError();
 }
 
 hipError_t launch_density_finish(const DeviceView& dv, const double* n_sorted, const double* v,
-                                 double* n_out, double* part, int nblk, const double* et_part,
+                                 double* n_out, double* part, int nblk, const double* et_batch,
                                  double* sums_out, hipStream_t st) {
   hipLaunchKernelGGL(density_finish_kernel, dim3(nblk, dv.n_sys), dim3(256), 0, st,
                      dv.sys_pt_range, dv.pts, dv.perm, n_sorted, v, n_out, part, nblk);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(sums_finish_kernel, dim3(dv.n_sys), dim3(256), 0, st, part, nblk,
-                     dv.sys_item_range, et_part, sums_out);
+                     dv.sys_batch_range, et_batch, sums_out);
   return hipGetLastError();
 }
 
@@ -895,10 +1002,10 @@ template hipError_t launch_phi_eval<double>(const DeviceView&, int, int, int, co
                                             double*, double*, hipStream_t);
 template hipError_t launch_phi_eval<float>(const DeviceView&, int, int, int, const double*,
                                            float*, float*, hipStream_t);
-template hipError_t launch_density<double>(const DeviceView&, const TileItem*, int, const double*,
+template hipError_t launch_density<double>(const DeviceView&, int, const TileItem*, int, const double*,
                                            const double*, const double*, double*, double*,
                                            hipStream_t);
-template hipError_t launch_density<float>(const DeviceView&, const TileItem*, int, const float*,
+template hipError_t launch_density<float>(const DeviceView&, int, const TileItem*, int, const float*,
                                           const float*, const float*, double*, double*,
                                           hipStream_t);
 template hipError_t launch_hs<double>(const DeviceView&, const TileItem*, int, const double*,

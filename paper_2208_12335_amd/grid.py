@@ -149,21 +149,15 @@ class AimsGrid:
     def get_tuning(self, prec="fp64"):
         t = AimsTuning()
         self._check(self._L.aims_get_tuning(self._h, PRECISION[prec], byref(t)))
-        return {"h_merge": t.h_merge, "nb_edges": list(t.nb_edges[:t.n_buckets]),
-                "variant": list(t.variant[:t.n_buckets])}
+        return {"h_merge": t.h_merge, "density_pblocks": t.density_pblocks}
 
-    def set_tuning(self, h_merge: int, nb_edges: Sequence[int] = (2 ** 31 - 1,),
-                   variant: Sequence[int] = (0,), prec="fp64"):
+    def set_tuning(self, h_merge: Optional[int] = None, density_pblocks: Optional[int] = None,
+                   prec="fp64"):
+        cur = self.get_tuning(prec)
         t = AimsTuning()
-        t.h_merge = int(h_merge)
-        t.n_buckets = len(nb_edges)
-        for k, (e, v) in enumerate(zip(nb_edges, variant)):
-            t.nb_edges[k] = int(e)
-            t.variant[k] = int(v)
+        t.h_merge = int(cur["h_merge"] if h_merge is None else h_merge)
+        t.density_pblocks = int(cur["density_pblocks"] if density_pblocks is None else density_pblocks)
         self._check(self._L.aims_set_tuning(self._h, PRECISION[prec], byref(t)))
-
-    def n_variants(self, prec="fp64"):
-        return int(self._L.aims_n_variants(PRECISION[prec]))
 
     def profile(self, on: bool = True):
         self._check(self._L.aims_profile_enable(self._h, 1 if on else 0))

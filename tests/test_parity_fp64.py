@@ -131,3 +131,20 @@ def test_h_merge_levels_same_result(gpu, merge):
     Hr, Sr = GridOracle(inst).integrate_h(inst.v)
     assert relerr(H.cpu().numpy().reshape(nb, nb), Hr) < TOL
     assert relerr(S.cpu().numpy().reshape(nb, nb), Sr) < TOL
+
+
+@pytest.mark.parametrize("pblocks", [2, 3, 4, 5])
+def test_density_tile_widths_same_result(gpu, pblocks):
+    # the density work tiles span 64 .. 160 points; every width gives the oracle's n
+    inst = synth.make_instance("c2", n_atoms=10, box=7.0, seed=1)
+    g = AimsGrid(inst, device=gpu.index)
+    g.set_tuning(density_pblocks=pblocks, prec="fp64")
+    assert g.get_tuning("fp64")["density_pblocks"] == pblocks
+    P = torch.from_numpy(inst.P).to(gpu).reshape(-1)
+    v = torch.from_numpy(inst.v).to(gpu)
+    n, sums = g.update_density(P, v)
+    torch.cuda.synchronize()
+    d = GridOracle(inst).density(inst.P, inst.v)
+    assert relerr(n.cpu().numpy(), d["n"]) < TOL
+    s = sums.cpu().numpy()[0]
+    assert abs(s[2] - d["E_T"]) < TOL * abs(d["E_T"])
