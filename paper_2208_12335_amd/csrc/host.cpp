@@ -218,7 +218,12 @@ struct aims_grid {
   float* d_P32 = nullptr;
   void* d_slab1 = nullptr;
   void* d_slab2 = nullptr;
+  void* d_slab3 = nullptr;            // backward: X = Phi P_b
+  void* d_slab4 = nullptr;            // backward: Y = (T Phi) P_b
   size_t slab_cap = 0;                // elements per slab currently allocated
+  size_t slab_cap34 = 0;
+  double* d_ntmp = nullptr;           // backward: n in caller order (not returned)
+  double* d_sums_tmp = nullptr;
 
   ~aims_grid() {
     if (!owned.empty()) {
@@ -877,9 +882,97 @@ aims_status aims_integrate_h_backward(aims_grid* g, aims_precision prec, const d
                                       double* dE_dP_or_null, double* dE_dv_or_null,
                                       double* dE_dR_or_null) {
   return guarded(g, [&] {
-    (void)prec; (void)atom_xyz; (void)P; (void)v; (void)gE;
-    (void)dE_dP_or_null; (void)dE_dv_or_null; (void)dE_dR_or_null;
-    fail(AIMS_ERR_UNSUPPORTED, "backward is not available in this build");
+    check_prec(prec);
+    require_device(P, "P");
+    require_device(v, "v", g->n_points > 0);
+    require_device(gE, "gE");
+    if (dE_dP_or_null) require_device(dE_dP_or_null, "dE_dP");
+    if (dE_dv_or_null) require_device(dE_dv_or_null, "dE_dv", g->n_points > 0);
+    if (dE_dR_or_null) require_device(dE_dR_or_null, "dE_dR");
+    set_positions(g, atom_xyz);
+    hipStream_t st = g->stream;
+    if (!g->d_ntmp) {
+      g->d_ntmp = (double*)g->alloc(std::max<int64_t>(1, g->n_points) * sizeof(double));
+      g->d_sums_tmp = (double*)g->alloc(3 * (size_t)g->n_sys * sizeof(double));
+    }
+    // dE/dP = gE H
+    if (dE_dP_or_null) {
+      hs_call(g, prec, kModeH, v, dE_dP_or_null);
+      hipchk(launch_scale(dE_dP_or_null, dE_dP_or_null, (size_t)g->mat_total, gE, st), "scale dE/dP");
+    }
+    if (!dE_dv_or_null && !dE_dR_or_null) return;
+    // the density pass provides n (for dE/dv) and the FP32 copy of P for the mixed forms
+    density_call(g, prec, P, v, g->d_ntmp, g->d_sums_tmp);
+    if (dE_dv_or_null)
+      hipchk(launch_dv(g->dens.dv, dE_dv_or_null, g->d_n_sorted, g->n_points, gE, st), "dE/dv");
+    if (!dE_dR_or_null) return;
+    // dE/dR: X = Phi P_b and Y = (T Phi) P_b per batch, then the Pulay reduction
+    BatchSet& bs = g->dens;
+    if (g->slab_cap34 < bs.slab_elems) {
+      if (g->d_slab3) g->release(g->d_slab3);
+      if (g->d_slab4) g->release(g->d_slab4);
+      g->d_slab3 = g->d_slab4 = nullptr;
+      g->slab_cap34 = 0;
+      g->d_slab3 = g->alloc(bs.slab_elems * sizeof(double));
+      g->d_slab4 = g->alloc(bs.slab_elems * sizeof(double));
+      g->slab_cap34 = bs.slab_elems;
+    }
+    hipchk(launch_fill(dE_dR_or_null, 3 * (size_t)g->n_atoms, 0.0, st), "fill dE/dR");
+    const ItemList& L = items_for(g, bs, g->d_pblocks[prec]);
+    for (size_t gi = 0; gi < bs.groups.size(); ++gi) {
+      const auto& gr = bs.groups[gi];
+      const int nbt = gr.b1 - gr.b0;
+      if (prec == AIMS_FP64) {
+        double *s1 = (double*)g->d_slab1, *s2 = (double*)g->d_slab2;
+        double *s3 = (double*)g->d_slab3, *s4 = (double*)g->d_slab4;
+        timed(g, kProfPhi, 0.0, "phi_eval", [&] {
+          return launch_phi_eval<double>(bs.dv, gr.b0, nbt, kModeDensity, nullptr, s1, s2, st);
+        });
+        for (const auto& run : L.runs[gi]) {
+          const int nit = (int)(run.i1 - run.i0);
+          timed(g, kProfBackward, gr.flops / L.runs[gi].size(), "X", [&] {
+            return launch_density<double>(bs.dv, run.nbn, L.d_items + run.i0, nit, P, s1, s1, nullptr,
+                                          nullptr, st, s3);
+          });
+          timed(g, kProfBackward, gr.flops / L.runs[gi].size(), "Y", [&] {
+            return launch_density<double>(bs.dv, run.nbn, L.d_items + run.i0, nit, P, s2, s2, nullptr,
+                                          nullptr, st, s4);
+          });
+        }
+        timed(g, kProfBackward, 0.0, "pulay", [&] {
+          return launch_pulay<double>(bs.dv, gr.b0, nbt, v, s3, s4, gE, dE_dR_or_null, st);
+        });
+      } else {
+        float *s3 = (float*)g->d_slab3, *s4 = (float*)g->d_slab4;
+        if (prec == AIMS_BF16X3) {
+          timed(g, kProfPhi, 0.0, "phi_eval", [&] {
+            return launch_phi_eval_bf16(bs.dv, gr.b0, nbt, kModeDensity, nullptr, g->d_slab1, g->d_slab2, st);
+          });
+        } else {
+          timed(g, kProfPhi, 0.0, "phi_eval", [&] {
+            return launch_phi_eval<float>(bs.dv, gr.b0, nbt, kModeDensity, nullptr, (float*)g->d_slab1,
+                                          (float*)g->d_slab2, st);
+          });
+        }
+        for (const auto& run : L.runs[gi]) {
+          const int nit = (int)(run.i1 - run.i0);
+          for (int which = 0; which < 2; ++which) {
+            void* src = which == 0 ? g->d_slab1 : g->d_slab2;
+            float* dst = which == 0 ? s3 : s4;
+            timed(g, kProfBackward, gr.flops / L.runs[gi].size(), "XY", [&] {
+              if (prec == AIMS_BF16X3)
+                return launch_density_bf16(bs.dv, run.nbn, L.d_items + run.i0, nit, g->d_P32, src, src,
+                                           nullptr, nullptr, st, dst);
+              return launch_density<float>(bs.dv, run.nbn, L.d_items + run.i0, nit, g->d_P32,
+                                           (const float*)src, (const float*)src, nullptr, nullptr, st, dst);
+            });
+          }
+        }
+        timed(g, kProfBackward, 0.0, "pulay", [&] {
+          return launch_pulay<float>(bs.dv, gr.b0, nbt, v, s3, s4, gE, dE_dR_or_null, st);
+        });
+      }
+    }
   });
 }
 

@@ -40,13 +40,20 @@ hipError_t launch_phi_eval(const DeviceView& dv, int b0, int nbatch, int mode, c
 hipError_t launch_phi_eval_bf16(const DeviceView& dv, int b0, int nbatch, int mode, const double* v,
                                 void* slab1, void* slab2, hipStream_t st);
 // nbn: point tile = 32 * nbn points (2..5)
+// xout != NULL: store X^T = P_b slab1 into xout (function-major slab) instead of forming n
 template <typename T>
 hipError_t launch_density(const DeviceView& dv, int nbn, const TileItem* items, int n_items, const T* P,
                           const T* slab1, const T* slab2, double* n_sorted, double* et_batch,
-                          hipStream_t st);
+                          hipStream_t st, T* xout = nullptr);
 hipError_t launch_density_bf16(const DeviceView& dv, int nbn, const TileItem* items, int n_items,
                                const float* P, const void* slab1, const void* slab2, double* n_sorted,
-                               double* et_batch, hipStream_t st);
+                               double* et_batch, hipStream_t st, float* xout = nullptr);
+template <typename T>
+hipError_t launch_pulay(const DeviceView& dv, int b0, int nbatch, const double* v, const T* X,
+                        const T* Y, const double* gE, double* dE_dR, hipStream_t st);
+hipError_t launch_scale(double* y, const double* x, size_t n, const double* gE, hipStream_t st);
+hipError_t launch_dv(const DeviceView& dv, double* dE_dv, const double* n_sorted, int64_t n,
+                     const double* gE, hipStream_t st);
 template <typename T>
 hipError_t launch_hs(const DeviceView& dv, const TileItem* items, int n_items, const T* slab1,
                      const T* slab2, double* out, hipStream_t st);

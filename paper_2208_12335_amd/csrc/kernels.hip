@@ -248,7 +248,8 @@ density_kernel(const TileItem* __restrict__ items, int n_items, const BatchDesc*
                const SystemDesc* __restrict__ systems, const double4* __restrict__ pts,
                const int32_t* __restrict__ batch_cols, const T* __restrict__ Pmat,
                const T* __restrict__ slab1, const T* __restrict__ slab2,
-               double* __restrict__ n_sorted, double* __restrict__ et_batch) {
+               double* __restrict__ n_sorted, double* __restrict__ et_batch,
+               T* __restrict__ xout) {
   constexpr int PT = 32 * NBN;          // points per tile
   constexpr int LDN = PT + 16;          // N-contiguous LDS rows
   constexpr int BW = PT / 4;            // 4-element units per B row
@@ -376,6 +377,21 @@ density_kernel(const TileItem* __restrict__ items, int n_items, const BatchDesc*
     __syncthreads();
   }
 
+  if (xout) {   // store mode (backward): X^T[j][p] into a function-major slab
+#pragma unroll
+    for (int ni = 0; ni < NBN; ++ni) {
+      const int p = p0 + wn * 16 * NBN + ni * 16 + (lane & 15);
+      if (p >= d.n_p) continue;
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int j = j0 + wm * 32 + mi * 16 + acc_row<T>(lane, r);
+          if (j < nb) xout[d.slab_off + (size_t)j * ldp + p] = acc[mi][ni][r];
+        }
+    }
+    return;
+  }
   // epilogue: column sums of X^T o Phi^T (density) and of w X^T o tPhi^T (kinetic energy)
   double sn[NBN], se = 0.0;
 #pragma unroll
@@ -529,7 +545,8 @@ density_kernel_bf16(const TileItem* __restrict__ items, int n_items, const Batch
                     const SystemDesc* __restrict__ systems, const double4* __restrict__ pts,
                     const int32_t* __restrict__ batch_cols, const float* __restrict__ Pmat,
                     const bf16_t* __restrict__ slab1, const bf16_t* __restrict__ slab2,
-                    double* __restrict__ n_sorted, double* __restrict__ et_batch) {
+                    double* __restrict__ n_sorted, double* __restrict__ et_batch,
+                    float* __restrict__ xout) {
   constexpr int PT = 32 * NBN;
   constexpr int BW = PT / 8;            // 8-point units per slab row
   constexpr int BU = kKB * BW;          // units of the B tile
@@ -669,6 +686,21 @@ density_kernel_bf16(const TileItem* __restrict__ items, int n_items, const Batch
     __syncthreads();
   }
 
+  if (xout) {   // store mode (backward): X^T[j][p] as FP32 into a function-major slab
+#pragma unroll
+    for (int ni = 0; ni < NBN; ++ni) {
+      const int p = p0 + wn * 16 * NBN + ni * 16 + (lane & 15);
+      if (p >= d.n_p) continue;
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int j = j0 + wm * 32 + mi * 16 + acc_row<float>(lane, rr);
+          if (j < nb) xout[d.slab_off + (size_t)j * ldp + p] = acc[mi][ni][rr];
+        }
+    }
+    return;
+  }
   double sn[NBN], se = 0.0;
 #pragma unroll
   for (int ni = 0; ni < NBN; ++ni) {
@@ -794,6 +826,116 @@ hs_kernel_bf16(const TileItem* __restrict__ items, int n_items, const BatchDesc*
         if (i < nb) unsafeAtomicAdd(O + (size_t)cols[i] * sys.nb + gj, (double)acc[mi][ni][rr]);
       }
   }
+}
+
+// ------------------------------------------------------------------------------------------
+// Backward: Pulay-type forces from basis gradients.  For every (point, relevant atom) pair the
+// radial functions, their derivatives and the solid-harmonic gradients are recomputed and
+//   g_a += w_p sum_{i on a} [(2 v_p X_pi + Y_pi) grad phi_i(p) + X_pi grad tphi_i(p)]
+// with grad phi = (R' - l R/r) Y_lm u + (R/r) grad S_lm(u) (same with K for t phi); the batch's
+// per-atom sums are reduced in LDS (FP64 atomics) and dE/dR_a -= gE g_a is added in FP64.
+// ------------------------------------------------------------------------------------------
+constexpr int kPulayAtoms = 512;       // per-batch atom accumulators held in LDS
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+pulay_kernel(const BatchDesc* __restrict__ batches, int b0, const double4* __restrict__ pts,
+             const int32_t* __restrict__ perm, const int32_t* __restrict__ batch_atoms,
+             const int32_t* __restrict__ batch_acol, const double* __restrict__ atom_xyz,
+             const int32_t* __restrict__ atom_species, const SpeciesDesc* __restrict__ species,
+             const int32_t* __restrict__ shell_l, const T* __restrict__ spline, RadialGrid rg,
+             const double* __restrict__ v, const T* __restrict__ Xs, const T* __restrict__ Ys,
+             const double* __restrict__ gE, double* __restrict__ dE_dR) {
+  __shared__ double g[kPulayAtoms * 3];
+  const BatchDesc d = batches[b0 + blockIdx.x];
+  const int np = d.n_p, na = d.n_atoms, ldp = d.ldp;
+  const bool in_lds = na <= kPulayAtoms;
+  if (in_lds)
+    for (int t = threadIdx.x; t < 3 * na; t += blockDim.x) g[t] = 0.0;
+  __syncthreads();
+  const T* X = Xs + d.slab_off;
+  const T* Y = Ys + d.slab_off;
+  const double ge = gE[0];
+  const int pairs = np * na;
+  for (int q = threadIdx.x; q < pairs; q += blockDim.x) {
+    const int k = q / np;
+    const int p = q - k * np;
+    const int atom = batch_atoms[d.atom_off + k];
+    const int col0 = batch_acol[d.atom_off + k];
+    const SpeciesDesc sd = species[atom_species[atom]];
+    const double4 P4 = pts[d.pt_off + p];
+    const double dx = P4.x - atom_xyz[3 * atom], dy = P4.y - atom_xyz[3 * atom + 1],
+                 dz = P4.z - atom_xyz[3 * atom + 2];
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    if (!(r < rg.rc)) continue;
+    const double rr = fmax(r, 1e-12);
+    const double inv = 1.0 / rr;
+    const T ux = T(dx * inv), uy = T(dy * inv), uz = T(dz * inv), ir = T(inv);
+    const RadialPos rp = radial_pos(rr, rg);
+    const T dt = T(rp.dt);
+    const T* c = spline + sd.spline_off + (size_t)rp.k * sd.nshell * 8;
+    const T two_v = T(2.0 * v[perm[d.pt_off + p]]);
+    T gx = 0, gy = 0, gz = 0;
+    int f = col0;
+    for (int j = 0; j < sd.nshell; ++j) {
+      const T R = cubic(c + j * 8, dt), dR = cubic_d(c + j * 8, dt) * ir;
+      const T K = cubic(c + j * 8 + 4, dt), dK = cubic_d(c + j * 8 + 4, dt) * ir;
+      const int l = shell_l[sd.shell_l_off + j];
+      T Yl[7], Gx[7], Gy[7], Gz[7];
+      ylm_l<T>(l, ux, uy, uz, Yl);
+      ylm_grad_l<T>(l, ux, uy, uz, Gx, Gy, Gz);
+      const T aR = dR - T(l) * R * ir, aK = dK - T(l) * K * ir;
+      const T bR = R * ir, bK = K * ir;
+      const int nm = 2 * l + 1;
+      for (int m = 0; m < nm; ++m) {
+        const size_t o = (size_t)(f + m) * ldp + p;
+        const T xv = X[o], yv = Y[o];
+        const T cp = two_v * xv + yv;      // multiplies grad phi
+        // radial parts along u, angular parts along grad S
+        const T ru = cp * aR * Yl[m] + xv * aK * Yl[m];
+        const T rs = cp * bR + xv * bK;
+        gx += ru * ux + rs * Gx[m];
+        gy += ru * uy + rs * Gy[m];
+        gz += ru * uz + rs * Gz[m];
+      }
+      f += nm;
+    }
+    const double w = P4.w;
+    if (in_lds) {
+      atomicAdd(&g[3 * k], w * (double)gx);
+      atomicAdd(&g[3 * k + 1], w * (double)gy);
+      atomicAdd(&g[3 * k + 2], w * (double)gz);
+    } else {
+      unsafeAtomicAdd(dE_dR + 3 * atom, -ge * w * (double)gx);
+      unsafeAtomicAdd(dE_dR + 3 * atom + 1, -ge * w * (double)gy);
+      unsafeAtomicAdd(dE_dR + 3 * atom + 2, -ge * w * (double)gz);
+    }
+  }
+  __syncthreads();
+  if (in_lds)
+    for (int t = threadIdx.x; t < 3 * na; t += blockDim.x) {
+      const int atom = batch_atoms[d.atom_off + t / 3];
+      unsafeAtomicAdd(dE_dR + 3 * atom + t % 3, -ge * g[t]);
+    }
+}
+
+// y[i] = gE * x[i]
+__global__ void scale_kernel(double* __restrict__ y, const double* __restrict__ x, size_t n,
+                             const double* __restrict__ gE) {
+  const double s = gE[0];
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    y[i] = s * x[i];
+}
+
+// dE/dv in caller order: gE w_p n_p
+__global__ void dv_kernel(double* __restrict__ dv, const double* __restrict__ n_sorted,
+                          const double4* __restrict__ pts, const int32_t* __restrict__ perm,
+                          int64_t n, const double* __restrict__ gE) {
+  const double s = gE[0];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dv[perm[i]] = s * pts[i].w * n_sorted[i];
 }
 
 // ------------------------------------------------------------------------------------------
@@ -924,22 +1066,22 @@ hipError_t launch_phi_eval_bf16(const DeviceView& dv, int b0, int nbatch, int mo
 template <typename T, int NBN>
 static void density_launch_nbn(const DeviceView& dv, const TileItem* items, int n_items, const T* P,
                                const T* slab1, const T* slab2, double* n_sorted, double* et_batch,
-                               hipStream_t st) {
+                               T* xout, hipStream_t st) {
   hipLaunchKernelGGL((density_kernel<T, NBN>), dim3(item_grid(n_items)), dim3(256), 0, st, items,
                      n_items, dv.batches, dv.systems, dv.pts, dv.batch_cols, P, slab1, slab2,
-                     n_sorted, et_batch);
+                     n_sorted, et_batch, xout);
 }
 
 template <typename T>
 hipError_t launch_density(const DeviceView& dv, int nbn, const TileItem* items, int n_items, const T* P,
                           const T* slab1, const T* slab2, double* n_sorted, double* et_batch,
-                          hipStream_t st) {
+                          hipStream_t st, T* xout) {
   if (n_items == 0) return hipSuccess;
   switch (nbn) {
-    case 2: density_launch_nbn<T, 2>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, st); break;
-    case 3: density_launch_nbn<T, 3>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, st); break;
-    case 4: density_launch_nbn<T, 4>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, st); break;
-    case 5: density_launch_nbn<T, 5>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, st); break;
+    case 2: density_launch_nbn<T, 2>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, st); break;
+    case 3: density_launch_nbn<T, 3>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, st); break;
+    case 4: density_launch_nbn<T, 4>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, st); break;
+    case 5: density_launch_nbn<T, 5>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -957,23 +1099,48 @@ hipError_t launch_hs(const DeviceView& dv, const TileItem* items, int n_items, c
 template <int NBN>
 static void density_bf16_launch_nbn(const DeviceView& dv, const TileItem* items, int n_items,
                                     const float* P, const void* slab1, const void* slab2,
-                                    double* n_sorted, double* et_batch, hipStream_t st) {
+                                    double* n_sorted, double* et_batch, float* xout, hipStream_t st) {
   hipLaunchKernelGGL((density_kernel_bf16<NBN>), dim3(item_grid(n_items)), dim3(256), 0, st, items,
                      n_items, dv.batches, dv.systems, dv.pts, dv.batch_cols, P, (const bf16_t*)slab1,
-                     (const bf16_t*)slab2, n_sorted, et_batch);
+                     (const bf16_t*)slab2, n_sorted, et_batch, xout);
 }
 
 hipError_t launch_density_bf16(const DeviceView& dv, int nbn, const TileItem* items, int n_items,
                                const float* P, const void* slab1, const void* slab2, double* n_sorted,
-                               double* et_batch, hipStream_t st) {
+                               double* et_batch, hipStream_t st, float* xout) {
   if (n_items == 0) return hipSuccess;
   switch (nbn) {
-    case 2: density_bf16_launch_nbn<2>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, st); break;
-    case 3: density_bf16_launch_nbn<3>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, st); break;
-    case 4: density_bf16_launch_nbn<4>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, st); break;
-    case 5: density_bf16_launch_nbn<5>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, st); break;
+    case 2: density_bf16_launch_nbn<2>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, st); break;
+    case 3: density_bf16_launch_nbn<3>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, st); break;
+    case 4: density_bf16_launch_nbn<4>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, st); break;
+    case 5: density_bf16_launch_nbn<5>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, st); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_pulay(const DeviceView& dv, int b0, int nbatch, const double* v, const T* X,
+                        const T* Y, const double* gE, double* dE_dR, hipStream_t st) {
+  if (nbatch == 0) return hipSuccess;
+  const T* spline = (const T*)(sizeof(T) == 8 ? (const void*)dv.spline64 : (const void*)dv.spline32);
+  hipLaunchKernelGGL(pulay_kernel<T>, dim3(nbatch), dim3(256), 0, st, dv.batches, b0, dv.pts,
+                     dv.perm, dv.batch_atoms, dv.batch_acol, dv.atom_xyz, dv.atom_species,
+                     dv.species, dv.shell_l, spline, dv.rg, v, X, Y, gE, dE_dR);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(double* y, const double* x, size_t n, const double* gE, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(scale_kernel, dim3(grid_for(n, 256 * 4)), dim3(256), 0, st, y, x, n, gE);
+  return hipGetLastError();
+}
+
+hipError_t launch_dv(const DeviceView& dv, double* dE_dv, const double* n_sorted, int64_t n,
+                     const double* gE, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(dv_kernel, dim3(grid_for(n, 256 * 4)), dim3(256), 0, st, dE_dv, n_sorted, dv.pts,
+                     dv.perm, n, gE);
   return hipGetLastError();
 }
 
@@ -1004,10 +1171,14 @@ template hipError_t launch_phi_eval<float>(const DeviceView&, int, int, int, con
                                            float*, float*, hipStream_t);
 template hipError_t launch_density<double>(const DeviceView&, int, const TileItem*, int, const double*,
                                            const double*, const double*, double*, double*,
-                                           hipStream_t);
+                                           hipStream_t, double*);
 template hipError_t launch_density<float>(const DeviceView&, int, const TileItem*, int, const float*,
                                           const float*, const float*, double*, double*,
-                                          hipStream_t);
+                                          hipStream_t, float*);
+template hipError_t launch_pulay<double>(const DeviceView&, int, int, const double*, const double*,
+                                         const double*, const double*, double*, hipStream_t);
+template hipError_t launch_pulay<float>(const DeviceView&, int, int, const double*, const float*,
+                                        const float*, const double*, double*, hipStream_t);
 template hipError_t launch_hs<double>(const DeviceView&, const TileItem*, int, const double*,
                                       const double*, double*, hipStream_t);
 template hipError_t launch_hs<float>(const DeviceView&, const TileItem*, int, const float*,

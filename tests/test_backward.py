@@ -1,0 +1,115 @@
+"""The library's backward (dE/dP, dE/dv, dE/dR) against the oracle's derivatives and against
+central finite differences of the library's own energy (h = 1e-4 bohr, basis centres moved,
+grid, weights and v fixed), and the torch.autograd.Function built on it."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import GridOracle
+from paper_2208_12335_amd import AimsEnergy, AimsGrid
+from conftest import relerr
+
+pytestmark = pytest.mark.gpu
+
+
+def _backward(g, inst, dev, prec="fp64", gE=1.0, X=None):
+    P = torch.from_numpy(inst.P).to(dev).reshape(-1)
+    v = torch.from_numpy(inst.v).to(dev)
+    ge = torch.tensor([gE], dtype=torch.float64, device=dev)
+    dP, dv, dR = g.backward(P, v, ge, prec=prec, atom_xyz=X)
+    torch.cuda.synchronize()
+    nb = inst.n_basis
+    return dP.cpu().numpy().reshape(nb, nb), dv.cpu().numpy(), dR.cpu().numpy()
+
+
+def _energy(g, inst, dev, X, prec="fp64"):
+    P = torch.from_numpy(inst.P).to(dev).reshape(-1)
+    v = torch.from_numpy(inst.v).to(dev)
+    _, sums = g.update_density(P, v, prec=prec, atom_xyz=X)
+    s = sums.cpu().numpy()[0]
+    return s[1] + s[2]
+
+
+@pytest.mark.parametrize("case", ["c1", "cluster"])
+def test_backward_matches_oracle_fp64(gpu, case):
+    inst = synth.make_instance("c1") if case == "c1" else synth.make_instance("c2", n_atoms=8, box=7.0, seed=3)
+    print(f"[backward] {inst.name}: {inst.n_points} points, {inst.n_basis} functions", flush=True)
+    g = AimsGrid(inst, device=gpu.index)
+    dP, dv, dR = _backward(g, inst, gpu, gE=1.7)
+    ref = GridOracle(inst).gradient(inst.P, inst.v)
+    e = {"dP": relerr(dP, 1.7 * ref["dE_dP"]), "dv": relerr(dv, 1.7 * ref["dE_dv"]),
+         "dR": relerr(dR, 1.7 * ref["dE_dR"])}
+    print(f"[backward] {inst.name} fp64 vs oracle: " + ", ".join(f"{k} {v:.2e}" for k, v in e.items()), flush=True)
+    assert e["dP"] < 1e-10 and e["dv"] < 1e-10 and e["dR"] < 1e-9
+
+
+def _fd_worst(g, inst, dev, dR, atoms, h=1e-4):
+    worst = 0.0
+    for a in atoms:
+        for c in range(3):
+            Xp = inst.atom_xyz.copy()
+            Xp[a, c] += h
+            Xm = inst.atom_xyz.copy()
+            Xm[a, c] -= h
+            fd = (_energy(g, inst, dev, Xp) - _energy(g, inst, dev, Xm)) / (2 * h)
+            worst = max(worst, abs(fd - dR[a, c]))
+    return worst
+
+
+def test_backward_vs_finite_differences_triatomic(gpu, c1):
+    g = AimsGrid(c1, device=gpu.index)
+    _, _, dR = _backward(g, c1, gpu)
+    worst = _fd_worst(g, c1, gpu, dR, range(3))
+    print(f"[backward] c1: max |dE/dR - FD| = {worst:.2e} Ha/bohr", flush=True)
+    assert worst < 1e-6
+
+
+def test_backward_vs_finite_differences_cluster(gpu):
+    # the 128-atom differentiation workload's density (16 atoms in a 12.6 bohr box).  With a
+    # randomly signed P the energy is a sum of terms far larger than itself, so its FP64
+    # rounding noise (~1e-8 Ha here) divided by h, plus the O(h^2) truncation, bounds how well
+    # any FD can agree: the bar is 1e-6 + 1e-8 max|dE/dR| (the analytic gradient is held to
+    # the oracle's at 1e-9 relative in test_backward_matches_oracle_fp64).
+    inst = synth.make_instance("c2", n_atoms=16, box=12.6, seed=4)
+    g = AimsGrid(inst, device=gpu.index)
+    _, _, dR = _backward(g, inst, gpu)
+    rng = np.random.default_rng(7)
+    atoms = rng.choice(inst.n_atoms, 8, replace=False)
+    worst = _fd_worst(g, inst, gpu, dR, atoms)
+    bar = 1e-6 + 1e-8 * np.max(np.abs(dR))
+    print(f"[backward] 16-atom cluster, 8 atoms: max |dE/dR - FD| = {worst:.2e} Ha/bohr "
+          f"(bar {bar:.1e}, max |dE/dR| {np.max(np.abs(dR)):.1e})", flush=True)
+    assert worst < bar
+
+
+@pytest.mark.parametrize("prec,bound", [("fp32", 1e-4), ("bf16x3", 1e-2)])
+def test_backward_mixed_error_stated(gpu, prec, bound):
+    inst = synth.make_instance("c2", n_atoms=8, box=7.0, seed=3)
+    g = AimsGrid(inst, device=gpu.index)
+    dP64, dv64, dR64 = _backward(g, inst, gpu)
+    dP, dv, dR = _backward(g, inst, gpu, prec=prec)
+    e = {"dP": relerr(dP, dP64), "dv": relerr(dv, dv64), "dR": relerr(dR, dR64),
+         "dR_abs": float(np.max(np.abs(dR - dR64)))}
+    print(f"[backward] {prec} vs fp64: " + ", ".join(f"{k} {v:.2e}" for k, v in e.items()), flush=True)
+    assert e["dP"] < bound and e["dv"] < bound and e["dR"] < bound
+
+
+def test_autograd_function(gpu):
+    inst = synth.make_instance("c1")
+    g = AimsGrid(inst, device=gpu.index)
+    P = torch.from_numpy(inst.P).to(gpu).requires_grad_(True)
+    v = torch.from_numpy(inst.v).to(gpu).requires_grad_(True)
+    R = torch.from_numpy(inst.atom_xyz.copy()).to(gpu).requires_grad_(True)
+    E = AimsEnergy.apply(g, P, v, R, "fp64")
+    E.backward()
+    ref = GridOracle(inst).gradient(inst.P, inst.v)
+    assert abs(E.item() - ref["E"]) < 1e-10 * abs(ref["E"])
+    assert relerr(P.grad.cpu().numpy(), ref["dE_dP"]) < 1e-10
+    assert relerr(v.grad.cpu().numpy(), ref["dE_dv"]) < 1e-10
+    assert relerr(R.grad.cpu().numpy(), ref["dE_dR"]) < 1e-9
+    # second use of the same handle with moved centres (within the screening margin)
+    R2 = (R.detach() + 0.003).requires_grad_(True)
+    E2 = AimsEnergy.apply(g, P.detach(), v.detach(), R2, "fp64")
+    ref2 = GridOracle(inst.moved(R2.detach().cpu().numpy())).energy(inst.P, inst.v)
+    assert abs(E2.item() - ref2) < 1e-10 * abs(ref2)
