@@ -148,10 +148,17 @@ void aims_step_graph_destroy(aims_step_graph *graph);
  *   density_pblocks  a density work tile covers 64 basis rows and up to 32 * density_pblocks
  *                    points of one batch (2..5); a batch of n_p points is cut into
  *                    ceil(n_p / (32 density_pblocks)) equal tiles.
+ *   persistent       0: one workgroup per work tile (hardware dispatch order, XCD-interleaved);
+ *                    1: the tiled density and H/S kernels launch as many workgroups as fit on
+ *                    the device at once, and each pulls tiles from eight per-XCD work counters
+ *                    (one atomic per tile, stealing from the other XCDs' counters when its
+ *                    own is empty).  The counters are cleared by a kernel at the start of each
+ *                    call, so calls in this mode can be captured into a step graph.
  * Setting a value builds its work lists once (device allocation), later calls reuse them. */
 typedef struct {
   int32_t h_merge;
   int32_t density_pblocks;
+  int32_t persistent;
 } aims_tuning;
 aims_status aims_get_tuning(const aims_grid *g, aims_precision prec, aims_tuning *out);
 aims_status aims_set_tuning(aims_grid *g, aims_precision prec, const aims_tuning *t);

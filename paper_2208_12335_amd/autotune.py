@@ -1,0 +1,148 @@
+"""Autotuner of the library's execution parameters, timed on the live device.
+
+Three knobs decide how the batched work of one s.c.f. step maps onto the GPU (the batch
+integration scheme itself is fixed by the grid partition):
+
+* ``density_pblocks`` -- the point extent (32 x pblocks) of a density work tile;
+* ``h_merge``        -- how many bisection levels the H/S pass merges (bigger batches, fewer
+  FP64 scatter-adds into H, more flops);
+* ``persistent``     -- one workgroup per tile, or a resident grid pulling tiles from per-XCD
+  work counters.
+
+The density pass depends only on (pblocks, persistent) and the H pass only on (h_merge,
+persistent), so the tuner times the two passes separately and picks, per ``persistent`` value,
+the best of each, then the better ``persistent``.  Results are cached in a JSON file keyed by
+(device architecture, precision, workload bucket) so later handles of a similar workload skip
+the measurement.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import tempfile
+from typing import Callable, Dict, Iterable, Optional, Tuple
+
+DENSITY_PBLOCKS = (2, 3, 4, 5)
+H_MERGE = (0, 1, 2, 3)
+PERSISTENT = (0, 1)
+
+
+def default_cache_path() -> str:
+    return os.environ.get("AIMS_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "paper_2208_12335_amd",
+                                       "tuning.json"))
+
+
+def workload_key(arch: str, prec: str, n_sys: int, n_points: int, sum_np_nb2: float) -> str:
+    """Bucket of a workload: systems per handle (power of two), points (power of two) and the
+    mean batch basis size sqrt(sum n_p n_b^2 / n_points) (in steps of 32)."""
+    sys_b = 1 << max(0, math.ceil(math.log2(max(1, n_sys))))
+    pts_b = 1 << max(0, round(math.log2(max(1, n_points))))
+    nb_b = 32 * max(1, round(math.sqrt(sum_np_nb2 / max(1, n_points)) / 32))
+    return f"{arch}|{prec}|sys{sys_b}|pts{pts_b}|nb{nb_b}"
+
+
+def search(cost: Callable[[str, dict], float],
+           density_pblocks: Iterable[int] = DENSITY_PBLOCKS,
+           h_merge: Iterable[int] = H_MERGE,
+           persistent: Iterable[int] = PERSISTENT) -> Tuple[dict, Dict[str, float]]:
+    """Pick the tuning that minimises density time + H time.
+
+    ``cost(kind, cfg)`` returns the time of pass ``kind`` ("density" or "h") under ``cfg``
+    (a dict with the three knobs).  Returns (best cfg, {candidate label: ms})."""
+    log: Dict[str, float] = {}
+    best, best_t = None, math.inf
+    for p in persistent:
+        bd, td = None, math.inf
+        for pb in density_pblocks:
+            t = float(cost("density", {"density_pblocks": pb, "persistent": p}))
+            log[f"density pblocks={pb} persistent={p}"] = t
+            if t < td:
+                bd, td = pb, t
+        bh, th = None, math.inf
+        for m in h_merge:
+            t = float(cost("h", {"h_merge": m, "persistent": p}))
+            log[f"h merge={m} persistent={p}"] = t
+            if t < th:
+                bh, th = m, t
+        if bd is not None and bh is not None and td + th < best_t:
+            best = {"h_merge": bh, "density_pblocks": bd, "persistent": p}
+            best_t = td + th
+    if best is None:
+        raise ValueError("empty candidate set")
+    return best, log
+
+
+def load_cache(path: str) -> dict:
+    try:
+        with open(path) as f:
+            data = json.load(f)
+        return data if isinstance(data, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def store_cache(path: str, key: str, entry: dict) -> None:
+    data = load_cache(path)
+    data[key] = entry
+    d = os.path.dirname(path) or "."
+    os.makedirs(d, exist_ok=True)
+    fd, tmp = tempfile.mkstemp(dir=d, prefix=".tuning.", suffix=".json")
+    with os.fdopen(fd, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def autotune(grid, P, v, prec: str = "fp64", *, reps: int = 3, cache: Optional[str] = None,
+             force: bool = False, density_pblocks: Iterable[int] = DENSITY_PBLOCKS,
+             h_merge: Iterable[int] = H_MERGE, persistent: Iterable[int] = PERSISTENT) -> dict:
+    """Time the candidates on ``grid``'s device with inputs P, v (device tensors), apply the
+    best tuning for ``prec`` and return {tuning..., "source": "cache"|"measured", "key": ...,
+    "ms": {...}}.  ``cache=""`` disables the cache file."""
+    import torch
+
+    props = torch.cuda.get_device_properties(grid.device)
+    arch = getattr(props, "gcnArchName", props.name).split(":")[0]
+    ws = grid.work_stats()
+    key = workload_key(arch, prec, grid.n_sys, grid.n_points, ws["sum_np_nb2"])
+    path = default_cache_path() if cache is None else cache
+    if path and not force:
+        hit = load_cache(path).get(key)
+        if hit and all(k in hit for k in ("h_merge", "density_pblocks", "persistent")):
+            grid.set_tuning(h_merge=hit["h_merge"], density_pblocks=hit["density_pblocks"],
+                            persistent=hit["persistent"], prec=prec)
+            return dict(hit, source="cache", key=key)
+
+    n = torch.empty(grid.n_points, dtype=torch.float64, device=grid.device)
+    sums = torch.empty(grid.n_sys, 3, dtype=torch.float64, device=grid.device)
+    H = torch.empty(grid.mat_elems, dtype=torch.float64, device=grid.device)
+    cur = grid.get_tuning(prec)
+    stream = grid.stream
+
+    def run(kind):
+        if kind == "density":
+            grid.update_density(P, v, prec=prec, n_out=n, sums_out=sums)
+        else:
+            grid.integrate_h(v, prec=prec, H_out=H)
+
+    def cost(kind, cfg):
+        grid.set_tuning(h_merge=cfg.get("h_merge", cur["h_merge"]),
+                        density_pblocks=cfg.get("density_pblocks", cur["density_pblocks"]),
+                        persistent=cfg["persistent"], prec=prec)
+        run(kind)                                   # warm (first use builds the work lists)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            run(kind)
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    best, log = search(cost, density_pblocks, h_merge, persistent)
+    grid.set_tuning(prec=prec, **best)
+    entry = dict(best, ms=log)
+    if path:
+        store_cache(path, key, entry)
+    return dict(entry, source="measured", key=key)

@@ -195,6 +195,9 @@ struct aims_grid {
   std::vector<std::unique_ptr<BatchSet>> hsets;  // H partitions by merge level (built on demand)
   int h_merge[3] = {1, 2, 2};                 // per precision
   int d_pblocks[3] = {2, 5, 5};               // per precision: density point-tile cap
+  int persistent[3] = {0, 0, 0};              // per precision: persistent tile launches
+  int* d_queue = nullptr;                     // 8 work counters per tiled launch of one call
+  size_t queue_cap = 0;                       // counters allocated
   int nblk_finish = 64;
 
   // profiling
@@ -478,6 +481,12 @@ ItemList& items_for(aims_grid* g, BatchSet& bs, int pblocks) {
   }
   if ((int64_t)L->items.size() > INT32_MAX) fail(AIMS_ERR_UNSUPPORTED, "too many tiles");
   L->d_items = g->upload(L->items);
+  size_t launches = 0;
+  for (const auto& r : L->runs) launches += r.size();
+  if (8 * launches > g->queue_cap) {
+    g->d_queue = (int*)g->alloc(8 * launches * sizeof(int));
+    g->queue_cap = 8 * launches;
+  }
   bs.lists.push_back(std::move(L));
   return *bs.lists.back();
 }
@@ -603,6 +612,7 @@ aims_grid* build(const aims_system* sys, int n_sys, int device, void* stream) {
 
   // ---- upload of the shared state, then the density partition ---------------------------
   hipchk(hipSetDevice(device), "hipSetDevice");
+  hipchk(prepare_launch_configs(), "occupancy query");
   DeviceView& dv = g->common;
   dv.systems = g->upload(g->systems);
   dv.pts = g->upload(g->pts_sorted);
@@ -712,6 +722,31 @@ void prof_collect(aims_grid* g) {
   g->prof_pending.clear();
 }
 
+// Counters of the persistent tile launches of one call: all of them are cleared by one small
+// kernel at the start of the call (no memset node, so the call may be captured into a graph),
+// then each tiled launch takes the next 8.
+struct QueueSeq {
+  int* base = nullptr;
+  size_t k = 0, cap = 0;
+  QueueSeq(aims_grid* g, const ItemList& L, aims_precision prec) {
+    if (!g->persistent[prec]) return;
+    size_t launches = 0;
+    for (const auto& r : L.runs) launches += r.size();
+    if (8 * launches > g->queue_cap) fail(AIMS_ERR_ARG, "work counters not allocated");
+    base = g->d_queue;
+    cap = 8 * launches;
+    hipchk(launch_zero_int(base, (int)cap, g->stream), "clear work counters");
+  }
+  Queue next() {
+    Queue q;
+    if (!base) return q;
+    if (k + 8 > cap) fail(AIMS_ERR_ARG, "work counter overflow");
+    q.counters = base + k;
+    k += 8;
+    return q;
+  }
+};
+
 // Density update with basis values of precision T (double / float) on the MFMA type of T,
 // or, with bf16x3, FP32 basis values split into bf16 hi/lo pairs.
 template <typename T>
@@ -722,6 +757,7 @@ void run_density(aims_grid* g, aims_precision prec, const T* P, const double* v,
   const ItemList& L = items_for(g, bs, g->d_pblocks[prec]);
   hipchk(launch_fill(g->d_n_sorted, (size_t)g->n_points, 0.0, st), "fill n");
   hipchk(launch_fill(g->d_et_batch, bs.batches.size(), 0.0, st), "fill E_T");
+  QueueSeq qs(g, L, prec);
   for (size_t gi = 0; gi < bs.groups.size(); ++gi) {
     const auto& gr = bs.groups[gi];
     const int nbt = gr.b1 - gr.b0;
@@ -742,12 +778,14 @@ void run_density(aims_grid* g, aims_precision prec, const T* P, const double* v,
       if (prec == AIMS_BF16X3) {
         timed(g, kProfDensity, work, "density", [&] {
           return launch_density_bf16(bs.dv, run.nbn, L.d_items + run.i0, nit, (const float*)P,
-                                     g->d_slab1, g->d_slab2, g->d_n_sorted, g->d_et_batch, st);
+                                     g->d_slab1, g->d_slab2, g->d_n_sorted, g->d_et_batch, st,
+                                     nullptr, qs.next());
         });
       } else {
         timed(g, kProfDensity, work, "density", [&] {
           return launch_density<T>(bs.dv, run.nbn, L.d_items + run.i0, nit, P, (const T*)g->d_slab1,
-                                   (const T*)g->d_slab2, g->d_n_sorted, g->d_et_batch, st);
+                                   (const T*)g->d_slab2, g->d_n_sorted, g->d_et_batch, st, nullptr,
+                                   qs.next());
         });
       }
     }
@@ -764,6 +802,7 @@ void run_hs(aims_grid* g, aims_precision prec, int mode, const double* v, double
   BatchSet& bs = hset(g, g->h_merge[prec]);
   const ItemList& L = items_for(g, bs, 0);
   hipchk(launch_fill(out, (size_t)g->mat_total, 0.0, st), "fill H");
+  QueueSeq qs(g, L, prec);
   for (size_t gi = 0; gi < bs.groups.size(); ++gi) {
     const auto& gr = bs.groups[gi];
     const int nbt = gr.b1 - gr.b0;
@@ -774,7 +813,7 @@ void run_hs(aims_grid* g, aims_precision prec, int mode, const double* v, double
           return launch_phi_eval_bf16(bs.dv, gr.b0, nbt, mode, v, g->d_slab1, g->d_slab2, st);
         });
         timed(g, kProfHS, gr.flops, "hs", [&] {
-          return launch_hs_bf16(bs.dv, L.d_items + run.i0, nit, g->d_slab1, g->d_slab2, out, st);
+          return launch_hs_bf16(bs.dv, L.d_items + run.i0, nit, g->d_slab1, g->d_slab2, out, st, qs.next());
         });
       } else {
         T* s1 = (T*)g->d_slab1;
@@ -783,7 +822,7 @@ void run_hs(aims_grid* g, aims_precision prec, int mode, const double* v, double
           return launch_phi_eval<T>(bs.dv, gr.b0, nbt, mode, v, s1, s2, st);
         });
         timed(g, kProfHS, gr.flops, "hs", [&] {
-          return launch_hs<T>(bs.dv, L.d_items + run.i0, nit, s1, s2, out, st);
+          return launch_hs<T>(bs.dv, L.d_items + run.i0, nit, s1, s2, out, st, qs.next());
         });
       }
     }
@@ -1058,6 +1097,7 @@ aims_status aims_get_tuning(const aims_grid* g, aims_precision prec, aims_tuning
   memset(out, 0, sizeof(*out));
   out->h_merge = g->h_merge[prec];
   out->density_pblocks = g->d_pblocks[prec];
+  out->persistent = g->persistent[prec];
   return AIMS_OK;
 }
 
@@ -1066,9 +1106,11 @@ aims_status aims_set_tuning(aims_grid* g, aims_precision prec, const aims_tuning
     if (!t || prec < AIMS_FP64 || prec > AIMS_BF16X3) fail(AIMS_ERR_ARG, "bad tuning arguments");
     if (t->h_merge < 0 || t->h_merge > 4) fail(AIMS_ERR_ARG, "h_merge must be in 0..4");
     if (t->density_pblocks < 2 || t->density_pblocks > 5) fail(AIMS_ERR_ARG, "density_pblocks must be in 2..5");
+    if (t->persistent != 0 && t->persistent != 1) fail(AIMS_ERR_ARG, "persistent must be 0 or 1");
     hset(g, t->h_merge);
     items_for(g, g->dens, t->density_pblocks);
     g->h_merge[prec] = t->h_merge;
+    g->persistent[prec] = t->persistent;
     g->d_pblocks[prec] = t->density_pblocks;
   });
 }

@@ -9,6 +9,13 @@ namespace aims {
 
 enum { kModeDensity = 0, kModeH = 1, kModeS = 2 };
 
+// Persistent launch: counters[8] (zero at launch) and the number of resident workgroups; a
+// null counters pointer selects one workgroup per work item.
+struct Queue {
+  int* counters = nullptr;
+  int workgroups = 0;
+};
+
 // Device pointers and scalars of one handle, passed by value to the launchers.
 struct DeviceView {
   const BatchDesc* batches;
@@ -44,10 +51,10 @@ hipError_t launch_phi_eval_bf16(const DeviceView& dv, int b0, int nbatch, int mo
 template <typename T>
 hipError_t launch_density(const DeviceView& dv, int nbn, const TileItem* items, int n_items, const T* P,
                           const T* slab1, const T* slab2, double* n_sorted, double* et_batch,
-                          hipStream_t st, T* xout = nullptr);
+                          hipStream_t st, T* xout = nullptr, Queue q = Queue());
 hipError_t launch_density_bf16(const DeviceView& dv, int nbn, const TileItem* items, int n_items,
                                const float* P, const void* slab1, const void* slab2, double* n_sorted,
-                               double* et_batch, hipStream_t st, float* xout = nullptr);
+                               double* et_batch, hipStream_t st, float* xout = nullptr, Queue q = Queue());
 template <typename T>
 hipError_t launch_pulay(const DeviceView& dv, int b0, int nbatch, const double* v, const T* X,
                         const T* Y, const double* gE, double* dE_dR, hipStream_t st);
@@ -56,9 +63,11 @@ hipError_t launch_dv(const DeviceView& dv, double* dE_dv, const double* n_sorted
                      const double* gE, hipStream_t st);
 template <typename T>
 hipError_t launch_hs(const DeviceView& dv, const TileItem* items, int n_items, const T* slab1,
-                     const T* slab2, double* out, hipStream_t st);
+                     const T* slab2, double* out, hipStream_t st, Queue q = Queue());
 hipError_t launch_hs_bf16(const DeviceView& dv, const TileItem* items, int n_items, const void* slab1,
-                          const void* slab2, double* out, hipStream_t st);
+                          const void* slab2, double* out, hipStream_t st, Queue q = Queue());
+hipError_t launch_zero_int(int* x, int n, hipStream_t st);
+hipError_t prepare_launch_configs();
 hipError_t launch_density_finish(const DeviceView& dv, const double* n_sorted, const double* v,
                                  double* n_out, double* part, int nblk, const double* et_batch,
                                  double* sums_out, hipStream_t st);

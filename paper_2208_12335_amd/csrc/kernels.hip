@@ -15,6 +15,9 @@
 // that crosses batches (n, H, S, N, E) is accumulated in FP64.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <mutex>
+#include <unordered_map>
 #include <type_traits>
 
 #include "aims_internal.h"
@@ -196,6 +199,37 @@ __device__ __forceinline__ int xcd_item(int g, int n) {
   return (g & 7) * per + (g >> 3);
 }
 
+
+// Work distribution.  Grid mode (queue == NULL): one workgroup per item, XCD-aware order.
+// Persistent mode: a fixed grid of workgroups drains eight per-XCD queues of contiguous
+// (spatially ordered) items; workgroup g starts on queue g % 8 -- the queue of its own XCD -- and
+// steals from the other queues once that is empty.  queue[8] must be zero at launch.
+template <typename F>
+__device__ __forceinline__ void run_items(int n_items, int* __restrict__ queue, F&& tile) {
+  if (!queue) {
+    const int item = xcd_item(blockIdx.x, n_items);
+    if (item < n_items) tile(item);
+    return;
+  }
+  __shared__ int s_next;
+  const int per = (n_items + 7) / 8;
+  const int x0 = blockIdx.x & 7;
+  for (int q = 0; q < 8;) {
+    const int x = (x0 + q) & 7;
+    if (threadIdx.x == 0) s_next = atomicAdd(queue + x, 1);
+    __syncthreads();
+    const int k = s_next;
+    __syncthreads();
+    const int item = x * per + k;
+    if (k >= per || item >= n_items) {
+      ++q;
+      continue;
+    }
+    tile(item);
+    __syncthreads();
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void load4(const T* __restrict__ p, T (&v)[4]);
 template <>
@@ -243,8 +277,8 @@ __device__ __forceinline__ void density_epilogue(double (&sn)[NBN], double se, i
 // Density, FP64 / FP32: X^T[j][p] = sum_i P_b[j][i] Phi^T[i][p] for 64 basis rows j and
 // 32 * NBN points p of one batch.
 template <typename T, int NBN>
-__global__ void __launch_bounds__(256)
-density_kernel(const TileItem* __restrict__ items, int n_items, const BatchDesc* __restrict__ batches,
+__device__ __forceinline__ void
+density_tile(int item, const TileItem* __restrict__ items, int n_items, const BatchDesc* __restrict__ batches,
                const SystemDesc* __restrict__ systems, const double4* __restrict__ pts,
                const int32_t* __restrict__ batch_cols, const T* __restrict__ Pmat,
                const T* __restrict__ slab1, const T* __restrict__ slab2,
@@ -255,8 +289,6 @@ density_kernel(const TileItem* __restrict__ items, int n_items, const BatchDesc*
   constexpr int BW = PT / 4;            // 4-element units per B row
   constexpr int BU = kKC * BW;          // units of the B tile
   constexpr int BQ = (BU + 255) / 256;  // units per thread
-  const int item = xcd_item(blockIdx.x, n_items);
-  if (item >= n_items) return;
   const TileItem it = items[item];
   const BatchDesc d = batches[it.batch];
   const SystemDesc sys = systems[d.sys];
@@ -419,15 +451,28 @@ density_kernel(const TileItem* __restrict__ items, int n_items, const BatchDesc*
                         et_batch, it.batch);
 }
 
+template <typename T, int NBN>
+__global__ void __launch_bounds__(256)
+density_kernel(const TileItem* __restrict__ items, int n_items, const BatchDesc* __restrict__ batches,
+               const SystemDesc* __restrict__ systems, const double4* __restrict__ pts,
+               const int32_t* __restrict__ batch_cols, const T* __restrict__ Pmat,
+               const T* __restrict__ slab1, const T* __restrict__ slab2,
+               double* __restrict__ n_sorted, double* __restrict__ et_batch,
+               T* __restrict__ xout,
+    int* __restrict__ queue) {
+  run_items(n_items, queue, [&](int item) {
+    density_tile<T, NBN>(item, items, n_items, batches, systems, pts, batch_cols, Pmat, slab1, slab2, n_sorted, et_batch, xout);
+  });
+}
+
+
 // H / S, FP64 / FP32: C[i][j] = sum_p slab1[i][p] slab2[j][p] over the batch's points, then a
 // FP64 scatter-add into the dense output.
 template <typename T>
-__global__ void __launch_bounds__(256)
-hs_kernel(const TileItem* __restrict__ items, int n_items, const BatchDesc* __restrict__ batches,
+__device__ __forceinline__ void
+hs_tile(int item, const TileItem* __restrict__ items, int n_items, const BatchDesc* __restrict__ batches,
           const SystemDesc* __restrict__ systems, const int32_t* __restrict__ batch_cols,
           const T* __restrict__ slab1, const T* __restrict__ slab2, double* __restrict__ out) {
-  const int item = xcd_item(blockIdx.x, n_items);
-  if (item >= n_items) return;
   const TileItem it = items[item];
   const BatchDesc d = batches[it.batch];
   const SystemDesc sys = systems[d.sys];
@@ -522,6 +567,18 @@ hs_kernel(const TileItem* __restrict__ items, int n_items, const BatchDesc* __re
   }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256)
+hs_kernel(const TileItem* __restrict__ items, int n_items, const BatchDesc* __restrict__ batches,
+          const SystemDesc* __restrict__ systems, const int32_t* __restrict__ batch_cols,
+          const T* __restrict__ slab1, const T* __restrict__ slab2, double* __restrict__ out,
+    int* __restrict__ queue) {
+  run_items(n_items, queue, [&](int item) {
+    hs_tile<T>(item, items, n_items, batches, systems, batch_cols, slab1, slab2, out);
+  });
+}
+
+
 // ------------------------------------------------------------------------------------------
 // BF16x3 kernels: a_hi b_hi + a_hi b_lo + a_lo b_hi on v_mfma_f32_16x16x32_bf16 (FP32
 // accumulation), K chunks of 32, same 64-row tiles.
@@ -540,8 +597,8 @@ __device__ __forceinline__ float bf_pair(const bf16_t* p, int lo_off) {
 // while staged; Phi comes from the function-major bf16 slab and is transposed into
 // K-contiguous LDS rows while staged.
 template <int NBN>
-__global__ void __launch_bounds__(256)
-density_kernel_bf16(const TileItem* __restrict__ items, int n_items, const BatchDesc* __restrict__ batches,
+__device__ __forceinline__ void
+density_tile_bf16(int item, const TileItem* __restrict__ items, int n_items, const BatchDesc* __restrict__ batches,
                     const SystemDesc* __restrict__ systems, const double4* __restrict__ pts,
                     const int32_t* __restrict__ batch_cols, const float* __restrict__ Pmat,
                     const bf16_t* __restrict__ slab1, const bf16_t* __restrict__ slab2,
@@ -551,8 +608,6 @@ density_kernel_bf16(const TileItem* __restrict__ items, int n_items, const Batch
   constexpr int BW = PT / 8;            // 8-point units per slab row
   constexpr int BU = kKB * BW;          // units of the B tile
   constexpr int BQ = (BU + 255) / 256;
-  const int item = xcd_item(blockIdx.x, n_items);
-  if (item >= n_items) return;
   const TileItem it = items[item];
   const BatchDesc d = batches[it.batch];
   const SystemDesc sys = systems[d.sys];
@@ -728,14 +783,27 @@ density_kernel_bf16(const TileItem* __restrict__ items, int n_items, const Batch
                         et_batch, it.batch);
 }
 
-// H/S: C[i][j] = sum_p slab1[i][p] slab2[j][p] from function-major bf16 slabs.
+template <int NBN>
 __global__ void __launch_bounds__(256)
-hs_kernel_bf16(const TileItem* __restrict__ items, int n_items, const BatchDesc* __restrict__ batches,
+density_kernel_bf16(const TileItem* __restrict__ items, int n_items, const BatchDesc* __restrict__ batches,
+                    const SystemDesc* __restrict__ systems, const double4* __restrict__ pts,
+                    const int32_t* __restrict__ batch_cols, const float* __restrict__ Pmat,
+                    const bf16_t* __restrict__ slab1, const bf16_t* __restrict__ slab2,
+                    double* __restrict__ n_sorted, double* __restrict__ et_batch,
+                    float* __restrict__ xout,
+    int* __restrict__ queue) {
+  run_items(n_items, queue, [&](int item) {
+    density_tile_bf16<NBN>(item, items, n_items, batches, systems, pts, batch_cols, Pmat, slab1, slab2, n_sorted, et_batch, xout);
+  });
+}
+
+
+// H/S: C[i][j] = sum_p slab1[i][p] slab2[j][p] from function-major bf16 slabs.
+__device__ __forceinline__ void
+hs_tile_bf16(int item, const TileItem* __restrict__ items, int n_items, const BatchDesc* __restrict__ batches,
                const SystemDesc* __restrict__ systems, const int32_t* __restrict__ batch_cols,
                const bf16_t* __restrict__ slab1, const bf16_t* __restrict__ slab2,
                double* __restrict__ out) {
-  const int item = xcd_item(blockIdx.x, n_items);
-  if (item >= n_items) return;
   const TileItem it = items[item];
   const BatchDesc d = batches[it.batch];
   const SystemDesc sys = systems[d.sys];
@@ -827,6 +895,18 @@ hs_kernel_bf16(const TileItem* __restrict__ items, int n_items, const BatchDesc*
       }
   }
 }
+
+__global__ void __launch_bounds__(256)
+hs_kernel_bf16(const TileItem* __restrict__ items, int n_items, const BatchDesc* __restrict__ batches,
+               const SystemDesc* __restrict__ systems, const int32_t* __restrict__ batch_cols,
+               const bf16_t* __restrict__ slab1, const bf16_t* __restrict__ slab2,
+               double* __restrict__ out,
+    int* __restrict__ queue) {
+  run_items(n_items, queue, [&](int item) {
+    hs_tile_bf16(item, items, n_items, batches, systems, batch_cols, slab1, slab2, out);
+  });
+}
+
 
 // ------------------------------------------------------------------------------------------
 // Backward: Pulay-type forces from basis gradients.  For every (point, relevant atom) pair the
@@ -1029,6 +1109,43 @@ static inline int grid_for(size_t n, int per) {
 
 static inline int item_grid(int n_items) { return ((n_items + 7) / 8) * 8; }
 
+// Workgroups of a 256-thread kernel that are resident on the current device at once
+// (occupancy x compute units), cached per kernel.
+static int resident_workgroups(const void* fn) {
+  static std::mutex mu;
+  static std::unordered_map<const void*, int> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(fn);
+  if (it != cache.end()) return it->second;
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, 256, 0) != hipSuccess)
+    return 0;
+  const int n = std::max(1, per) * std::max(1, cus);
+  cache[fn] = n;
+  return n;
+}
+
+// Grid of a tiled launch: one workgroup per item, or (persistent) the resident workgroup
+// count rounded down to a multiple of the 8 XCDs.
+static inline int tile_grid(int n_items, const Queue& q, const void* fn) {
+  const int g = item_grid(n_items);
+  if (!q.counters) return g;
+  const int res = q.workgroups > 0 ? q.workgroups : resident_workgroups(fn);
+  return std::min(g, std::max(8, res / 8 * 8));
+}
+
+__global__ void zero_int_kernel(int* __restrict__ x, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) x[i] = 0;
+}
+
+hipError_t launch_zero_int(int* x, int n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_int_kernel, dim3(std::min(256, (n + 255) / 256)), dim3(256), 0, st, x, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill(double* x, size_t n, double val, hipStream_t st) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n, 256 * 4)), dim3(256), 0, st, x, n, val);
@@ -1066,22 +1183,22 @@ hipError_t launch_phi_eval_bf16(const DeviceView& dv, int b0, int nbatch, int mo
 template <typename T, int NBN>
 static void density_launch_nbn(const DeviceView& dv, const TileItem* items, int n_items, const T* P,
                                const T* slab1, const T* slab2, double* n_sorted, double* et_batch,
-                               T* xout, hipStream_t st) {
-  hipLaunchKernelGGL((density_kernel<T, NBN>), dim3(item_grid(n_items)), dim3(256), 0, st, items,
-                     n_items, dv.batches, dv.systems, dv.pts, dv.batch_cols, P, slab1, slab2,
-                     n_sorted, et_batch, xout);
+                               T* xout, const Queue& q, hipStream_t st) {
+  hipLaunchKernelGGL((density_kernel<T, NBN>), dim3(tile_grid(n_items, q, (const void*)density_kernel<T, NBN>)), dim3(256), 0,
+                     st, items, n_items, dv.batches, dv.systems, dv.pts, dv.batch_cols, P, slab1, slab2,
+                     n_sorted, et_batch, xout, q.counters);
 }
 
 template <typename T>
 hipError_t launch_density(const DeviceView& dv, int nbn, const TileItem* items, int n_items, const T* P,
                           const T* slab1, const T* slab2, double* n_sorted, double* et_batch,
-                          hipStream_t st, T* xout) {
+                          hipStream_t st, T* xout, Queue q) {
   if (n_items == 0) return hipSuccess;
   switch (nbn) {
-    case 2: density_launch_nbn<T, 2>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, st); break;
-    case 3: density_launch_nbn<T, 3>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, st); break;
-    case 4: density_launch_nbn<T, 4>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, st); break;
-    case 5: density_launch_nbn<T, 5>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, st); break;
+    case 2: density_launch_nbn<T, 2>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, q, st); break;
+    case 3: density_launch_nbn<T, 3>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, q, st); break;
+    case 4: density_launch_nbn<T, 4>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, q, st); break;
+    case 5: density_launch_nbn<T, 5>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, q, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1089,31 +1206,32 @@ hipError_t launch_density(const DeviceView& dv, int nbn, const TileItem* items, 
 
 template <typename T>
 hipError_t launch_hs(const DeviceView& dv, const TileItem* items, int n_items, const T* slab1,
-                     const T* slab2, double* out, hipStream_t st) {
+                     const T* slab2, double* out, hipStream_t st, Queue q) {
   if (n_items == 0) return hipSuccess;
-  hipLaunchKernelGGL(hs_kernel<T>, dim3(item_grid(n_items)), dim3(256), 0, st, items, n_items,
-                     dv.batches, dv.systems, dv.batch_cols, slab1, slab2, out);
+  hipLaunchKernelGGL(hs_kernel<T>, dim3(tile_grid(n_items, q, (const void*)hs_kernel<T>)), dim3(256), 0, st, items, n_items,
+                     dv.batches, dv.systems, dv.batch_cols, slab1, slab2, out, q.counters);
   return hipGetLastError();
 }
 
 template <int NBN>
 static void density_bf16_launch_nbn(const DeviceView& dv, const TileItem* items, int n_items,
                                     const float* P, const void* slab1, const void* slab2,
-                                    double* n_sorted, double* et_batch, float* xout, hipStream_t st) {
-  hipLaunchKernelGGL((density_kernel_bf16<NBN>), dim3(item_grid(n_items)), dim3(256), 0, st, items,
+                                    double* n_sorted, double* et_batch, float* xout, const Queue& q,
+                                    hipStream_t st) {
+  hipLaunchKernelGGL((density_kernel_bf16<NBN>), dim3(tile_grid(n_items, q, (const void*)density_kernel_bf16<NBN>)), dim3(256), 0, st, items,
                      n_items, dv.batches, dv.systems, dv.pts, dv.batch_cols, P, (const bf16_t*)slab1,
-                     (const bf16_t*)slab2, n_sorted, et_batch, xout);
+                     (const bf16_t*)slab2, n_sorted, et_batch, xout, q.counters);
 }
 
 hipError_t launch_density_bf16(const DeviceView& dv, int nbn, const TileItem* items, int n_items,
                                const float* P, const void* slab1, const void* slab2, double* n_sorted,
-                               double* et_batch, hipStream_t st, float* xout) {
+                               double* et_batch, hipStream_t st, float* xout, Queue q) {
   if (n_items == 0) return hipSuccess;
   switch (nbn) {
-    case 2: density_bf16_launch_nbn<2>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, st); break;
-    case 3: density_bf16_launch_nbn<3>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, st); break;
-    case 4: density_bf16_launch_nbn<4>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, st); break;
-    case 5: density_bf16_launch_nbn<5>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, st); break;
+    case 2: density_bf16_launch_nbn<2>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, q, st); break;
+    case 3: density_bf16_launch_nbn<3>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, q, st); break;
+    case 4: density_bf16_launch_nbn<4>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, q, st); break;
+    case 5: density_bf16_launch_nbn<5>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, q, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1145,11 +1263,11 @@ hipError_t launch_dv(const DeviceView& dv, double* dE_dv, const double* n_sorted
 }
 
 hipError_t launch_hs_bf16(const DeviceView& dv, const TileItem* items, int n_items, const void* slab1,
-                          const void* slab2, double* out, hipStream_t st) {
+                          const void* slab2, double* out, hipStream_t st, Queue q) {
   if (n_items == 0) return hipSuccess;
-  hipLaunchKernelGGL(hs_kernel_bf16, dim3(item_grid(n_items)), dim3(256), 0, st, items, n_items,
+  hipLaunchKernelGGL(hs_kernel_bf16, dim3(tile_grid(n_items, q, (const void*)hs_kernel_bf16)), dim3(256), 0, st, items, n_items,
                      dv.batches, dv.systems, dv.batch_cols, (const bf16_t*)slab1, (const bf16_t*)slab2,
-                     out);
+                     out, q.counters);
   return hipGetLastError();
 }
 
@@ -1171,17 +1289,34 @@ template hipError_t launch_phi_eval<float>(const DeviceView&, int, int, int, con
                                            float*, float*, hipStream_t);
 template hipError_t launch_density<double>(const DeviceView&, int, const TileItem*, int, const double*,
                                            const double*, const double*, double*, double*,
-                                           hipStream_t, double*);
+                                           hipStream_t, double*, Queue);
 template hipError_t launch_density<float>(const DeviceView&, int, const TileItem*, int, const float*,
                                           const float*, const float*, double*, double*,
-                                          hipStream_t, float*);
+                                          hipStream_t, float*, Queue);
 template hipError_t launch_pulay<double>(const DeviceView&, int, int, const double*, const double*,
                                          const double*, const double*, double*, hipStream_t);
 template hipError_t launch_pulay<float>(const DeviceView&, int, int, const double*, const float*,
                                         const float*, const double*, double*, hipStream_t);
 template hipError_t launch_hs<double>(const DeviceView&, const TileItem*, int, const double*,
-                                      const double*, double*, hipStream_t);
+                                      const double*, double*, hipStream_t, Queue);
 template hipError_t launch_hs<float>(const DeviceView&, const TileItem*, int, const float*,
-                                     const float*, double*, hipStream_t);
+                                     const float*, double*, hipStream_t, Queue);
+
+// Resident-workgroup counts of every tiled kernel, queried once on the current device
+// (outside any stream capture, so that later persistent launches only read the cache).
+hipError_t prepare_launch_configs() {
+  const void* fns[] = {
+      (const void*)density_kernel<double, 2>, (const void*)density_kernel<double, 3>,
+      (const void*)density_kernel<double, 4>, (const void*)density_kernel<double, 5>,
+      (const void*)density_kernel<float, 2>,  (const void*)density_kernel<float, 3>,
+      (const void*)density_kernel<float, 4>,  (const void*)density_kernel<float, 5>,
+      (const void*)density_kernel_bf16<2>,    (const void*)density_kernel_bf16<3>,
+      (const void*)density_kernel_bf16<4>,    (const void*)density_kernel_bf16<5>,
+      (const void*)hs_kernel<double>,         (const void*)hs_kernel<float>,
+      (const void*)hs_kernel_bf16};
+  for (const void* f : fns)
+    if (resident_workgroups(f) <= 0) return hipErrorInvalidDeviceFunction;
+  return hipSuccess;
+}
 
 }  // namespace aims

@@ -1,0 +1,60 @@
+"""Host logic of the autotuner: candidate search, workload buckets and the JSON cache."""
+import json
+
+import pytest
+
+from paper_2208_12335_amd.autotune import load_cache, search, store_cache, workload_key
+
+
+def test_search_picks_min_of_sum_per_persistent_flag():
+    # density favours persistent=1 slightly, H favours persistent=0 strongly
+    d = {(2, 0): 5.0, (3, 0): 4.0, (4, 0): 4.5, (5, 0): 6.0,
+         (2, 1): 3.9, (3, 1): 3.8, (4, 1): 4.2, (5, 1): 5.0}
+    h = {(0, 0): 9.0, (1, 0): 6.0, (2, 0): 7.0, (3, 0): 8.0,
+         (0, 1): 9.5, (1, 1): 8.0, (2, 1): 7.5, (3, 1): 8.5}
+    calls = []
+
+    def cost(kind, cfg):
+        calls.append((kind, dict(cfg)))
+        if kind == "density":
+            return d[(cfg["density_pblocks"], cfg["persistent"])]
+        return h[(cfg["h_merge"], cfg["persistent"])]
+
+    best, log = search(cost)
+    # persistent=0: 4.0 + 6.0 = 10.0 ; persistent=1: 3.8 + 7.5 = 11.3
+    assert best == {"h_merge": 1, "density_pblocks": 3, "persistent": 0}
+    assert len(calls) == 16 and len(log) == 16
+    # the density pass is never timed with an h_merge knob and vice versa
+    assert all("h_merge" not in c for k, c in calls if k == "density")
+    assert all("density_pblocks" not in c for k, c in calls if k == "h")
+
+
+def test_search_restricted_candidates_and_empty():
+    best, _ = search(lambda k, c: 1.0, density_pblocks=[4], h_merge=[2], persistent=[1])
+    assert best == {"h_merge": 2, "density_pblocks": 4, "persistent": 1}
+    with pytest.raises(ValueError):
+        search(lambda k, c: 1.0, persistent=[])
+
+
+def test_workload_key_buckets():
+    k1 = workload_key("gfx950", "fp64", 1, 1_122_621, 1_122_621 * 410.0 ** 2)
+    k2 = workload_key("gfx950", "fp64", 1, 1_100_000, 1_100_000 * 405.0 ** 2)
+    assert k1 == k2 == "gfx950|fp64|sys1|pts1048576|nb416"
+    assert workload_key("gfx950", "fp32", 1, 1_122_621, 1.0) != k1
+    assert "sys256" in workload_key("gfx950", "fp64", 256, 10_000_000, 1e12)
+    assert "sys256" in workload_key("gfx950", "fp64", 200, 10_000_000, 1e12)
+
+
+def test_cache_roundtrip(tmp_path):
+    p = str(tmp_path / "sub" / "tuning.json")
+    assert load_cache(p) == {}
+    store_cache(p, "a", {"h_merge": 1, "density_pblocks": 3, "persistent": 0})
+    store_cache(p, "b", {"h_merge": 2, "density_pblocks": 5, "persistent": 1})
+    data = load_cache(p)
+    assert data["a"]["density_pblocks"] == 3 and data["b"]["persistent"] == 1
+    with open(p, "w") as f:
+        f.write("{not json")
+    assert load_cache(p) == {}
+    with open(p, "w") as f:
+        json.dump([1, 2], f)
+    assert load_cache(p) == {}
