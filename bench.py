@@ -2,13 +2,18 @@
 """Throughput of one s.c.f. step of NAO real-space grid integration on one MI355X.
 
 A step is one density update (n = sum_ij P_ij phi_i phi_j with the N, E_V, E_T sums) followed
-by one Hamiltonian integration (H_ij = sum_p w_p phi_i (v phi_j + t phi_j)), on the 64-atom
-random cluster (l <= 3 basis, 75 x 302 grid, batches <= 256 points) with inputs resident in
-HBM.  Both the plain FP64 form and the mixed form are timed; ``value`` is the mixed form's
-GFLOP/s with F = 4 sum_b n_p n_b^2 (the per-batch contractions, counted once), and its energy
-error against the FP64 form is reported next to it.  One JSON line on stdout.
+by one Hamiltonian integration (H_ij = sum_p w_p phi_i (v phi_j + t phi_j)), with inputs
+resident in HBM.  GFLOP/s use F = 4 sum_b n_p n_b^2 (the per-batch contractions, counted once,
+also for BF16x3).  The FP64 form and the mixed forms are timed; the headline ``value`` is the
+fastest form whose total energy stays within 1e-6 Ha of the FP64 form.  One JSON line on
+stdout.
 
-    python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--mixed fp32|bf16x3]
+    python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--workload c2|c3|c4|c5]
+
+Workloads: c2 (default) the 64-atom random cluster, 75 x 302 grid, batches <= 256;
+c3 the 512-atom water cluster; c4 256 independent molecules in one grouped handle (timed as a
+graph replay, as eager calls and as 256 per-molecule launch sets); c5 the 128-atom cluster,
+forward + backward (dE/dP, dE/dv, dE/dR) per step, F = 8 sum_b n_p n_b^2.
 """
 import argparse
 import json
@@ -19,18 +24,34 @@ import time
 import numpy as np
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}   # MI355X dense MFMA peaks
-HBM_GBS = 8000.0
+DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}
+FAMILIES = ("phi_eval", "density", "hs", "backward", "finish")
+
+WORKLOADS = {
+    "c2": "64-atom random cluster (Z in {1,6,8}, box 20 bohr), l<=3 NAO basis, 75x302 grid, "
+          "batches <= 256 points; one step = density update + H integration",
+    "c3": "512-atom water cluster (170 H2O + OH, 1 g/cm^3), l<=3 NAO basis, 75x302 grid, "
+          "batches <= 300 points; one step = density update + H integration",
+    "c4": "256 independent molecules (3-40 atoms, Z in {1,6,7,8}) in one grouped handle, "
+          "l<=2 NAO basis, 50x110 grid, batches <= 200 points; one step = density update + "
+          "H integration of every molecule",
+    "c5": "128-atom random cluster (box 25.2 bohr), l<=3 NAO basis, 75x302 grid, batches <= "
+          "256; one step = density update + backward (dE/dP, dE/dv, dE/dR)",
+}
+
+
+def _threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        return os.cpu_count() or 1
 
 
 def _cpu_baseline(inst, F, n_chunks, seed=0):
     """The FP64 oracle as it stands, on a bounded random sample of point chunks of the same
     workload, extrapolated to the whole step by the point count."""
     from oracle import GridOracle
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        threads = os.cpu_count() or 1
     o = GridOracle(inst)
     rng = np.random.default_rng(seed)
     nch = (inst.n_points + o.chunk - 1) // o.chunk
@@ -41,10 +62,249 @@ def _cpu_baseline(inst, F, n_chunks, seed=0):
     o.integrate_h(inst.v, want_S=False, points=idx)
     dt = time.perf_counter() - t0
     t_full = dt * inst.n_points / idx.size
-    return {"value": F / t_full / 1e9, "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
+    return {"value": F / t_full / 1e9, "unit": "GFLOP/s", "cores": int(_threads()), "kind": "oracle",
             "s_per_step": t_full,
             "sample": f"{len(pick)} random chunks of {o.chunk} points ({idx.size} of "
                       f"{inst.n_points} points, {dt:.1f} s), extrapolated by point count"}
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+class Timer:
+    """HIP events on the library stream around K steps (the kernels run on that stream)."""
+
+    def __init__(self, torch, stream):
+        self.torch, self.stream = torch, stream
+
+    def run(self, fn, steps, warmup):
+        torch = self.torch
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        w0 = time.perf_counter()
+        e0.record(self.stream)
+        for _ in range(steps):
+            fn()
+        e1.record(self.stream)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - w0) / steps * 1e3
+        return e0.elapsed_time(e1) / steps, wall
+
+
+def _kernels(g, steps):
+    out = {}
+    for k in FAMILIES:
+        cnt, kms, work = g.profile_read(k)
+        if cnt:
+            out[k] = {"launches": cnt, "ms_per_step": kms / steps, "avg_launch_ms": kms / cnt,
+                      "work_flop": work}
+    return out
+
+
+def _roofline(kern, head, steps):
+    dom = max(("density", "hs"), key=lambda k: kern.get(k, {}).get("ms_per_step", 0.0))
+    kd = kern[dom]
+    achieved = kd["work_flop"] / (kd["ms_per_step"] * steps * 1e-3) / 1e12
+    return {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[head],
+            "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[head], "traffic": None,
+            "avg_launch_ms": kd["avg_launch_ms"], "launches_per_step": kd["launches"] / steps}
+
+
+def _forms_summary(res):
+    ref = res["fp64"]
+    for prec, r in res.items():
+        r["abs_dE_Ha_vs_fp64"] = abs(r["E"] - ref["E"])
+        r["rel_dN_vs_fp64"] = abs(r["N"] - ref["N"]) / abs(ref["N"])
+        r["meets_1e-6_Ha"] = bool(r["abs_dE_Ha_vs_fp64"] <= 1e-6)
+    ok = [p for p in res if res[p]["meets_1e-6_Ha"]]
+    head = min(ok, key=lambda p: res[p]["ms_per_step"])
+    fastest = min(res, key=lambda p: res[p]["ms_per_step"])
+    return head, fastest
+
+
+def _make(workload, torch):
+    import synth
+    if workload == "c2":
+        return synth.make_instance("c2", seed=0)
+    with synth.generator_device(torch.device("cuda", 0)):
+        if workload == "c4":
+            return synth.make_molecule_set(n_mol=256, seed=0)
+        return synth.make_instance(workload, seed=0)
+
+
+def bench_single(args, torch, inst, backward=False):
+    """c2 / c3 / c5: one handle, every precision form, optionally with the backward."""
+    from paper_2208_12335_amd import AimsGrid
+    from paper_2208_12335_amd.autotune import autotune
+
+    dev = torch.device("cuda", 0)
+    t0 = time.time()
+    g = AimsGrid(inst, device=0)
+    ws = g.work_stats()
+    F = ws["flops_per_step"] * (2.0 if backward else 1.0)
+    _log(f"setup {time.time() - t0:.1f} s, {ws['n_batches']} batches, F = {F:.3e} flop/step")
+    P = torch.from_numpy(inst.P).to(dev).reshape(-1)
+    v = torch.from_numpy(inst.v).to(dev)
+    n = torch.empty(g.n_points, dtype=torch.float64, device=dev)
+    sums = torch.empty(1, 3, dtype=torch.float64, device=dev)
+    H = torch.empty(g.mat_elems, dtype=torch.float64, device=dev)
+    gE = torch.ones(1, dtype=torch.float64, device=dev)
+    timer = Timer(torch, g.stream)
+
+    forms = ["fp64"] + [f for f in args.forms.split(",") if f and f != "fp64"]
+    res = {}
+    for prec in forms:
+        if not args.no_autotune:
+            t0 = time.time()
+            r = autotune(g, P, v, prec=prec, reps=2, cache="")   # measured here, never cached
+            _log(f"{prec}: autotuned {dict((k, r[k]) for k in ('h_merge', 'density_pblocks', 'persistent'))}"
+                 f" ({time.time() - t0:.1f} s)")
+
+        if backward:
+            def step():
+                g.update_density(P, v, prec=prec, n_out=n, sums_out=sums)
+                g.backward(P, v, gE, prec=prec)
+        else:
+            def step():
+                g.update_density(P, v, prec=prec, n_out=n, sums_out=sums)
+                g.integrate_h(v, prec=prec, H_out=H)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        g.profile(True)
+        ms, wall = timer.run(step, args.steps, 0)
+        kern = _kernels(g, args.steps)
+        g.profile(False)
+        s = sums.cpu().numpy()[0]
+        res[prec] = {"ms_per_step": ms, "wall_ms_per_step": wall, "gflops": F / (ms * 1e-3) / 1e9,
+                     "N": float(s[0]), "E": float(s[1] + s[2]), "kernels": kern,
+                     "tuning": g.get_tuning(prec)}
+        _log(f"{prec}: {ms:.3f} ms/step, {res[prec]['gflops']:.1f} GFLOP/s")
+
+    head, fastest = _forms_summary(res)
+    hr = res[head]
+    line = {
+        "metric": "H+density integration GFLOP/s and ms per SCF step (fastest form within 1e-6 Ha "
+                  "of FP64; mixed forms reported beside it)" if not backward else
+                  "density + backward (dE/dP, dE/dv, dE/dR) GFLOP/s and ms per step",
+        "value": hr["gflops"], "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": hr["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[head],
+        "data": "synthetic", "headline_form": head,
+        "config": {"workload": WORKLOADS[args.workload], "n_points": inst.n_points,
+                   "n_basis": inst.n_basis, "n_batches": ws["n_batches"], "flop_per_step": F,
+                   "sum_np_nb2": ws["sum_np_nb2"], "parallelism": "single GPU"},
+        "forms": {p: {k: r[k] for k in ("ms_per_step", "wall_ms_per_step", "gflops",
+                                         "abs_dE_Ha_vs_fp64", "meets_1e-6_Ha", "rel_dN_vs_fp64",
+                                         "tuning", "E", "N")}
+                  for p, r in res.items()},
+        "fastest_form": {"form": fastest, "ms_per_step": res[fastest]["ms_per_step"],
+                         "gflops": res[fastest]["gflops"],
+                         "speedup_vs_fp64": res["fp64"]["ms_per_step"] / res[fastest]["ms_per_step"]},
+        "kernels": {p: r["kernels"] for p, r in res.items()},
+        "autotuned": not args.no_autotune,
+        "roofline": _roofline(hr["kernels"], head, args.steps),
+    }
+    if args.cpu_chunks > 0:
+        _log("CPU baseline (oracle sample)...")
+        cb = _cpu_baseline(inst, ws["flops_per_step"], args.cpu_chunks)
+        if backward:
+            cb["sample"] += " (forward step only)"
+        line["cpu_baseline"] = cb
+    return line
+
+
+def bench_grouped(args, torch, mols):
+    """c4: one grouped handle over every molecule, timed as a captured step graph and as eager
+    calls, against 256 per-molecule handles (one launch set per molecule)."""
+    from paper_2208_12335_amd import AimsGrid
+    from paper_2208_12335_amd.autotune import autotune
+
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.Stream(dev)
+    t0 = time.time()
+    g = AimsGrid(mols, device=0, stream=stream)
+    ws = g.work_stats()
+    F = ws["flops_per_step"]
+    _log(f"grouped setup {time.time() - t0:.1f} s, {ws['n_batches']} batches, F = {F:.3e}")
+    P = torch.cat([torch.from_numpy(m.P).reshape(-1) for m in mols]).to(dev)
+    v = torch.cat([torch.from_numpy(m.v) for m in mols]).to(dev)
+    n = torch.empty(g.n_points, dtype=torch.float64, device=dev)
+    sums = torch.empty(len(mols), 3, dtype=torch.float64, device=dev)
+    H = torch.empty(g.mat_elems, dtype=torch.float64, device=dev)
+    timer = Timer(torch, stream)
+    prec = "fp64"
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        if not args.no_autotune:
+            r = autotune(g, P, v, prec=prec, reps=2, cache="")
+            _log(f"autotuned {dict((k, r[k]) for k in ('h_merge', 'density_pblocks', 'persistent'))}")
+
+        def eager():
+            g.update_density(P, v, prec=prec, n_out=n, sums_out=sums)
+            g.integrate_h(v, prec=prec, H_out=H)
+
+        ms_eager, wall_eager = timer.run(eager, args.steps, args.warmup)
+        g.profile(True)
+        timer.run(eager, args.steps, 0)
+        kern = _kernels(g, args.steps)
+        g.profile(False)
+        E_eager = sums.cpu().numpy().copy()
+        graph = g.step_graph(P, v, n, sums, H, prec=prec)
+        ms_graph, wall_graph = timer.run(graph.launch, args.steps, args.warmup)
+        E_graph = sums.cpu().numpy().copy()
+    _log(f"grouped eager {ms_eager:.3f} ms, graph {ms_graph:.3f} ms")
+
+    # per-molecule baseline: one handle and one launch set per molecule on the same stream
+    singles = []
+    tg = g.get_tuning(prec)
+    for m in mols:
+        gm = AimsGrid(m, device=0, stream=stream)
+        gm.set_tuning(h_merge=tg["h_merge"], density_pblocks=tg["density_pblocks"], prec=prec)
+        Pm = torch.from_numpy(m.P).to(dev).reshape(-1)
+        vm = torch.from_numpy(m.v).to(dev)
+        nm = torch.empty(gm.n_points, dtype=torch.float64, device=dev)
+        sm = torch.empty(1, 3, dtype=torch.float64, device=dev)
+        Hm = torch.empty(gm.mat_elems, dtype=torch.float64, device=dev)
+        singles.append((gm, Pm, vm, nm, sm, Hm))
+    torch.cuda.synchronize()
+
+    def per_molecule():
+        for gm, Pm, vm, nm, sm, Hm in singles:
+            gm.update_density(Pm, vm, prec=prec, n_out=nm, sums_out=sm)
+            gm.integrate_h(vm, prec=prec, H_out=Hm)
+
+    with torch.cuda.stream(stream):
+        ms_single, wall_single = timer.run(per_molecule, args.steps, args.warmup)
+    E_single = np.stack([s[4].cpu().numpy()[0] for s in singles])
+    _log(f"per-molecule {ms_single:.3f} ms (wall {wall_single:.3f} ms)")
+    dE = float(np.max(np.abs((E_graph[:, 1] + E_graph[:, 2]) - (E_single[:, 1] + E_single[:, 2]))))
+    nmol = len(mols)
+    return {
+        "metric": "grouped s.c.f. step throughput over 256 molecules (graph replay), molecules/s",
+        "value": nmol / (ms_graph * 1e-3), "unit": "molecules/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_graph,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS["c4"], "n_molecules": nmol, "n_points": g.n_points,
+                   "n_basis_total": g.n_basis, "n_batches": ws["n_batches"], "flop_per_step": F,
+                   "parallelism": "single GPU"},
+        "gflops_graph": F / (ms_graph * 1e-3) / 1e9,
+        "modes": {"graph": {"ms_per_step": ms_graph, "wall_ms_per_step": wall_graph},
+                  "eager_grouped": {"ms_per_step": ms_eager, "wall_ms_per_step": wall_eager},
+                  "per_molecule": {"ms_per_step": ms_single, "wall_ms_per_step": wall_single,
+                                   "molecules_per_s": nmol / (ms_single * 1e-3)}},
+        "speedup_graph_vs_per_molecule": ms_single / ms_graph,
+        "max_abs_dE_Ha_grouped_vs_per_molecule": dE,
+        "max_abs_dE_Ha_graph_vs_eager": float(np.max(np.abs(E_graph - E_eager))),
+        "tuning": tg, "kernels": {"fp64": kern},
+        "roofline": _roofline(kern, "fp64", args.steps),
+    }
 
 
 def main():
@@ -52,6 +312,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--forms", default="fp64,fp32,bf16x3",
                     help="precision forms to time (fp64 is always included)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -61,119 +322,18 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(the batches would shard across GPUs with one FP64 reduction of H; see DESIGN.md)",
+              "(the batches would shard across GPUs with one FP64 reduction of H)",
               file=sys.stderr)
         sys.exit(2)
 
     import torch
-    import synth
-    from paper_2208_12335_amd import AimsGrid
-    from paper_2208_12335_amd.autotune import autotune
-
-    dev = torch.device("cuda", 0)
     t0 = time.time()
-    inst = synth.make_instance("c2", seed=0)
-    print(f"[bench] instance: {inst.n_points} points, {inst.n_basis} functions "
-          f"({time.time() - t0:.1f} s)", file=sys.stderr, flush=True)
-    t0 = time.time()
-    g = AimsGrid(inst, device=0)
-    ws = g.work_stats()
-    F = ws["flops_per_step"]
-    print(f"[bench] setup {time.time() - t0:.1f} s, {ws['n_batches']} batches, "
-          f"F = {F:.3e} flop/step", file=sys.stderr, flush=True)
-    P = torch.from_numpy(inst.P).to(dev).reshape(-1)
-    v = torch.from_numpy(inst.v).to(dev)
-    n = torch.empty(g.n_points, dtype=torch.float64, device=dev)
-    sums = torch.empty(1, 3, dtype=torch.float64, device=dev)
-    H = torch.empty(g.mat_elems, dtype=torch.float64, device=dev)
-    stream = g.stream
-
-    def step(prec):
-        g.update_density(P, v, prec=prec, n_out=n, sums_out=sums)
-        g.integrate_h(v, prec=prec, H_out=H)
-
-    forms = ["fp64"] + [f for f in args.forms.split(",") if f and f != "fp64"]
-    res = {}
-    tuned = {}
-    for prec in forms:
-        if not args.no_autotune:
-            t0 = time.time()
-            r = autotune(g, P, v, prec=prec, reps=2, cache="")   # measured here, never cached
-            tuned[prec] = {k: r[k] for k in ("h_merge", "density_pblocks", "persistent")}
-            print(f"[bench] {prec}: autotuned {tuned[prec]} ({time.time() - t0:.1f} s)",
-                  file=sys.stderr, flush=True)
-        for _ in range(args.warmup):
-            step(prec)
-        torch.cuda.synchronize()
-        g.profile(True)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        w0 = time.perf_counter()
-        e0.record(stream)
-        for _ in range(args.steps):
-            step(prec)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        wall = (time.perf_counter() - w0) / args.steps * 1e3
-        ms = e0.elapsed_time(e1) / args.steps
-        kern = {}
-        for k in ("phi_eval", "density", "hs", "finish"):
-            cnt, kms, work = g.profile_read(k)
-            kern[k] = {"launches": cnt, "ms_per_step": kms / args.steps,
-                       "avg_launch_ms": kms / cnt if cnt else 0.0, "work_flop": work}
-        g.profile(False)
-        s = sums.cpu().numpy()[0]
-        res[prec] = {"ms_per_step": ms, "wall_ms_per_step": wall, "gflops": F / (ms * 1e-3) / 1e9,
-                     "N": float(s[0]), "E": float(s[1] + s[2]), "kernels": kern,
-                     "H_fro": float(torch.linalg.norm(H).item()),
-                     "tuning": g.get_tuning(prec)}
-        print(f"[bench] {prec}: {ms:.3f} ms/step, {res[prec]['gflops']:.1f} GFLOP/s", file=sys.stderr,
-              flush=True)
-
-    ref = res["fp64"]
-    for prec, r in res.items():
-        r["abs_dE_Ha_vs_fp64"] = abs(r["E"] - ref["E"])
-        r["rel_dN_vs_fp64"] = abs(r["N"] - ref["N"]) / abs(ref["N"])
-        r["rel_dHfro_vs_fp64"] = abs(r["H_fro"] - ref["H_fro"]) / ref["H_fro"]
-        r["meets_1e-6_Ha"] = bool(r["abs_dE_Ha_vs_fp64"] <= 1e-6)
-    # headline: the fastest form that holds the total energy within 1e-6 Ha of the FP64 form
-    ok = [p for p in res if res[p]["meets_1e-6_Ha"]]
-    head = min(ok, key=lambda p: res[p]["ms_per_step"])
-    hr = res[head]
-    dom = max(("density", "hs"), key=lambda k: hr["kernels"][k]["ms_per_step"])
-    kd = hr["kernels"][dom]
-    achieved = kd["work_flop"] / (kd["ms_per_step"] * args.steps * 1e-3) / 1e12 if kd["ms_per_step"] else 0.0
-    roof = {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[head],
-            "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[head], "traffic": None,
-            "avg_launch_ms": kd["avg_launch_ms"], "launches_per_step": kd["launches"] / args.steps}
-    fastest = min(res, key=lambda p: res[p]["ms_per_step"])
-    line = {
-        "metric": "H+density integration GFLOP/s and ms per SCF step (fastest form within 1e-6 Ha "
-                  "of FP64; mixed forms reported beside it)",
-        "value": hr["gflops"], "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": hr["ms_per_step"], "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[head],
-        "data": "synthetic", "headline_form": head,
-        "config": {"workload": "64-atom random cluster (Z in {1,6,8}, box 20 bohr), l<=3 NAO basis "
-                               f"({inst.n_basis} functions), 75x302 grid ({inst.n_points} points), "
-                               "batches <= 256 points; one step = density update + H integration",
-                   "n_points": inst.n_points, "n_basis": inst.n_basis,
-                   "n_batches": ws["n_batches"], "flop_per_step": F, "sum_nb2": ws["sum_nb2"],
-                   "parallelism": "single GPU"},
-        "forms": {p: {k: r[k] for k in ("ms_per_step", "gflops", "abs_dE_Ha_vs_fp64", "meets_1e-6_Ha",
-                                         "rel_dN_vs_fp64", "rel_dHfro_vs_fp64", "tuning", "E", "N")}
-                  for p, r in res.items()},
-        "fastest_form": {"form": fastest, "ms_per_step": res[fastest]["ms_per_step"],
-                         "gflops": res[fastest]["gflops"],
-                         "speedup_vs_fp64": ref["ms_per_step"] / res[fastest]["ms_per_step"]},
-        "kernels": {p: r["kernels"] for p, r in res.items()},
-        "autotuned": not args.no_autotune,
-        "roofline": roof,
-    }
-    if args.cpu_chunks > 0:
-        print("[bench] CPU baseline (oracle sample)...", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = _cpu_baseline(inst, F, args.cpu_chunks)
+    inst = _make(args.workload, torch)
+    _log(f"instance {args.workload} ({time.time() - t0:.1f} s)")
+    if args.workload == "c4":
+        line = bench_grouped(args, torch, inst)
+    else:
+        line = bench_single(args, torch, inst, backward=(args.workload == "c5"))
     print(json.dumps(line), flush=True)
 
 

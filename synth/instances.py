@@ -55,6 +55,42 @@ GRID_RULES = {
 }
 
 
+_DEVICE = [None]
+
+
+class generator_device:
+    """Context manager choosing the torch device of the generator's bulk arithmetic (distance
+    tables, partition weights, potential): ``with generator_device("cuda"): ...``.  The
+    default is the CPU.  The instance definition does not depend on the device; values agree
+    to floating-point rounding."""
+
+    def __init__(self, device):
+        self.device = device
+
+    def __enter__(self):
+        self.prev = _DEVICE[0]
+        _DEVICE[0] = self.device
+        return self
+
+    def __exit__(self, *exc):
+        _DEVICE[0] = self.prev
+        return False
+
+
+def _torch_device():
+    import torch
+    return torch.device(_DEVICE[0]) if _DEVICE[0] is not None else torch.device("cpu")
+
+
+def _dist(X, A):
+    """Distance table |X_i - A_j| (torch, on X's device)."""
+    import torch
+    if X.device.type == "cpu":
+        return torch.cdist(X, A, compute_mode='donot_use_mm_for_euclid_dist')
+    d = X[:, None, :] - A[None, :, :]
+    return torch.sqrt((d * d).sum(-1))
+
+
 @dataclasses.dataclass
 class Instance:
     """One molecular system with its integration grid, potential and density matrix."""
@@ -211,8 +247,10 @@ def stratmann_partition(points: np.ndarray, owner: np.ndarray, atoms: np.ndarray
     candidates (one candidate means weight 1 for the nearest atom and 0 for the others).
     For systems with more than ``max_neighbors`` atoms the candidate set and the products are
     further limited to the ``max_neighbors`` nearest atoms (a point-dependent set, so the
-    weights still sum to one at every point); with fewer atoms the formula is exact."""
+    weights still sum to one at every point); with fewer atoms the formula is exact.
+    Runs on the generator's torch device (see :func:`generator_device`)."""
     import torch
+    dev = _torch_device()
     na = atoms.shape[0]
     npts = points.shape[0]
     out = np.zeros(npts, dtype=np.float64)
@@ -224,44 +262,44 @@ def stratmann_partition(points: np.ndarray, owner: np.ndarray, atoms: np.ndarray
     dAA = np.linalg.norm(atoms[:, None, :] - atoms[None, :, :], axis=-1)
     with np.errstate(divide="ignore"):
         inv_aa = np.where(dAA > 0, 1.0 / np.where(dAA > 0, dAA, 1.0), 0.0)
-    A = torch.from_numpy(atoms)
-    Dinv = torch.from_numpy(inv_aa)
-    # distances, sorted, and the candidate count per point
-    Ds_all = np.empty((npts, M))
-    order_all = np.empty((npts, M), dtype=np.int64)
-    for s0 in range(0, npts, 65536):
-        D = torch.cdist(torch.from_numpy(points[s0:s0 + 65536]), A, compute_mode='donot_use_mm_for_euclid_dist')
-        Ds, order = torch.topk(D, M, dim=1, largest=False)
-        Ds_all[s0:s0 + 65536] = Ds.numpy()
-        order_all[s0:s0 + 65536] = order.numpy()
-    ncand = (Ds_all < Ds_all[:, :1] * ((1.0 + a) / (1.0 - a))).sum(axis=1)
-    one = ncand <= 1
-    out[one] = (order_all[one, 0] == owner[one]).astype(np.float64)
-    k = 2
-    lo = 1
-    while lo < M:
-        hi = min(k, M)
-        sel = np.nonzero((ncand > lo) & (ncand <= hi))[0]
-        for s0 in range(0, sel.size, max(1, chunk * 64 // hi)):
-            idx = sel[s0:s0 + max(1, chunk * 64 // hi)]
-            Ds = torch.from_numpy(Ds_all[idx])                     # [c, M]
-            order = torch.from_numpy(order_all[idx])               # [c, M]
-            cand = order[:, :hi]                                   # [c, k]
-            inv = Dinv[cand[:, :, None], order[:, None, :]]        # [c, k, M], 0 where b == c
-            nu = (Ds[:, :hi, None] - Ds[:, None, :]) * inv / a
-            nu.clamp_(-1.0, 1.0)
-            nu2 = nu * nu
-            g = nu * (35.0 + nu2 * (-35.0 + nu2 * (21.0 - 5.0 * nu2))) / 16.0
-            s = 0.5 * (1.0 - g)
-            same = cand[:, :, None] == order[:, None, :]
-            s = torch.where(same, torch.ones_like(s), s)
-            Pb = torch.prod(s, dim=2)                              # [c, k]
-            own = torch.from_numpy(owner[idx].astype(np.int64))[:, None]
-            Pown = torch.where(cand == own, Pb, torch.zeros_like(Pb)).sum(dim=1)
-            tot = Pb.sum(dim=1)
-            out[idx] = (Pown / tot).numpy()
-        lo = hi
-        k *= 2
+    A = torch.from_numpy(np.ascontiguousarray(atoms)).to(dev)
+    Dinv = torch.from_numpy(inv_aa).to(dev)
+    big = 65536
+    for c0 in range(0, npts, big):
+        X = torch.from_numpy(np.ascontiguousarray(points[c0:c0 + big])).to(dev)
+        D = _dist(X, A)
+        Ds_all, order_all = torch.topk(D, M, dim=1, largest=False)
+        del D
+        own_all = torch.from_numpy(owner[c0:c0 + big].astype(np.int64)).to(dev)
+        res = torch.zeros(X.shape[0], dtype=torch.float64, device=dev)
+        ncand = (Ds_all < Ds_all[:, :1] * ((1.0 + a) / (1.0 - a))).sum(dim=1)
+        one = ncand <= 1
+        res[one] = (order_all[one, 0] == own_all[one]).to(torch.float64)
+        k = 2
+        lo = 1
+        while lo < M:
+            hi = min(k, M)
+            sel = torch.nonzero((ncand > lo) & (ncand <= hi)).reshape(-1)
+            step = max(1, chunk * 64 // hi) if dev.type == "cpu" else 65536
+            for s0 in range(0, sel.numel(), step):
+                idx = sel[s0:s0 + step]
+                Ds = Ds_all[idx]                                       # [c, M]
+                order = order_all[idx]                                 # [c, M]
+                cand = order[:, :hi]                                   # [c, k]
+                inv = Dinv[cand[:, :, None], order[:, None, :]]        # [c, k, M], 0 where b == c
+                nu = (Ds[:, :hi, None] - Ds[:, None, :]) * inv / a
+                nu.clamp_(-1.0, 1.0)
+                nu2 = nu * nu
+                g = nu * (35.0 + nu2 * (-35.0 + nu2 * (21.0 - 5.0 * nu2))) / 16.0
+                s = 0.5 * (1.0 - g)
+                same = cand[:, :, None] == order[:, None, :]
+                s = torch.where(same, torch.ones_like(s), s)
+                Pb = torch.prod(s, dim=2)                              # [c, k]
+                Pown = torch.where(cand == own_all[idx][:, None], Pb, torch.zeros_like(Pb)).sum(dim=1)
+                res[idx] = Pown / Pb.sum(dim=1)
+            lo = hi
+            k *= 2
+        out[c0:c0 + X.shape[0]] = res.cpu().numpy()
     return out
 
 
@@ -429,10 +467,12 @@ def build_grid(atom_xyz: np.ndarray, n_radial: int, angular: str, rc: float = RC
 
 def _min_distance(points: np.ndarray, atom_xyz: np.ndarray) -> np.ndarray:
     import torch
-    A = torch.from_numpy(np.ascontiguousarray(atom_xyz))
+    dev = _torch_device()
+    A = torch.from_numpy(np.ascontiguousarray(atom_xyz)).to(dev)
     out = np.empty(points.shape[0])
     for s0 in range(0, points.shape[0], 65536):
-        out[s0:s0 + 65536] = torch.cdist(torch.from_numpy(points[s0:s0 + 65536]), A, compute_mode='donot_use_mm_for_euclid_dist').min(1).values.numpy()
+        X = torch.from_numpy(np.ascontiguousarray(points[s0:s0 + 65536])).to(dev)
+        out[s0:s0 + 65536] = _dist(X, A).min(1).values.cpu().numpy()
     return out
 
 
@@ -440,16 +480,18 @@ def nuclear_potential(points: np.ndarray, atom_xyz: np.ndarray, Z: np.ndarray,
                       sigma: float = NUCLEAR_SIGMA) -> np.ndarray:
     """v(p) = sum_a -Z_a erf(r/sigma)/r, with the r -> 0 limit -Z 2/(sigma sqrt(pi))."""
     import torch
-    A = torch.from_numpy(np.ascontiguousarray(atom_xyz))
-    Zt = torch.from_numpy(np.asarray(Z, dtype=np.float64))
+    dev = _torch_device()
+    A = torch.from_numpy(np.ascontiguousarray(atom_xyz)).to(dev)
+    Zt = torch.from_numpy(np.asarray(Z, dtype=np.float64)).to(dev)
     v = np.empty(points.shape[0])
     lim = 2.0 / (sigma * math.sqrt(math.pi))
     for s0 in range(0, points.shape[0], 65536):
-        r = torch.cdist(torch.from_numpy(points[s0:s0 + 65536]), A, compute_mode='donot_use_mm_for_euclid_dist')
+        X = torch.from_numpy(np.ascontiguousarray(points[s0:s0 + 65536])).to(dev)
+        r = _dist(X, A)
         small = r < 1e-12
         rs = torch.where(small, torch.ones_like(r), r)
         t = torch.where(small, torch.full_like(r, lim), torch.erf(rs / sigma) / rs)
-        v[s0:s0 + 65536] = -(t * Zt).sum(1).numpy()
+        v[s0:s0 + 65536] = -(t * Zt).sum(1).cpu().numpy()
     return v
 
 

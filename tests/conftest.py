@@ -43,3 +43,17 @@ def relerr(x, ref):
     den = np.max(np.abs(ref)) if ref.size else 0.0
     num = np.max(np.abs(x - ref)) if ref.size else 0.0
     return 0.0 if den == 0 and num == 0 else num / den
+
+
+def pair_block(o, inst, a, b, v):
+    """H and S block of atoms (a, b) by the oracle ``o``, over the points within rc of both
+    (every other point contributes exactly zero to the block)."""
+    import numpy as np
+    d = np.linalg.norm(inst.pt_xyz[:, None, :] - inst.atom_xyz[None, [a, b], :], axis=-1)
+    idx = np.nonzero((d[:, 0] < inst.rc) & (d[:, 1] < inst.rc))[0]
+    Pa, Ta, ca = o.basis_values(inst.pt_xyz[idx], atoms=np.array([a]))
+    Pb, Tb, cb = o.basis_values(inst.pt_xyz[idx], atoms=np.array([b]))
+    w = inst.pt_w[idx][:, None]
+    H = Pa.T @ (w * (v[idx][:, None] * Pb + Tb))
+    S = Pa.T @ (w * Pb)
+    return ca, cb, H, S

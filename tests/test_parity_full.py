@@ -8,7 +8,7 @@ import torch
 import synth
 from oracle import GridOracle
 from paper_2208_12335_amd import AimsGrid
-from conftest import relerr
+from conftest import pair_block, relerr
 
 pytestmark = pytest.mark.gpu
 
@@ -29,18 +29,6 @@ def c2_run(gpu):
     return inst, g, out
 
 
-def _pair_block(o, inst, a, b, v):
-    """H and S block of atoms (a, b) by the oracle, over the points within rc of both."""
-    d = np.linalg.norm(inst.pt_xyz[:, None, :] - inst.atom_xyz[None, [a, b], :], axis=-1)
-    idx = np.nonzero((d[:, 0] < inst.rc) & (d[:, 1] < inst.rc))[0]
-    Pa, Ta, ca = o.basis_values(inst.pt_xyz[idx], atoms=np.array([a]))
-    Pb, Tb, cb = o.basis_values(inst.pt_xyz[idx], atoms=np.array([b]))
-    w = inst.pt_w[idx][:, None]
-    H = Pa.T @ (w * (v[idx][:, None] * Pb + Tb))
-    S = Pa.T @ (w * Pb)
-    return ca, cb, H, S
-
-
 def test_c2_density_sampled_points(c2_run):
     inst, g, out = c2_run
     o = GridOracle(inst)
@@ -59,7 +47,7 @@ def test_c2_h_and_s_sampled_blocks(c2_run):
     worst_H = worst_S = 0.0
     pairs = [(int(a), int(b)) for a, b in rng.integers(0, inst.n_atoms, size=(6, 2))] + [(3, 3)]
     for a, b in pairs:
-        ca, cb, Hr, Sr = _pair_block(o, inst, a, b, inst.v)
+        ca, cb, Hr, Sr = pair_block(o, inst, a, b, inst.v)
         worst_H = max(worst_H, relerr(out["H"][np.ix_(ca, cb)], Hr) if np.abs(Hr).max() > 0 else 0)
         worst_S = max(worst_S, relerr(out["S"][np.ix_(ca, cb)], Sr) if np.abs(Sr).max() > 0 else 0)
     print(f"[full] sampled H blocks {worst_H:.2e}, S blocks {worst_S:.2e}", flush=True)
