@@ -319,6 +319,9 @@ def main():
                     help="time the library's default tuning instead of the autotuner's choice")
     ap.add_argument("--cpu-chunks", type=int, default=10,
                     help="point chunks of the oracle's CPU baseline sample (0 = skip)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (3 launches): the reference "
+                         "kernel that scales the HBM byte counters of a profiler run")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -327,6 +330,16 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": n * 8, "copy_calibration_bytes_written": n * 8,
+                          "launches": 3}), flush=True)
+        return
     t0 = time.time()
     inst = _make(args.workload, torch)
     _log(f"instance {args.workload} ({time.time() - t0:.1f} s)")

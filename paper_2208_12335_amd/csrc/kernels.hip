@@ -134,6 +134,13 @@ __device__ __forceinline__ void eval_atom_point(double dx, double dy, double dz,
   }
 }
 
+// Basis values of one batch: kPhiSlices workgroups of four waves per batch; wave w of the
+// batch (0 .. 4 kPhiSlices - 1) takes the batch's relevant atoms w, w + 4 kPhiSlices, ... and,
+// for each, sweeps the padded point range with its 64 lanes.  Every wave works on one atom at a
+// time, so the species, shell and table addressing is wave-uniform (scalar); lanes past the
+// batch's points write the zero padding of the atom's rows.
+constexpr int kPhiSlices = 4;
+
 template <typename T, int LAYOUT>
 __global__ void __launch_bounds__(256)
 phi_eval_kernel(const BatchDesc* __restrict__ batches, int b0, const double4* __restrict__ pts,
@@ -143,32 +150,29 @@ phi_eval_kernel(const BatchDesc* __restrict__ batches, int b0, const double4* __
                 const int32_t* __restrict__ shell_l, const T* __restrict__ spline, RadialGrid rg,
                 const double* __restrict__ v, int mode, void* __restrict__ slab1,
                 void* __restrict__ slab2) {
-  const BatchDesc d = batches[b0 + blockIdx.x];
+  const int bi = blockIdx.x / kPhiSlices;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(blockIdx.x % kPhiSlices) * 4 + (int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  const BatchDesc d = batches[b0 + bi];
   const int np = d.n_p, na = d.n_atoms, ldp = d.ldp;
   typedef typename std::conditional<LAYOUT == kLayoutDense, T, bf16_t>::type S;
   const int64_t off = (LAYOUT == kLayoutDense ? 1 : 2) * d.slab_off;
   SlabStore<T, LAYOUT> store{(S*)slab1 + off, (S*)slab2 + off, ldp};
-  const int pairs = np * na;
-  for (int q = threadIdx.x; q < pairs; q += blockDim.x) {
-    const int k = q / np;
-    const int p = q - k * np;
+  for (int k = wave; k < na; k += 4 * kPhiSlices) {
     const int atom = batch_atoms[d.atom_off + k];
     const int col0 = batch_acol[d.atom_off + k];
     const SpeciesDesc sd = species[atom_species[atom]];
-    const double4 P4 = pts[d.pt_off + p];
-    double wv = 0.0;
-    if (mode == kModeH) wv = P4.w * v[perm[d.pt_off + p]];
-    eval_atom_point<T>(P4.x - atom_xyz[3 * atom], P4.y - atom_xyz[3 * atom + 1],
-                       P4.z - atom_xyz[3 * atom + 2], sd, shell_l, spline, rg, mode, T(P4.w),
-                       T(wv), col0, p, store);
-  }
-  // zero the padding columns so that the K loops may run over whole padded rows
-  const int padw = ldp - np;
-  if (padw > 0) {
-    const int tot = d.n_b * padw;
-    for (int q = threadIdx.x; q < tot; q += blockDim.x) {
-      const int row = q / padw;
-      store(row, np + (q - row * padw), T(0), T(0));
+    const double ax = atom_xyz[3 * atom], ay = atom_xyz[3 * atom + 1], az = atom_xyz[3 * atom + 2];
+    for (int p = lane; p < ldp; p += 64) {
+      if (p < np) {
+        const double4 P4 = pts[d.pt_off + p];
+        double wv = 0.0;
+        if (mode == kModeH) wv = P4.w * v[perm[d.pt_off + p]];
+        eval_atom_point<T>(P4.x - ax, P4.y - ay, P4.z - az, sd, shell_l, spline, rg, mode,
+                           T(P4.w), T(wv), col0, p, store);
+      } else {
+        for (int f = 0; f < sd.nfn; ++f) store(col0 + f, p, T(0), T(0));
+      }
     }
   }
 }
@@ -316,20 +320,25 @@ density_tile(int item, const TileItem* __restrict__ items, int n_items, const Ba
 #pragma unroll
     for (int ni = 0; ni < NBN; ++ni) acc[mi][ni] = acc_t{0, 0, 0, 0};
 
-  // A staging: row ra, 4 consecutive k at 4 sa; column indices loaded one chunk ahead
-  const int ra = tid >> 2, sa = tid & 3;
-  const int grow = (j0 + ra < nb) ? cols[j0 + ra] : -1;
-  const T* Prow = Pm + (size_t)(grow < 0 ? 0 : grow) * sys.nb;
-  int cidx[4];
-  T av[4], bv[BQ][4];
-  bool kval[4];
-  auto load_cols = [&](int kc) {     // unconditional load of a clamped index (no branch)
+  // A staging: thread (kk = tid % 16, rr = tid / 16) stages P_b[j0 + rr + 16 c][kc + kk] for
+  // c = 0..3, so that the 16 lanes of one row read consecutive basis columns (one or two cache
+  // lines per row and instruction); the column index is loaded one chunk ahead
+  const int kk = tid & 15, rr = tid >> 4;
+  const T* Prow[4];
+  bool rok[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int k = kc + 4 * sa + c;
-      kval[c] = k < nb;
-      cidx[c] = cols[k < nb ? k : nb - 1];
-    }
+  for (int c = 0; c < 4; ++c) {
+    const int j = j0 + rr + 16 * c;
+    rok[c] = j < nb;
+    Prow[c] = Pm + (size_t)cols[rok[c] ? j : 0] * sys.nb;
+  }
+  int cidx;
+  T av[4], bv[BQ][4];
+  bool kval;
+  auto load_cols = [&](int kc) {     // unconditional load of a clamped index (no branch)
+    const int k = kc + kk;
+    kval = k < nb;
+    cidx = cols[k < nb ? k : nb - 1];
   };
   // loads are issued unconditionally from clamped addresses (no branch, so they stay in flight
   // across the multiply of the current chunk); invalid elements are zeroed when stashed
@@ -337,8 +346,8 @@ density_tile(int item, const TileItem* __restrict__ items, int n_items, const Ba
   auto fetch = [&](int kc) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      aok[c] = grow >= 0 && kval[c];
-      av[c] = Prow[cidx[c]];
+      aok[c] = rok[c] && kval;
+      av[c] = Prow[c][cidx];
     }
 #pragma unroll
     for (int q = 0; q < BQ; ++q) {
@@ -350,7 +359,7 @@ density_tile(int item, const TileItem* __restrict__ items, int n_items, const Ba
   };
   auto stash = [&](int buf) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) As[buf][ra * kLdK + 4 * sa + c] = aok[c] ? av[c] : T(0);
+    for (int c = 0; c < 4; ++c) As[buf][(rr + 16 * c) * kLdK + kk] = aok[c] ? av[c] : T(0);
 #pragma unroll
     for (int q = 0; q < BQ; ++q) {
       const int u = tid + 256 * q;
@@ -1163,7 +1172,7 @@ hipError_t launch_phi_eval(const DeviceView& dv, int b0, int nbatch, int mode, c
                            T* slab1, T* slab2, hipStream_t st) {
   if (nbatch == 0) return hipSuccess;
   const T* spline = (const T*)(sizeof(T) == 8 ? (const void*)dv.spline64 : (const void*)dv.spline32);
-  hipLaunchKernelGGL((phi_eval_kernel<T, kLayoutDense>), dim3(nbatch), dim3(256), 0, st, dv.batches,
+  hipLaunchKernelGGL((phi_eval_kernel<T, kLayoutDense>), dim3(nbatch * kPhiSlices), dim3(256), 0, st, dv.batches,
                      b0, dv.pts, dv.perm, dv.batch_atoms, dv.batch_acol, dv.atom_xyz,
                      dv.atom_species, dv.species, dv.shell_l, spline, dv.rg, v, mode,
                      (void*)slab1, (void*)slab2);
@@ -1173,7 +1182,7 @@ hipError_t launch_phi_eval(const DeviceView& dv, int b0, int nbatch, int mode, c
 hipError_t launch_phi_eval_bf16(const DeviceView& dv, int b0, int nbatch, int mode, const double* v,
                                 void* slab1, void* slab2, hipStream_t st) {
   if (nbatch == 0) return hipSuccess;
-  hipLaunchKernelGGL((phi_eval_kernel<float, kLayoutBfFn>), dim3(nbatch), dim3(256), 0, st,
+  hipLaunchKernelGGL((phi_eval_kernel<float, kLayoutBfFn>), dim3(nbatch * kPhiSlices), dim3(256), 0, st,
                      dv.batches, b0, dv.pts, dv.perm, dv.batch_atoms, dv.batch_acol, dv.atom_xyz,
                      dv.atom_species, dv.species, dv.shell_l, dv.spline32, dv.rg, v, mode,
                      slab1, slab2);
