@@ -24,6 +24,9 @@ import time
 import numpy as np
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}   # MI355X dense MFMA peaks
+HERE = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "density_kernel_c2_hbm_traffic.md")
+KERNEL_SRC = os.path.join(HERE, "paper_2208_12335_amd", "csrc", "kernels.hip")
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}
 FAMILIES = ("phi_eval", "density", "hs", "backward", "finish")
 
@@ -79,20 +82,23 @@ class Timer:
         self.torch, self.stream = torch, stream
 
     def run(self, fn, steps, warmup):
+        """Mean ms per step over the K steps (events around all of them), wall-clock ms per
+        step; per-step event pairs give the median and minimum in ``self.last``."""
         torch = self.torch
         for _ in range(warmup):
             fn()
         torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
         w0 = time.perf_counter()
-        e0.record(self.stream)
-        for _ in range(steps):
+        ev[0].record(self.stream)
+        for i in range(steps):
             fn()
-        e1.record(self.stream)
+            ev[i + 1].record(self.stream)
         torch.cuda.synchronize()
         wall = (time.perf_counter() - w0) / steps * 1e3
-        return e0.elapsed_time(e1) / steps, wall
+        per = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(steps))
+        self.last = {"median": per[len(per) // 2], "min": per[0]}
+        return ev[0].elapsed_time(ev[-1]) / steps, wall
 
 
 def _kernels(g, steps):
@@ -105,13 +111,33 @@ def _kernels(g, steps):
     return out
 
 
-def _roofline(kern, head, steps):
+def _measured_traffic(workload, form, family, tuning):
+    """HBM bytes per launch of the dominant kernel from the committed profiler summary (two
+    rocprofv3 --pmc passes, FETCH_SIZE and WRITE_SIZE, scaled by a plain copy kernel), used only
+    when that summary was taken on the same kernel source, workload, form and tuning."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+        rec = json.loads(next(l for l in text.splitlines() if l.startswith("{")))
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    except (OSError, StopIteration, ValueError):
+        return None
+    if (rec.get("kernels_sha256") != sha or rec.get("workload") != workload or
+            rec.get("form") != form or rec.get("family") != family or rec.get("tuning") != tuning):
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
+def _roofline(kern, head, steps, workload=None, tuning=None):
     dom = max(("density", "hs"), key=lambda k: kern.get(k, {}).get("ms_per_step", 0.0))
     kd = kern[dom]
     achieved = kd["work_flop"] / (kd["ms_per_step"] * steps * 1e-3) / 1e12
     return {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[head],
-            "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[head], "traffic": None,
-            "avg_launch_ms": kd["avg_launch_ms"], "launches_per_step": kd["launches"] / steps}
+            "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[head],
+            "traffic": _measured_traffic(workload, head, dom, tuning),
+            "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+            "avg_launch_ms": kd["avg_launch_ms"], "launches_per_step": kd["launches"] / steps,
+            "work_flop_per_launch": kd["work_flop"] / kd["launches"]}
 
 
 def _forms_summary(res):
@@ -144,6 +170,8 @@ def bench_single(args, torch, inst, backward=False):
     dev = torch.device("cuda", 0)
     t0 = time.time()
     g = AimsGrid(inst, device=0)
+    torch.cuda.synchronize()
+    setup_s = time.time() - t0
     ws = g.work_stats()
     F = ws["flops_per_step"] * (2.0 if backward else 1.0)
     _log(f"setup {time.time() - t0:.1f} s, {ws['n_batches']} batches, F = {F:.3e} flop/step")
@@ -156,9 +184,12 @@ def bench_single(args, torch, inst, backward=False):
     timer = Timer(torch, g.stream)
 
     forms = ["fp64"] + [f for f in args.forms.split(",") if f and f != "fp64"]
+    fixed = json.loads(args.tuning) if args.tuning else {}
     res = {}
     for prec in forms:
-        if not args.no_autotune:
+        if prec in fixed:
+            g.set_tuning(prec=prec, **fixed[prec])
+        elif not args.no_autotune:
             t0 = time.time()
             r = autotune(g, P, v, prec=prec, reps=2, cache="")   # measured here, never cached
             _log(f"{prec}: autotuned {dict((k, r[k]) for k in ('h_merge', 'density_pblocks', 'persistent'))}"
@@ -182,12 +213,17 @@ def bench_single(args, torch, inst, backward=False):
         g.profile(False)
         s = sums.cpu().numpy()[0]
         res[prec] = {"ms_per_step": ms, "wall_ms_per_step": wall, "gflops": F / (ms * 1e-3) / 1e9,
+                     "ms_per_step_median": timer.last["median"], "ms_per_step_min": timer.last["min"],
                      "N": float(s[0]), "E": float(s[1] + s[2]), "kernels": kern,
                      "tuning": g.get_tuning(prec)}
         _log(f"{prec}: {ms:.3f} ms/step, {res[prec]['gflops']:.1f} GFLOP/s")
 
     head, fastest = _forms_summary(res)
     hr = res[head]
+    # outside the step: the overlap matrix (computed once per geometry)
+    S = torch.empty(g.mat_elems, dtype=torch.float64, device=dev)
+    g.set_tuning(prec="fp64", **res["fp64"]["tuning"])
+    ms_S, _ = timer.run(lambda: g.integrate_h(v, prec="fp64", H_out=H, S_out=S, want_S=True), 3, 1)
     line = {
         "metric": "H+density integration GFLOP/s and ms per SCF step (fastest form within 1e-6 Ha "
                   "of FP64; mixed forms reported beside it)" if not backward else
@@ -199,7 +235,8 @@ def bench_single(args, torch, inst, backward=False):
         "config": {"workload": WORKLOADS[args.workload], "n_points": inst.n_points,
                    "n_basis": inst.n_basis, "n_batches": ws["n_batches"], "flop_per_step": F,
                    "sum_np_nb2": ws["sum_np_nb2"], "parallelism": "single GPU"},
-        "forms": {p: {k: r[k] for k in ("ms_per_step", "wall_ms_per_step", "gflops",
+        "forms": {p: {k: r[k] for k in ("ms_per_step", "ms_per_step_median", "ms_per_step_min",
+                                         "wall_ms_per_step", "gflops",
                                          "abs_dE_Ha_vs_fp64", "meets_1e-6_Ha", "rel_dN_vs_fp64",
                                          "tuning", "E", "N")}
                   for p, r in res.items()},
@@ -207,8 +244,9 @@ def bench_single(args, torch, inst, backward=False):
                          "gflops": res[fastest]["gflops"],
                          "speedup_vs_fp64": res["fp64"]["ms_per_step"] / res[fastest]["ms_per_step"]},
         "kernels": {p: r["kernels"] for p, r in res.items()},
-        "autotuned": not args.no_autotune,
-        "roofline": _roofline(hr["kernels"], head, args.steps),
+        "autotuned": {p: (p not in fixed and not args.no_autotune) for p in forms},
+        "outside_step": {"setup_s": setup_s, "ms_integrate_h_with_S_fp64": ms_S},
+        "roofline": _roofline(hr["kernels"], head, args.steps, args.workload, hr["tuning"]),
     }
     if args.cpu_chunks > 0:
         _log("CPU baseline (oracle sample)...")
@@ -317,7 +355,10 @@ def main():
                     help="precision forms to time (fp64 is always included)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the library's default tuning instead of the autotuner's choice")
-    ap.add_argument("--cpu-chunks", type=int, default=10,
+    ap.add_argument("--tuning", default="",
+                    help='fixed tuning per form instead of the autotuner, as JSON, e.g. '
+                         '\'{"fp64": {"h_merge": 1, "density_pblocks": 2, "persistent": 1}}\'')
+    ap.add_argument("--cpu-chunks", type=int, default=120,
                     help="point chunks of the oracle's CPU baseline sample (0 = skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 launches): the reference "
