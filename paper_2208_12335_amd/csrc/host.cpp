@@ -940,12 +940,14 @@ aims_status aims_integrate_h_backward(aims_grid* g, aims_precision prec, const d
       hipchk(launch_scale(dE_dP_or_null, dE_dP_or_null, (size_t)g->mat_total, gE, st), "scale dE/dP");
     }
     if (!dE_dv_or_null && !dE_dR_or_null) return;
-    // the density pass provides n (for dE/dv) and the FP32 copy of P for the mixed forms
-    density_call(g, prec, P, v, g->d_ntmp, g->d_sums_tmp);
-    if (dE_dv_or_null)
+    if (!dE_dR_or_null) {
+      // n (for dE/dv) from a plain density pass
+      density_call(g, prec, P, v, g->d_ntmp, g->d_sums_tmp);
       hipchk(launch_dv(g->dens.dv, dE_dv_or_null, g->d_n_sorted, g->n_points, gE, st), "dE/dv");
-    if (!dE_dR_or_null) return;
-    // dE/dR: X = Phi P_b and Y = (T Phi) P_b per batch, then the Pulay reduction
+      return;
+    }
+    // dE/dR: X = Phi P_b (whose pass also forms n, for dE/dv) and Y = (T Phi) P_b per batch,
+    // then the Pulay reduction
     BatchSet& bs = g->dens;
     if (g->slab_cap34 < bs.slab_elems) {
       if (g->d_slab3) g->release(g->d_slab3);
@@ -956,12 +958,16 @@ aims_status aims_integrate_h_backward(aims_grid* g, aims_precision prec, const d
       g->d_slab4 = g->alloc(bs.slab_elems * sizeof(double));
       g->slab_cap34 = bs.slab_elems;
     }
+    const bool mixed = prec != AIMS_FP64;
+    if (mixed) hipchk(launch_convert_f32(P, g->d_P32, (size_t)g->mat_total, st), "convert P");
+    hipchk(launch_fill(g->d_n_sorted, (size_t)g->n_points, 0.0, st), "fill n");
+    hipchk(launch_fill(g->d_et_batch, bs.batches.size(), 0.0, st), "fill E_T");
     hipchk(launch_fill(dE_dR_or_null, 3 * (size_t)g->n_atoms, 0.0, st), "fill dE/dR");
     const ItemList& L = items_for(g, bs, g->d_pblocks[prec]);
     for (size_t gi = 0; gi < bs.groups.size(); ++gi) {
       const auto& gr = bs.groups[gi];
       const int nbt = gr.b1 - gr.b0;
-      if (prec == AIMS_FP64) {
+      if (!mixed) {
         double *s1 = (double*)g->d_slab1, *s2 = (double*)g->d_slab2;
         double *s3 = (double*)g->d_slab3, *s4 = (double*)g->d_slab4;
         timed(g, kProfPhi, 0.0, "phi_eval", [&] {
@@ -970,8 +976,8 @@ aims_status aims_integrate_h_backward(aims_grid* g, aims_precision prec, const d
         for (const auto& run : L.runs[gi]) {
           const int nit = (int)(run.i1 - run.i0);
           timed(g, kProfBackward, gr.flops / L.runs[gi].size(), "X", [&] {
-            return launch_density<double>(bs.dv, run.nbn, L.d_items + run.i0, nit, P, s1, s1, nullptr,
-                                          nullptr, st, s3);
+            return launch_density<double>(bs.dv, run.nbn, L.d_items + run.i0, nit, P, s1, s2,
+                                          g->d_n_sorted, g->d_et_batch, st, s3);
           });
           timed(g, kProfBackward, gr.flops / L.runs[gi].size(), "Y", [&] {
             return launch_density<double>(bs.dv, run.nbn, L.d_items + run.i0, nit, P, s2, s2, nullptr,
@@ -996,14 +1002,17 @@ aims_status aims_integrate_h_backward(aims_grid* g, aims_precision prec, const d
         for (const auto& run : L.runs[gi]) {
           const int nit = (int)(run.i1 - run.i0);
           for (int which = 0; which < 2; ++which) {
-            void* src = which == 0 ? g->d_slab1 : g->d_slab2;
+            const void* src = which == 0 ? g->d_slab1 : g->d_slab2;
             float* dst = which == 0 ? s3 : s4;
+            double* nout = which == 0 ? g->d_n_sorted : nullptr;
+            double* eout = which == 0 ? g->d_et_batch : nullptr;
             timed(g, kProfBackward, gr.flops / L.runs[gi].size(), "XY", [&] {
               if (prec == AIMS_BF16X3)
-                return launch_density_bf16(bs.dv, run.nbn, L.d_items + run.i0, nit, g->d_P32, src, src,
-                                           nullptr, nullptr, st, dst);
+                return launch_density_bf16(bs.dv, run.nbn, L.d_items + run.i0, nit, g->d_P32, src,
+                                           g->d_slab2, nout, eout, st, dst);
               return launch_density<float>(bs.dv, run.nbn, L.d_items + run.i0, nit, g->d_P32,
-                                           (const float*)src, (const float*)src, nullptr, nullptr, st, dst);
+                                           (const float*)src, (const float*)g->d_slab2, nout, eout,
+                                           st, dst);
             });
           }
         }
@@ -1012,6 +1021,8 @@ aims_status aims_integrate_h_backward(aims_grid* g, aims_precision prec, const d
         });
       }
     }
+    if (dE_dv_or_null)
+      hipchk(launch_dv(g->dens.dv, dE_dv_or_null, g->d_n_sorted, g->n_points, gE, st), "dE/dv");
   });
 }
 

@@ -47,7 +47,8 @@ hipError_t launch_phi_eval(const DeviceView& dv, int b0, int nbatch, int mode, c
 hipError_t launch_phi_eval_bf16(const DeviceView& dv, int b0, int nbatch, int mode, const double* v,
                                 void* slab1, void* slab2, hipStream_t st);
 // nbn: point tile = 32 * nbn points (2..5)
-// xout != NULL: store X^T = P_b slab1 into xout (function-major slab) instead of forming n
+// xout != NULL: store X^T = P_b slab1 into xout (function-major slab); n and the E_T partials
+// are formed as well unless n_sorted is NULL
 template <typename T>
 hipError_t launch_density(const DeviceView& dv, int nbn, const TileItem* items, int n_items, const T* P,
                           const T* slab1, const T* slab2, double* n_sorted, double* et_batch,

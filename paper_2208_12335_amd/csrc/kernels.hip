@@ -95,6 +95,26 @@ struct SlabStore<float, kLayoutBfFn> {
   }
 };
 
+// One shell of angular momentum L (compile-time, so only that harmonic's registers are live).
+template <typename T, int L, typename Store>
+__device__ __forceinline__ void eval_shell(const T* __restrict__ c, T dt, T ux, T uy, T uz, int mode,
+                                           T w, T wv, int f, int p, const Store& store) {
+  const T R = cubic(c, dt);
+  const T K = cubic(c + 4, dt);
+  T Y[7];
+  ylm_l<T>(L, ux, uy, uz, Y);
+#pragma unroll
+  for (int m = 0; m < 2 * L + 1; ++m) {
+    const T phi = R * Y[m];
+    const T tphi = K * Y[m];
+    T second;
+    if (mode == kModeDensity) second = tphi;
+    else if (mode == kModeH) second = wv * phi + w * tphi;
+    else second = w * phi;
+    store(f + m, p, phi, second);
+  }
+}
+
 template <typename T, typename Store>
 __device__ __forceinline__ void eval_atom_point(double dx, double dy, double dz,
                                                 const SpeciesDesc& sd,
@@ -115,22 +135,14 @@ __device__ __forceinline__ void eval_atom_point(double dx, double dy, double dz,
   const T* c = spline + sd.spline_off + (size_t)rp.k * sd.nshell * 8;
   int f = col0;
   for (int j = 0; j < sd.nshell; ++j) {
-    const T R = cubic(c + j * 8, dt);
-    const T K = cubic(c + j * 8 + 4, dt);
     const int l = shell_l[sd.shell_l_off + j];
-    T Y[7];
-    ylm_l<T>(l, ux, uy, uz, Y);
-    const int nm = 2 * l + 1;
-    for (int m = 0; m < nm; ++m) {
-      const T phi = R * Y[m];
-      const T tphi = K * Y[m];
-      T second;
-      if (mode == kModeDensity) second = tphi;
-      else if (mode == kModeH) second = wv * phi + w * tphi;
-      else second = w * phi;
-      store(f + m, p, phi, second);
+    switch (l) {
+      case 0: eval_shell<T, 0>(c + j * 8, dt, ux, uy, uz, mode, w, wv, f, p, store); break;
+      case 1: eval_shell<T, 1>(c + j * 8, dt, ux, uy, uz, mode, w, wv, f, p, store); break;
+      case 2: eval_shell<T, 2>(c + j * 8, dt, ux, uy, uz, mode, w, wv, f, p, store); break;
+      default: eval_shell<T, 3>(c + j * 8, dt, ux, uy, uz, mode, w, wv, f, p, store); break;
     }
-    f += nm;
+    f += 2 * l + 1;
   }
 }
 
@@ -418,7 +430,8 @@ density_tile(int item, const TileItem* __restrict__ items, int n_items, const Ba
     __syncthreads();
   }
 
-  if (xout) {   // store mode (backward): X^T[j][p] into a function-major slab
+  if (xout) {   // store mode (backward): X^T[j][p] into a function-major slab, and, with a
+                // density output, the epilogue as well
 #pragma unroll
     for (int ni = 0; ni < NBN; ++ni) {
       const int p = p0 + wn * 16 * NBN + ni * 16 + (lane & 15);
@@ -431,7 +444,7 @@ density_tile(int item, const TileItem* __restrict__ items, int n_items, const Ba
           if (j < nb) xout[d.slab_off + (size_t)j * ldp + p] = acc[mi][ni][r];
         }
     }
-    return;
+    if (!n_sorted) return;      // else also the density epilogue below
   }
   // epilogue: column sums of X^T o Phi^T (density) and of w X^T o tPhi^T (kinetic energy)
   double sn[NBN], se = 0.0;
@@ -763,7 +776,7 @@ density_tile_bf16(int item, const TileItem* __restrict__ items, int n_items, con
           if (j < nb) xout[d.slab_off + (size_t)j * ldp + p] = acc[mi][ni][rr];
         }
     }
-    return;
+    if (!n_sorted) return;      // else also the density epilogue below
   }
   double sn[NBN], se = 0.0;
 #pragma unroll
@@ -921,11 +934,40 @@ hs_kernel_bf16(const TileItem* __restrict__ items, int n_items, const BatchDesc*
 // Backward: Pulay-type forces from basis gradients.  For every (point, relevant atom) pair the
 // radial functions, their derivatives and the solid-harmonic gradients are recomputed and
 //   g_a += w_p sum_{i on a} [(2 v_p X_pi + Y_pi) grad phi_i(p) + X_pi grad tphi_i(p)]
-// with grad phi = (R' - l R/r) Y_lm u + (R/r) grad S_lm(u) (same with K for t phi); the batch's
-// per-atom sums are reduced in LDS (FP64 atomics) and dE/dR_a -= gE g_a is added in FP64.
+// with grad phi = (R' - l R/r) Y_lm u + (R/r) grad S_lm(u) (same with K for t phi); each
+// atom's sum over a batch's points is reduced across a wave and dE/dR_a -= gE g_a is added
+// with FP64 atomics.
 // ------------------------------------------------------------------------------------------
-constexpr int kPulayAtoms = 512;       // per-batch atom accumulators held in LDS
+// One shell of angular momentum L (a compile-time constant, so that only that harmonic's
+// registers are live): adds its functions' terms of the per-point gradient sum.
+template <typename T, int L>
+__device__ __forceinline__ void pulay_shell(const T* __restrict__ c, T dt, T ir, T ux, T uy, T uz,
+                                            T two_v, const T* __restrict__ X,
+                                            const T* __restrict__ Y, size_t o0, int ldp, T& gx,
+                                            T& gy, T& gz) {
+  const T R = cubic(c, dt), dR = cubic_d(c, dt) * ir;
+  const T K = cubic(c + 4, dt), dK = cubic_d(c + 4, dt) * ir;
+  T Yl[7], Gx[7], Gy[7], Gz[7];
+  ylm_l<T>(L, ux, uy, uz, Yl);
+  ylm_grad_l<T>(L, ux, uy, uz, Gx, Gy, Gz);
+  const T aR = dR - T(L) * R * ir, aK = dK - T(L) * K * ir;
+  const T bR = R * ir, bK = K * ir;
+#pragma unroll
+  for (int m = 0; m < 2 * L + 1; ++m) {
+    const size_t o = o0 + (size_t)m * ldp;
+    const T xv = X[o], yv = Y[o];
+    const T cp = two_v * xv + yv;        // multiplies grad phi
+    const T ru = (cp * aR + xv * aK) * Yl[m];   // radial part, along u
+    const T rs = cp * bR + xv * bK;             // angular part, along grad S
+    gx += ru * ux + rs * Gx[m];
+    gy += ru * uy + rs * Gy[m];
+    gz += ru * uz + rs * Gz[m];
+  }
+}
 
+// Work mapping as in the basis evaluation: kPhiSlices workgroups per batch, one relevant atom
+// per wave at a time, lanes over the batch's points; each wave reduces its atom's gradient
+// across lanes and adds -gE g_a to dE/dR_a with three FP64 atomics.
 template <typename T>
 __global__ void __launch_bounds__(256)
 pulay_kernel(const BatchDesc* __restrict__ batches, int b0, const double4* __restrict__ pts,
@@ -935,77 +977,60 @@ pulay_kernel(const BatchDesc* __restrict__ batches, int b0, const double4* __res
              const int32_t* __restrict__ shell_l, const T* __restrict__ spline, RadialGrid rg,
              const double* __restrict__ v, const T* __restrict__ Xs, const T* __restrict__ Ys,
              const double* __restrict__ gE, double* __restrict__ dE_dR) {
-  __shared__ double g[kPulayAtoms * 3];
-  const BatchDesc d = batches[b0 + blockIdx.x];
+  const int bi = blockIdx.x / kPhiSlices;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(blockIdx.x % kPhiSlices) * 4 + (int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  const BatchDesc d = batches[b0 + bi];
   const int np = d.n_p, na = d.n_atoms, ldp = d.ldp;
-  const bool in_lds = na <= kPulayAtoms;
-  if (in_lds)
-    for (int t = threadIdx.x; t < 3 * na; t += blockDim.x) g[t] = 0.0;
-  __syncthreads();
   const T* X = Xs + d.slab_off;
   const T* Y = Ys + d.slab_off;
   const double ge = gE[0];
-  const int pairs = np * na;
-  for (int q = threadIdx.x; q < pairs; q += blockDim.x) {
-    const int k = q / np;
-    const int p = q - k * np;
+  for (int k = wave; k < na; k += 4 * kPhiSlices) {
     const int atom = batch_atoms[d.atom_off + k];
     const int col0 = batch_acol[d.atom_off + k];
     const SpeciesDesc sd = species[atom_species[atom]];
-    const double4 P4 = pts[d.pt_off + p];
-    const double dx = P4.x - atom_xyz[3 * atom], dy = P4.y - atom_xyz[3 * atom + 1],
-                 dz = P4.z - atom_xyz[3 * atom + 2];
-    const double r = sqrt(dx * dx + dy * dy + dz * dz);
-    if (!(r < rg.rc)) continue;
-    const double rr = fmax(r, 1e-12);
-    const double inv = 1.0 / rr;
-    const T ux = T(dx * inv), uy = T(dy * inv), uz = T(dz * inv), ir = T(inv);
-    const RadialPos rp = radial_pos(rr, rg);
-    const T dt = T(rp.dt);
-    const T* c = spline + sd.spline_off + (size_t)rp.k * sd.nshell * 8;
-    const T two_v = T(2.0 * v[perm[d.pt_off + p]]);
-    T gx = 0, gy = 0, gz = 0;
-    int f = col0;
-    for (int j = 0; j < sd.nshell; ++j) {
-      const T R = cubic(c + j * 8, dt), dR = cubic_d(c + j * 8, dt) * ir;
-      const T K = cubic(c + j * 8 + 4, dt), dK = cubic_d(c + j * 8 + 4, dt) * ir;
-      const int l = shell_l[sd.shell_l_off + j];
-      T Yl[7], Gx[7], Gy[7], Gz[7];
-      ylm_l<T>(l, ux, uy, uz, Yl);
-      ylm_grad_l<T>(l, ux, uy, uz, Gx, Gy, Gz);
-      const T aR = dR - T(l) * R * ir, aK = dK - T(l) * K * ir;
-      const T bR = R * ir, bK = K * ir;
-      const int nm = 2 * l + 1;
-      for (int m = 0; m < nm; ++m) {
-        const size_t o = (size_t)(f + m) * ldp + p;
-        const T xv = X[o], yv = Y[o];
-        const T cp = two_v * xv + yv;      // multiplies grad phi
-        // radial parts along u, angular parts along grad S
-        const T ru = cp * aR * Yl[m] + xv * aK * Yl[m];
-        const T rs = cp * bR + xv * bK;
-        gx += ru * ux + rs * Gx[m];
-        gy += ru * uy + rs * Gy[m];
-        gz += ru * uz + rs * Gz[m];
+    const double ax = atom_xyz[3 * atom], ay = atom_xyz[3 * atom + 1], az = atom_xyz[3 * atom + 2];
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int p = lane; p < np; p += 64) {
+      const double4 P4 = pts[d.pt_off + p];
+      const double dx = P4.x - ax, dy = P4.y - ay, dz = P4.z - az;
+      const double r = sqrt(dx * dx + dy * dy + dz * dz);
+      if (!(r < rg.rc)) continue;
+      const double rr = fmax(r, 1e-12);
+      const double inv = 1.0 / rr;
+      const T ux = T(dx * inv), uy = T(dy * inv), uz = T(dz * inv), ir = T(inv);
+      const RadialPos rp = radial_pos(rr, rg);
+      const T dt = T(rp.dt);
+      const T* c = spline + sd.spline_off + (size_t)rp.k * sd.nshell * 8;
+      const T two_v = T(2.0 * v[perm[d.pt_off + p]]);
+      T gx = 0, gy = 0, gz = 0;
+      int f = col0;
+      for (int j = 0; j < sd.nshell; ++j) {
+        const int l = shell_l[sd.shell_l_off + j];
+        const size_t o0 = (size_t)f * ldp + p;
+        switch (l) {
+          case 0: pulay_shell<T, 0>(c + j * 8, dt, ir, ux, uy, uz, two_v, X, Y, o0, ldp, gx, gy, gz); break;
+          case 1: pulay_shell<T, 1>(c + j * 8, dt, ir, ux, uy, uz, two_v, X, Y, o0, ldp, gx, gy, gz); break;
+          case 2: pulay_shell<T, 2>(c + j * 8, dt, ir, ux, uy, uz, two_v, X, Y, o0, ldp, gx, gy, gz); break;
+          default: pulay_shell<T, 3>(c + j * 8, dt, ir, ux, uy, uz, two_v, X, Y, o0, ldp, gx, gy, gz); break;
+        }
+        f += 2 * l + 1;
       }
-      f += nm;
+      sx += P4.w * (double)gx;
+      sy += P4.w * (double)gy;
+      sz += P4.w * (double)gz;
     }
-    const double w = P4.w;
-    if (in_lds) {
-      atomicAdd(&g[3 * k], w * (double)gx);
-      atomicAdd(&g[3 * k + 1], w * (double)gy);
-      atomicAdd(&g[3 * k + 2], w * (double)gz);
-    } else {
-      unsafeAtomicAdd(dE_dR + 3 * atom, -ge * w * (double)gx);
-      unsafeAtomicAdd(dE_dR + 3 * atom + 1, -ge * w * (double)gy);
-      unsafeAtomicAdd(dE_dR + 3 * atom + 2, -ge * w * (double)gz);
+    for (int off = 32; off > 0; off >>= 1) {
+      sx += __shfl_xor(sx, off);
+      sy += __shfl_xor(sy, off);
+      sz += __shfl_xor(sz, off);
+    }
+    if (lane == 0) {
+      unsafeAtomicAdd(dE_dR + 3 * atom, -ge * sx);
+      unsafeAtomicAdd(dE_dR + 3 * atom + 1, -ge * sy);
+      unsafeAtomicAdd(dE_dR + 3 * atom + 2, -ge * sz);
     }
   }
-  __syncthreads();
-  if (in_lds)
-    for (int t = threadIdx.x; t < 3 * na; t += blockDim.x) {
-      const int atom = batch_atoms[d.atom_off + t / 3];
-      unsafeAtomicAdd(dE_dR + 3 * atom + t % 3, -ge * g[t]);
-    }
 }
 
 // y[i] = gE * x[i]
@@ -1251,7 +1276,7 @@ hipError_t launch_pulay(const DeviceView& dv, int b0, int nbatch, const double* 
                         const T* Y, const double* gE, double* dE_dR, hipStream_t st) {
   if (nbatch == 0) return hipSuccess;
   const T* spline = (const T*)(sizeof(T) == 8 ? (const void*)dv.spline64 : (const void*)dv.spline32);
-  hipLaunchKernelGGL(pulay_kernel<T>, dim3(nbatch), dim3(256), 0, st, dv.batches, b0, dv.pts,
+  hipLaunchKernelGGL(pulay_kernel<T>, dim3(nbatch * kPhiSlices), dim3(256), 0, st, dv.batches, b0, dv.pts,
                      dv.perm, dv.batch_atoms, dv.batch_acol, dv.atom_xyz, dv.atom_species,
                      dv.species, dv.shell_l, spline, dv.rg, v, X, Y, gE, dE_dR);
   return hipGetLastError();
