@@ -32,9 +32,15 @@ def cluster():
     return synth.make_instance("c2", n_atoms=12, box=8.0, seed=3)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
-def test_persistent_matches_grid_launch(gpu, cluster, prec):
-    print(f"[persistent] {prec} {cluster.n_points} points", flush=True)
+@pytest.mark.parametrize("prec,scratch_mb", [("fp64", None), ("fp32", None), ("bf16x3", None),
+                                              ("fp64", "16"), ("bf16x3", "16")])
+def test_persistent_matches_grid_launch(gpu, cluster, prec, scratch_mb, monkeypatch):
+    """Persistent launches (resident grid, per-XCD work counters) against one workgroup per
+    tile; a 16 MB scratch budget cuts each pass into many groups of batches, so that the
+    counters are cleared and reused across many launches of one call."""
+    if scratch_mb:
+        monkeypatch.setenv("AIMS_SCRATCH_MB", scratch_mb)
+    print(f"[persistent] {prec} {cluster.n_points} points, scratch {scratch_mb}", flush=True)
     g = AimsGrid(cluster, device=gpu.index)
     P = torch.from_numpy(cluster.P).to(gpu).reshape(-1)
     v = torch.from_numpy(cluster.v).to(gpu)
