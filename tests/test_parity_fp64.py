@@ -58,6 +58,22 @@ def test_small_cluster_fp64_parity_multi_tile(gpu, n_atoms, box, seed):
     assert abs(sums[1] + sums[2] - np.sum(inst.P * H)) < 1e-10 * abs(sums[1] + sums[2])
 
 
+@pytest.mark.parametrize("max_batch", [1, 512])
+def test_extreme_batch_sizes(gpu, max_batch):
+    """Single-point batches (every tile ragged, K = 1 point in H) and the largest supported
+    batch (512 points: H tiles with K = 512, density point tiles split into equal blocks)."""
+    import dataclasses
+    base = synth.make_instance("c2", n_atoms=6, box=6.0, seed=7)
+    if max_batch == 1:           # keep the oracle fast: a random subset of 3000 points
+        idx = np.sort(np.random.default_rng(3).choice(base.n_points, 3000, replace=False))
+        base = dataclasses.replace(base, pt_xyz=base.pt_xyz[idx], pt_w=base.pt_w[idx],
+                                   pt_atom=base.pt_atom[idx], v=base.v[idx])
+    inst = dataclasses.replace(base, max_batch=max_batch)
+    g, n, sums, H, S = _check_against_oracle(inst, gpu)
+    assert g.work_stats()["n_batches"] == (inst.n_points if max_batch == 1 else
+                                          g.work_stats()["n_batches"])
+
+
 def test_determinism_and_repeat(gpu, c1):
     _, n1, s1, H1, _ = _run(c1, gpu, want_S=False)
     _, n2, s2, H2, _ = _run(c1, gpu, want_S=False)
