@@ -148,6 +148,11 @@ void aims_step_graph_destroy(aims_step_graph *graph);
  *   density_pblocks  a density work tile covers 64 basis rows and up to 32 * density_pblocks
  *                    points of one batch (2..5); a batch of n_p points is cut into
  *                    ceil(n_p / (32 density_pblocks)) equal tiles.
+ *   h_flops_per_atomic  0: the H/S batches are the fixed merge level above; R > 0: a cost
+ *                    model chooses them (h_merge is then ignored): each node of the set-up
+ *                    bisection, up to 16 x max_batch points, becomes one H batch when
+ *                    2 n_p n_b^2 + R n_b^2 (flops plus R flop-equivalents per FP64 scatter-add)
+ *                    is below the best cost of its two halves.  0..2^20.
  *   persistent       0: one workgroup per work tile (hardware dispatch order, XCD-interleaved);
  *                    1: the tiled density and H/S kernels launch as many workgroups as fit on
  *                    the device at once, and each pulls tiles from eight per-XCD work counters
@@ -159,6 +164,7 @@ typedef struct {
   int32_t h_merge;
   int32_t density_pblocks;
   int32_t persistent;
+  int32_t h_flops_per_atomic;
 } aims_tuning;
 aims_status aims_get_tuning(const aims_grid *g, aims_precision prec, aims_tuning *out);
 aims_status aims_set_tuning(aims_grid *g, aims_precision prec, const aims_tuning *t);

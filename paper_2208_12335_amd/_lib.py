@@ -37,7 +37,8 @@ class AimsSystem(ctypes.Structure):
 
 
 class AimsTuning(ctypes.Structure):
-    _fields_ = [("h_merge", c_int32), ("density_pblocks", c_int32), ("persistent", c_int32)]
+    _fields_ = [("h_merge", c_int32), ("density_pblocks", c_int32), ("persistent", c_int32),
+                ("h_flops_per_atomic", c_int32)]
 
 
 # every symbol the header declares, with its signature

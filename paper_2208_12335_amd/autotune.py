@@ -1,16 +1,18 @@
 """Autotuner of the library's execution parameters, timed on the live device.
 
-Three knobs decide how the batched work of one s.c.f. step maps onto the GPU (the batch
+Four knobs decide how the batched work of one s.c.f. step maps onto the GPU (the batch
 integration scheme itself is fixed by the grid partition):
 
 * ``density_pblocks`` -- the point extent (32 x pblocks) of a density work tile;
 * ``h_merge``        -- how many bisection levels the H/S pass merges (bigger batches, fewer
   FP64 scatter-adds into H, more flops);
+* ``h_flops_per_atomic`` -- instead of a fixed level, a cost-model partition of the H/S pass
+  that charges this many flop-equivalents per scatter-add (0 = fixed level);
 * ``persistent``     -- one workgroup per tile, or a resident grid pulling tiles from per-XCD
   work counters.
 
-The density pass depends only on (pblocks, persistent) and the H pass only on (h_merge,
-persistent), so the tuner times the two passes separately and picks, per ``persistent`` value,
+The density pass depends only on (pblocks, persistent) and the H pass only on its partition
+(h_merge or h_flops_per_atomic) and persistent, so the tuner times the two passes separately and picks, per ``persistent`` value,
 the best of each, then the better ``persistent``.  Results are cached in a JSON file keyed by
 (device architecture, precision, workload bucket) so later handles of a similar workload skip
 the measurement.
@@ -25,7 +27,9 @@ from typing import Callable, Dict, Iterable, Optional, Tuple
 
 DENSITY_PBLOCKS = (2, 3, 4, 5)
 H_MERGE = (0, 1, 2, 3)
+H_RATIO = (64, 256, 1024, 4096)
 PERSISTENT = (0, 1)
+KNOBS = ("h_merge", "density_pblocks", "persistent", "h_flops_per_atomic")
 
 
 def default_cache_path() -> str:
@@ -46,13 +50,15 @@ def workload_key(arch: str, prec: str, n_sys: int, n_points: int, sum_np_nb2: fl
 def search(cost: Callable[[str, dict], float],
            density_pblocks: Iterable[int] = DENSITY_PBLOCKS,
            h_merge: Iterable[int] = H_MERGE,
-           persistent: Iterable[int] = PERSISTENT) -> Tuple[dict, Dict[str, float]]:
+           persistent: Iterable[int] = PERSISTENT,
+           h_ratio: Iterable[int] = H_RATIO) -> Tuple[dict, Dict[str, float]]:
     """Pick the tuning that minimises density time + H time.
 
     ``cost(kind, cfg)`` returns the time of pass ``kind`` ("density" or "h") under ``cfg``
-    (a dict with the three knobs).  Returns (best cfg, {candidate label: ms})."""
+    (a dict with the knobs that pass depends on).  Returns (best cfg, {candidate label: ms})."""
     log: Dict[str, float] = {}
     best, best_t = None, math.inf
+    h_parts = [(m, 0) for m in h_merge] + [(0, r) for r in h_ratio]
     for p in persistent:
         bd, td = None, math.inf
         for pb in density_pblocks:
@@ -61,13 +67,14 @@ def search(cost: Callable[[str, dict], float],
             if t < td:
                 bd, td = pb, t
         bh, th = None, math.inf
-        for m in h_merge:
-            t = float(cost("h", {"h_merge": m, "persistent": p}))
-            log[f"h merge={m} persistent={p}"] = t
+        for m, r in h_parts:
+            t = float(cost("h", {"h_merge": m, "h_flops_per_atomic": r, "persistent": p}))
+            log[f"h merge={m} ratio={r} persistent={p}"] = t
             if t < th:
-                bh, th = m, t
+                bh, th = (m, r), t
         if bd is not None and bh is not None and td + th < best_t:
-            best = {"h_merge": bh, "density_pblocks": bd, "persistent": p}
+            best = {"h_merge": bh[0], "h_flops_per_atomic": bh[1], "density_pblocks": bd,
+                    "persistent": p}
             best_t = td + th
     if best is None:
         raise ValueError("empty candidate set")
@@ -96,7 +103,8 @@ def store_cache(path: str, key: str, entry: dict) -> None:
 
 def autotune(grid, P, v, prec: str = "fp64", *, reps: int = 3, cache: Optional[str] = None,
              force: bool = False, density_pblocks: Iterable[int] = DENSITY_PBLOCKS,
-             h_merge: Iterable[int] = H_MERGE, persistent: Iterable[int] = PERSISTENT) -> dict:
+             h_merge: Iterable[int] = H_MERGE, persistent: Iterable[int] = PERSISTENT,
+             h_ratio: Iterable[int] = H_RATIO) -> dict:
     """Time the candidates on ``grid``'s device with inputs P, v (device tensors), apply the
     best tuning for ``prec`` and return {tuning..., "source": "cache"|"measured", "key": ...,
     "ms": {...}}.  ``cache=""`` disables the cache file."""
@@ -109,9 +117,8 @@ def autotune(grid, P, v, prec: str = "fp64", *, reps: int = 3, cache: Optional[s
     path = default_cache_path() if cache is None else cache
     if path and not force:
         hit = load_cache(path).get(key)
-        if hit and all(k in hit for k in ("h_merge", "density_pblocks", "persistent")):
-            grid.set_tuning(h_merge=hit["h_merge"], density_pblocks=hit["density_pblocks"],
-                            persistent=hit["persistent"], prec=prec)
+        if hit and all(k in hit for k in KNOBS):
+            grid.set_tuning(prec=prec, **{k: hit[k] for k in KNOBS})
             return dict(hit, source="cache", key=key)
 
     n = torch.empty(grid.n_points, dtype=torch.float64, device=grid.device)
@@ -128,6 +135,7 @@ def autotune(grid, P, v, prec: str = "fp64", *, reps: int = 3, cache: Optional[s
 
     def cost(kind, cfg):
         grid.set_tuning(h_merge=cfg.get("h_merge", cur["h_merge"]),
+                        h_flops_per_atomic=cfg.get("h_flops_per_atomic", cur["h_flops_per_atomic"]),
                         density_pblocks=cfg.get("density_pblocks", cur["density_pblocks"]),
                         persistent=cfg["persistent"], prec=prec)
         run(kind)                                   # warm (first use builds the work lists)
@@ -140,7 +148,7 @@ def autotune(grid, P, v, prec: str = "fp64", *, reps: int = 3, cache: Optional[s
         e1.synchronize()
         return e0.elapsed_time(e1) / reps
 
-    best, log = search(cost, density_pblocks, h_merge, persistent)
+    best, log = search(cost, density_pblocks, h_merge, persistent, h_ratio)
     grid.set_tuning(prec=prec, **best)
     entry = dict(best, ms=log)
     if path:

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <iterator>
+#include <map>
 #include <atomic>
 #include <cmath>
 #include <cstdarg>
@@ -153,6 +155,7 @@ struct ItemList {
 
 struct BatchSet {
   int merge = 0;
+  int ratio = 0;                   // > 0: cost-model partition (flop-equivalents per scatter-add)
   bool density = false;            // tile lists for the density kernel (else for the H kernel)
   std::vector<BatchDesc> batches;
   std::vector<int32_t> batch_atoms, batch_acol, batch_cols;
@@ -194,6 +197,7 @@ struct aims_grid {
   BatchSet dens;                              // density partition (merge 0)
   std::vector<std::unique_ptr<BatchSet>> hsets;  // H partitions by merge level (built on demand)
   int h_merge[3] = {1, 2, 2};                 // per precision
+  int h_ratio[3] = {0, 0, 0};                 // per precision: > 0 selects the cost-model H partition
   int d_pblocks[3] = {2, 5, 5};               // per precision: density point-tile cap
   int persistent[3] = {0, 0, 0};              // per precision: persistent tile launches
   int* d_queue = nullptr;                     // 8 work counters per tiled launch of one call
@@ -325,14 +329,74 @@ void segments(int64_t lo, int64_t hi, int64_t maxb, std::vector<std::pair<int64_
   segments(mid, hi, maxb, out);
 }
 
-void build_set(aims_grid* g, BatchSet& bs, int merge, bool density) {
+// Cost-model partition of one system for the H pass.  Every node of the set-up bisection (a
+// contiguous point range) may become one H batch of up to 16 x max_batch points; its relevant
+// atoms are the union of its children's (an atom is relevant to a range iff it is relevant to
+// one of its points), so the density batches' exact screening gives every node's basis size
+// n_b.  A node of n points costs 2 n n_b^2 flops plus `ratio` flop-equivalents for each of its
+// n_b^2 FP64 scatter-adds into H; a bottom-up pass keeps a node whole when that is cheaper than
+// the best partitions of its two halves.
+struct NodeCost {
+  double cost;
+  std::vector<int32_t> atoms;                         // sorted, system-local
+  std::vector<std::pair<int64_t, int64_t>> segs;      // chosen H batches of the subtree
+};
+
+NodeCost cost_partition(int64_t lo, int64_t hi, int64_t maxb, int64_t cap, double ratio,
+                        const std::map<int64_t, const std::vector<int32_t>*>& leaf_atoms,
+                        const std::vector<int>& nfn) {
+  NodeCost r;
+  if (hi - lo <= maxb) {
+    auto it = leaf_atoms.find(lo);
+    if (it != leaf_atoms.end()) r.atoms = *it->second;
+  } else {
+    const int64_t mid = lo + (hi - lo) / 2;
+    NodeCost a = cost_partition(lo, mid, maxb, cap, ratio, leaf_atoms, nfn);
+    NodeCost b = cost_partition(mid, hi, maxb, cap, ratio, leaf_atoms, nfn);
+    std::set_union(a.atoms.begin(), a.atoms.end(), b.atoms.begin(), b.atoms.end(),
+                   std::back_inserter(r.atoms));
+    r.cost = a.cost + b.cost;
+    r.segs = std::move(a.segs);
+    r.segs.insert(r.segs.end(), b.segs.begin(), b.segs.end());
+  }
+  double nb = 0;
+  for (int32_t at : r.atoms) nb += nfn[at];
+  const double own = 2.0 * (double)(hi - lo) * nb * nb + ratio * nb * nb;
+  if (hi - lo <= maxb || (hi - lo <= cap && own <= r.cost)) {
+    r.cost = own;
+    r.segs.assign(1, {lo, hi});
+  }
+  return r;
+}
+
+void build_set(aims_grid* g, BatchSet& bs, int merge, bool density, int ratio = 0) {
   bs.merge = merge;
+  bs.ratio = ratio;
   bs.density = density;
   const double reach = g->rg.rc + g->margin;
   for (int k = 0; k < g->n_sys; ++k) {
     const int64_t base = g->sys_pt_range[2 * k], end = g->sys_pt_range[2 * k + 1];
     std::vector<std::pair<int64_t, int64_t>> segs;
-    segments(base, end, (int64_t)g->sys_max_batch[k] << merge, segs);
+    if (ratio > 0 && !density) {
+      // leaves: the density batches of this system and their screened atoms
+      const int a0k = g->systems[k].atom_off;
+      std::vector<std::vector<int32_t>> leaf_lists;
+      std::map<int64_t, const std::vector<int32_t>*> leaf_atoms;
+      leaf_lists.reserve(g->dens.batches.size());
+      for (const BatchDesc& d : g->dens.batches) {
+        if (d.sys != k) continue;
+        std::vector<int32_t> at(g->dens.batch_atoms.begin() + d.atom_off,
+                                g->dens.batch_atoms.begin() + d.atom_off + d.n_atoms);
+        for (auto& x : at) x -= a0k;
+        std::sort(at.begin(), at.end());
+        leaf_lists.push_back(std::move(at));
+        leaf_atoms[d.pt_off] = &leaf_lists.back();
+      }
+      const int64_t maxb = g->sys_max_batch[k];
+      segs = cost_partition(base, end, maxb, maxb << 4, (double)ratio, leaf_atoms, g->atom_nfn[k]).segs;
+    } else {
+      segments(base, end, (int64_t)g->sys_max_batch[k] << merge, segs);
+    }
     const int nseg = (int)segs.size();
     const int a0 = g->systems[k].atom_off;
     const int na = (int)g->atom_nfn[k].size();
@@ -491,11 +555,12 @@ ItemList& items_for(aims_grid* g, BatchSet& bs, int pblocks) {
   return *bs.lists.back();
 }
 
-BatchSet& hset(aims_grid* g, int merge) {
+BatchSet& hset(aims_grid* g, int merge, int ratio = 0) {
+  if (ratio > 0) merge = 0;
   for (auto& p : g->hsets)
-    if (p->merge == merge) return *p;
+    if (p->merge == merge && p->ratio == ratio) return *p;
   std::unique_ptr<BatchSet> bs(new BatchSet());
-  build_set(g, *bs, merge, false);
+  build_set(g, *bs, merge, false, ratio);
   items_for(g, *bs, 0);
   g->hsets.push_back(std::move(bs));
   return *g->hsets.back();
@@ -635,7 +700,7 @@ aims_grid* build(const aims_system* sys, int n_sys, int device, void* stream) {
   for (int p = 0; p < 3; ++p) items_for(g.get(), g->dens, g->d_pblocks[p]);
   g->d_P32 = (float*)g->alloc(std::max<int64_t>(1, g->mat_total) * sizeof(float));
   // the H partitions of the default merge levels
-  for (int p = 0; p < 3; ++p) hset(g.get(), g->h_merge[p]);
+  for (int p = 0; p < 3; ++p) hset(g.get(), g->h_merge[p], g->h_ratio[p]);
   return g.release();
 }
 
@@ -799,7 +864,7 @@ void run_density(aims_grid* g, aims_precision prec, const T* P, const double* v,
 template <typename T>
 void run_hs(aims_grid* g, aims_precision prec, int mode, const double* v, double* out) {
   hipStream_t st = g->stream;
-  BatchSet& bs = hset(g, g->h_merge[prec]);
+  BatchSet& bs = hset(g, g->h_merge[prec], g->h_ratio[prec]);
   const ItemList& L = items_for(g, bs, 0);
   hipchk(launch_fill(out, (size_t)g->mat_total, 0.0, st), "fill H");
   QueueSeq qs(g, L, prec);
@@ -1107,6 +1172,7 @@ aims_status aims_get_tuning(const aims_grid* g, aims_precision prec, aims_tuning
   if (!g || !out || prec < AIMS_FP64 || prec > AIMS_BF16X3) return AIMS_ERR_ARG;
   memset(out, 0, sizeof(*out));
   out->h_merge = g->h_merge[prec];
+  out->h_flops_per_atomic = g->h_ratio[prec];
   out->density_pblocks = g->d_pblocks[prec];
   out->persistent = g->persistent[prec];
   return AIMS_OK;
@@ -1118,9 +1184,12 @@ aims_status aims_set_tuning(aims_grid* g, aims_precision prec, const aims_tuning
     if (t->h_merge < 0 || t->h_merge > 4) fail(AIMS_ERR_ARG, "h_merge must be in 0..4");
     if (t->density_pblocks < 2 || t->density_pblocks > 5) fail(AIMS_ERR_ARG, "density_pblocks must be in 2..5");
     if (t->persistent != 0 && t->persistent != 1) fail(AIMS_ERR_ARG, "persistent must be 0 or 1");
-    hset(g, t->h_merge);
+    if (t->h_flops_per_atomic < 0 || t->h_flops_per_atomic > (1 << 20))
+      fail(AIMS_ERR_ARG, "h_flops_per_atomic must be in 0..2^20");
+    hset(g, t->h_merge, t->h_flops_per_atomic);
     items_for(g, g->dens, t->density_pblocks);
     g->h_merge[prec] = t->h_merge;
+    g->h_ratio[prec] = t->h_flops_per_atomic;
     g->persistent[prec] = t->persistent;
     g->d_pblocks[prec] = t->density_pblocks;
   });

@@ -150,15 +150,18 @@ class AimsGrid:
         t = AimsTuning()
         self._check(self._L.aims_get_tuning(self._h, PRECISION[prec], byref(t)))
         return {"h_merge": t.h_merge, "density_pblocks": t.density_pblocks,
-                "persistent": t.persistent}
+                "persistent": t.persistent, "h_flops_per_atomic": t.h_flops_per_atomic}
 
     def set_tuning(self, h_merge: Optional[int] = None, density_pblocks: Optional[int] = None,
-                   prec="fp64", persistent: Optional[int] = None):
+                   prec="fp64", persistent: Optional[int] = None,
+                   h_flops_per_atomic: Optional[int] = None):
         cur = self.get_tuning(prec)
         t = AimsTuning()
         t.h_merge = int(cur["h_merge"] if h_merge is None else h_merge)
         t.density_pblocks = int(cur["density_pblocks"] if density_pblocks is None else density_pblocks)
         t.persistent = int(cur["persistent"] if persistent is None else persistent)
+        t.h_flops_per_atomic = int(cur["h_flops_per_atomic"] if h_flops_per_atomic is None
+                                   else h_flops_per_atomic)
         self._check(self._L.aims_set_tuning(self._h, PRECISION[prec], byref(t)))
 
     def profile(self, on: bool = True):

@@ -20,9 +20,9 @@ def test_search_picks_min_of_sum_per_persistent_flag():
             return d[(cfg["density_pblocks"], cfg["persistent"])]
         return h[(cfg["h_merge"], cfg["persistent"])]
 
-    best, log = search(cost)
+    best, log = search(cost, h_ratio=[])
     # persistent=0: 4.0 + 6.0 = 10.0 ; persistent=1: 3.8 + 7.5 = 11.3
-    assert best == {"h_merge": 1, "density_pblocks": 3, "persistent": 0}
+    assert best == {"h_merge": 1, "h_flops_per_atomic": 0, "density_pblocks": 3, "persistent": 0}
     assert len(calls) == 16 and len(log) == 16
     # the density pass is never timed with an h_merge knob and vice versa
     assert all("h_merge" not in c for k, c in calls if k == "density")
@@ -30,10 +30,26 @@ def test_search_picks_min_of_sum_per_persistent_flag():
 
 
 def test_search_restricted_candidates_and_empty():
-    best, _ = search(lambda k, c: 1.0, density_pblocks=[4], h_merge=[2], persistent=[1])
-    assert best == {"h_merge": 2, "density_pblocks": 4, "persistent": 1}
+    best, _ = search(lambda k, c: 1.0, density_pblocks=[4], h_merge=[2], persistent=[1], h_ratio=[])
+    assert best == {"h_merge": 2, "h_flops_per_atomic": 0, "density_pblocks": 4, "persistent": 1}
     with pytest.raises(ValueError):
         search(lambda k, c: 1.0, persistent=[])
+
+
+def test_search_cost_model_partition():
+    # the cost-model partition with ratio 256 beats every fixed level; the density knobs are
+    # timed without any H knob
+    def cost(kind, cfg):
+        if kind == "density":
+            assert set(cfg) == {"density_pblocks", "persistent"}
+            return 5.0
+        if cfg["h_flops_per_atomic"]:
+            assert cfg["h_merge"] == 0
+            return {64: 7.0, 256: 5.5, 1024: 6.0, 4096: 8.0}[cfg["h_flops_per_atomic"]]
+        return 6.5 + cfg["h_merge"]
+    best, log = search(cost)
+    assert best["h_flops_per_atomic"] == 256 and best["h_merge"] == 0
+    assert len(log) == 2 * (4 + 4 + 4)
 
 
 def test_workload_key_buckets():

@@ -133,13 +133,15 @@ def test_empty_grid(gpu, c1):
     assert torch.count_nonzero(H).item() == 0 and torch.count_nonzero(S).item() == 0
 
 
-@pytest.mark.parametrize("merge", [0, 1, 2, 3])
-def test_h_merge_levels_same_result(gpu, merge):
-    # coarser H batches (the bisection stopped earlier) change only the rounding order
+@pytest.mark.parametrize("merge,ratio", [(0, 0), (1, 0), (2, 0), (3, 0), (0, 64), (0, 4096)])
+def test_h_merge_levels_same_result(gpu, merge, ratio):
+    # coarser H batches (the bisection stopped earlier, at fixed levels or where the cost model
+    # prefers fewer scatter-adds) change only the rounding order
     inst = synth.make_instance("c2", n_atoms=10, box=7.0, seed=1)
     g = AimsGrid(inst, device=gpu.index)
-    g.set_tuning(merge, prec="fp64")
-    assert g.get_tuning("fp64")["h_merge"] == merge
+    g.set_tuning(merge, prec="fp64", h_flops_per_atomic=ratio)
+    t = g.get_tuning("fp64")
+    assert t["h_merge"] == merge and t["h_flops_per_atomic"] == ratio
     v = torch.from_numpy(inst.v).to(gpu)
     H, S = g.integrate_h(v, want_S=True)
     torch.cuda.synchronize()

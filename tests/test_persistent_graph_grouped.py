@@ -136,12 +136,12 @@ def test_autotune_live(gpu, cluster, tmp_path):
     ref = _step(g, P, v)
     cache = str(tmp_path / "tuning.json")
     r = autotune(g, P, v, prec="fp64", reps=1, cache=cache)
-    print("[autotune]", {k: r[k] for k in ("h_merge", "density_pblocks", "persistent", "key")},
+    print("[autotune]", {k: r[k] for k in ("h_merge", "h_flops_per_atomic", "density_pblocks",
+                                           "persistent", "key")},
           flush=True)
-    assert r["source"] == "measured" and len(r["ms"]) == 16
+    assert r["source"] == "measured" and len(r["ms"]) == 24
     t = g.get_tuning("fp64")
-    assert (t["h_merge"], t["density_pblocks"], t["persistent"]) == \
-        (r["h_merge"], r["density_pblocks"], r["persistent"])
+    assert t == {k: r[k] for k in ("h_merge", "density_pblocks", "persistent", "h_flops_per_atomic")}
     out = _step(g, P, v)
     # a different h_merge changes the H batches (same sums up to rounding)
     assert relerr(out[0], ref[0]) <= 1e-12 and relerr(out[2], ref[2]) <= 1e-12
