@@ -159,7 +159,9 @@ void aims_step_graph_destroy(aims_step_graph *graph);
  *                    (one atomic per tile, stealing from the other XCDs' counters when its
  *                    own is empty).  The counters are cleared by a kernel at the start of each
  *                    call, so calls in this mode can be captured into a step graph.
- * Setting a value builds its work lists once (device allocation), later calls reuse them. */
+ * Setting a value builds its work lists once (device allocation), later calls reuse them;
+ * buffers referenced by step graphs captured earlier stay allocated (a graph keeps replaying
+ * the tuning it was captured with). */
 typedef struct {
   int32_t h_merge;
   int32_t density_pblocks;

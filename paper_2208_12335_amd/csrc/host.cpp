@@ -494,9 +494,8 @@ void build_set(aims_grid* g, BatchSet& bs, int merge, bool density, int ratio = 
   bs.dv.batch_cols = g->upload(bs.batch_cols);
   bs.dv.sys_batch_range = g->upload(bs.sys_batch_range);
   if (bs.slab_elems > g->slab_cap) {
-    if (g->d_slab1) g->release(g->d_slab1);
-    if (g->d_slab2) g->release(g->d_slab2);
-    g->d_slab1 = g->d_slab2 = nullptr;
+    // the smaller scratch stays allocated until the handle is destroyed: a step graph captured
+    // earlier may still reference it
     g->slab_cap = 0;
     g->d_slab1 = g->alloc(bs.slab_elems * sizeof(double));
     g->d_slab2 = g->alloc(bs.slab_elems * sizeof(double));
