@@ -33,6 +33,11 @@
  * it).  Calls are asynchronous on the stream given at setup; one handle must not be used from
  * two threads at once.  Errors: every call returns an aims_status; all argument validation
  * happens on the host before any launch, and aims_last_error() holds the message.
+ *
+ * Environment (read at setup): AIMS_SCRATCH_MB sets the scratch budget that bounds a group of
+ * batches (default 1024, minimum 16); AIMS_H_MERGE sets the initial h_merge of every precision
+ * (0..4); AIMS_FAIL_ALLOC=1 makes every device allocation fail with AIMS_ERR_OOM (to test the
+ * error path).
  */
 #ifndef AIMS_GRID_H
 #define AIMS_GRID_H

@@ -121,6 +121,20 @@ def test_positions_and_errors(gpu, c1):
     assert relerr(n0.cpu().numpy(), d0["n"]) < TOL
 
 
+def test_allocation_failure_is_reported(gpu, c1, monkeypatch):
+    """A failed device allocation (forced from the host) surfaces as AIMS_ERR_OOM with a
+    message, leaves no handle behind, and a later set-up works."""
+    monkeypatch.setenv("AIMS_FAIL_ALLOC", "1")
+    with pytest.raises(AimsError) as e:
+        AimsGrid(c1, device=gpu.index)
+    assert e.value.status == -2 and "alloc" in str(e.value)
+    monkeypatch.delenv("AIMS_FAIL_ALLOC")
+    g = AimsGrid(c1, device=gpu.index)
+    n, _ = g.update_density(torch.from_numpy(c1.P).to(gpu).reshape(-1), torch.from_numpy(c1.v).to(gpu))
+    torch.cuda.synchronize()
+    assert torch.isfinite(n).all()
+
+
 def test_empty_grid(gpu, c1):
     import dataclasses
     e = dataclasses.replace(c1, pt_xyz=np.zeros((0, 3)), pt_w=np.zeros(0), v=np.zeros(0))
