@@ -19,9 +19,14 @@ R_s and K_s are natural cubic splines in s = ln r through the tabulated knot val
 (``scipy.interpolate.CubicSpline``), zero for r >= rc; Y_lm are the real, orthonormal spherical
 harmonics without the Condon-Shortley phase, built from the general real-solid-harmonic sum.
 
+``forces.moving_grid_gradient`` differentiates the same energy with every ingredient moving
+with the atoms (atom-centred grid points, Stratmann partition weights, the erf nuclear
+potential, the basis centres): the total analytic gradient, by torch autograd.
+
 Parity status: every function here is pinned by closed forms, invariants, library routines,
 brute force or finite differences in ``tests/test_oracle_*.py``; none is "parity unpinned".
 """
 from .harmonics import real_ylm, real_ylm_grad, ylm_terms  # noqa: F401
 from .radial import RadialSplines  # noqa: F401
 from .integrate import GridOracle  # noqa: F401
+from .forces import moving_grid_gradient  # noqa: F401

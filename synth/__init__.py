@@ -11,6 +11,7 @@ from .instances import (  # noqa: F401
     CONFIGS,
     make_instance,
     make_molecule_set,
+    regrid,
     generator_device,
     custom_instance,
     becke_radial,

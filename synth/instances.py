@@ -115,6 +115,7 @@ class Instance:
     P: np.ndarray                 # [nb, nb] float64, symmetric
     max_batch: int
     meta: dict = dataclasses.field(default_factory=dict)
+    pt_wgrid: Optional[np.ndarray] = None   # [n_pts] radial x angular weight (before partition)
 
     # ---- derived basis layout -------------------------------------------------------------
     @property
@@ -438,7 +439,8 @@ def species_for(zset: Sequence[int], rule: str, rng) -> Dict[str, np.ndarray]:
 def build_grid(atom_xyz: np.ndarray, n_radial: int, angular: str, rc: float = RC,
                prune: bool = True, max_neighbors: int = 64):
     """Atom-centred product grids with Stratmann partition weights; returns
-    (points, weights, owner, meta).  Points are atom-major, shell-major, angle-minor."""
+    (points, weights, owner, meta, wgrid) with wgrid the radial x angular weight before the
+    partition.  Points are atom-major, shell-major, angle-minor."""
     r, wr = becke_radial(n_radial)
     u, wa = ANGULAR[angular]()
     na = atom_xyz.shape[0]
@@ -462,7 +464,7 @@ def build_grid(atom_xyz: np.ndarray, n_radial: int, angular: str, rc: float = RC
         keep &= w != 0.0
     meta = {"n_raw": int(n_raw), "n_beyond_rc": n_far,
             "n_zero_weight": int(zero.sum()) if prune else 0, "n_kept": int(keep.sum())}
-    return pts[keep], w[keep], owner[keep], meta
+    return pts[keep], w[keep], owner[keep], meta, w0[keep]
 
 
 def _min_distance(points: np.ndarray, atom_xyz: np.ndarray) -> np.ndarray:
@@ -511,15 +513,21 @@ def random_density_matrix(rng, atom_xyz: np.ndarray, atom_nfn: np.ndarray,
     return np.ascontiguousarray(P)
 
 
+EXACT_PARTITION_ATOMS = 128   # up to this many atoms the partition products run over all atoms
+
+
 def _assemble(name, rng, atom_xyz, atom_Z, zset, rule, max_batch, pair_cutoff=None,
-              max_neighbors=64):
+              max_neighbors=None):
+    if max_neighbors is None:
+        n = atom_xyz.shape[0]
+        max_neighbors = n if n <= EXACT_PARTITION_ATOMS else 64
     sp = species_for(zset, rule, rng)
     zidx = {int(z): i for i, z in enumerate(sp["species_Z"])}
     atom_species = np.array([zidx[int(z)] for z in atom_Z], dtype=np.int32)
     R, K = radial_tables(sp["shell_l"], sp["shell_zeta"])
     g = GRID_RULES[rule]
-    pts, w, owner, meta = build_grid(atom_xyz, g["n_radial"], g["angular"],
-                                     max_neighbors=max_neighbors)
+    pts, w, owner, meta, wgrid = build_grid(atom_xyz, g["n_radial"], g["angular"],
+                                            max_neighbors=max_neighbors)
     v = nuclear_potential(pts, atom_xyz, atom_Z)
     inst = Instance(name=name, atom_xyz=np.ascontiguousarray(atom_xyz, np.float64),
                     atom_Z=atom_Z.astype(np.int32), atom_species=atom_species,
@@ -527,11 +535,29 @@ def _assemble(name, rng, atom_xyz, atom_Z, zset, rule, max_batch, pair_cutoff=No
                     shell_l=sp["shell_l"], shell_zeta=sp["shell_zeta"], n_log=N_LOG, r0=R0,
                     rc=RC, shell_R=R, shell_K=K, pt_xyz=np.ascontiguousarray(pts),
                     pt_w=np.ascontiguousarray(w), pt_atom=owner.astype(np.int32), v=v,
-                    P=np.zeros((0, 0)), max_batch=int(max_batch), meta=dict(meta))
+                    P=np.zeros((0, 0)), max_batch=int(max_batch), meta=dict(meta),
+                    pt_wgrid=np.ascontiguousarray(wgrid))
     nfn = inst.species_nfn()[atom_species]
     inst.P = random_density_matrix(rng, atom_xyz, nfn, pair_cutoff)
     inst.meta.update({"rule": rule, "grid": g, "pair_cutoff": pair_cutoff})
     return inst
+
+
+def regrid(inst: Instance, atom_xyz: np.ndarray) -> Instance:
+    """The same system (species, radial tables, density matrix, batch size) with every atom at
+    ``atom_xyz`` and its grid built afresh there: atom-centred grids moved with their atoms,
+    partition weights and the nuclear potential recomputed.  Used to take finite differences
+    of quantities whose grid moves with the atoms."""
+    atom_xyz = np.ascontiguousarray(atom_xyz, dtype=np.float64)
+    g = inst.meta["grid"]
+    n = atom_xyz.shape[0]
+    pts, w, owner, meta, wgrid = build_grid(atom_xyz, g["n_radial"], g["angular"], rc=inst.rc,
+                                            max_neighbors=n if n <= EXACT_PARTITION_ATOMS else 64)
+    v = nuclear_potential(pts, atom_xyz, inst.atom_Z)
+    return dataclasses.replace(inst, atom_xyz=atom_xyz, pt_xyz=np.ascontiguousarray(pts),
+                               pt_w=np.ascontiguousarray(w), pt_atom=owner.astype(np.int32),
+                               v=v, pt_wgrid=np.ascontiguousarray(wgrid),
+                               meta=dict(inst.meta, **meta))
 
 
 CONFIGS = ("c1", "c2", "c3", "c4", "c5")
@@ -605,14 +631,14 @@ def custom_instance(atom_xyz: np.ndarray, atom_species: np.ndarray,
     na = atom_xyz.shape[0]
     rel = (r[:, None, None] * u[None, :, :]).reshape(-1, 3)
     pts = (atom_xyz[:, None, :] + rel[None, :, :]).reshape(-1, 3)
-    w = np.tile((wr[:, None] * wa[None, :]).reshape(-1), na)
+    w0 = np.tile((wr[:, None] * wa[None, :]).reshape(-1), na)
     owner = np.repeat(np.arange(na, dtype=np.int32), rel.shape[0])
-    w = w * stratmann_partition(pts, owner, atom_xyz)
+    w = w0 * stratmann_partition(pts, owner, atom_xyz, max_neighbors=max(64, na))
     keep = np.ones(pts.shape[0], dtype=bool)
     if prune:
         d = np.min(np.linalg.norm(pts[:, None, :] - atom_xyz[None], axis=-1), axis=1)
         keep = (w != 0.0) & (d <= rc + PRUNE_MARGIN)
-    pts, w, owner = pts[keep], w[keep], owner[keep]
+    pts, w, owner, w0 = pts[keep], w[keep], owner[keep], w0[keep]
     nsp = len(species_shells)
     inst = Instance(name=name, atom_xyz=atom_xyz,
                     atom_Z=(np.ones(na, np.int32) if atom_Z is None else np.asarray(atom_Z, np.int32)),
@@ -622,7 +648,7 @@ def custom_instance(atom_xyz: np.ndarray, atom_species: np.ndarray,
                     r0=r0, rc=rc, shell_R=R, shell_K=K, pt_xyz=np.ascontiguousarray(pts),
                     pt_w=np.ascontiguousarray(w), pt_atom=owner.astype(np.int32),
                     v=np.zeros(pts.shape[0]), P=np.zeros((0, 0)), max_batch=max_batch,
-                    meta={"custom": True})
+                    meta={"custom": True}, pt_wgrid=np.ascontiguousarray(w0))
     if potential is not None:
         inst.v = np.ascontiguousarray(potential(pts), dtype=np.float64)
     nb = inst.n_basis

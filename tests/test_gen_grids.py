@@ -96,7 +96,7 @@ def test_c1_counts_and_pruning_contributes_nothing(c1):
     assert c1.n_basis == 24
     assert np.all(c1.pt_w > 0)
     # the dropped points carry zero partition weight or lie beyond rc of every atom
-    pts, w, owner, meta = I.build_grid(c1.atom_xyz, 50, "gl110", prune=False)
+    pts, w, owner, meta, wgrid = I.build_grid(c1.atom_xyz, 50, "gl110", prune=False)
     d = np.min(np.linalg.norm(pts[:, None] - c1.atom_xyz[None], axis=-1), axis=1)
     kept = (w != 0) & (d <= I.RC + I.PRUNE_MARGIN)
     assert kept.sum() == c1.n_points
