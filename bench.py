@@ -224,6 +224,19 @@ def bench_single(args, torch, inst, backward=False):
     S = torch.empty(g.mat_elems, dtype=torch.float64, device=dev)
     g.set_tuning(prec="fp64", **res["fp64"]["tuning"])
     ms_S, _ = timer.run(lambda: g.integrate_h(v, prec="fp64", H_out=H, S_out=S, want_S=True), 3, 1)
+    outside = {"setup_s": setup_s, "ms_integrate_h_with_S_fp64": ms_S}
+    if backward and inst.pt_wgrid is not None:
+        # total (moving-grid) forces: Pulay + partition-weight + nuclear-potential + point motion
+        g.set_moving_grid()
+        dR = torch.empty(inst.n_atoms, 3, dtype=torch.float64, device=dev)
+        fsums = torch.empty(1, 3, dtype=torch.float64, device=dev)
+
+        def forces():
+            nonlocal dR
+            dR, _ = g.total_forces(P, gE, prec="fp64", sums_out=fsums)
+        outside["ms_total_forces_fp64"], _ = timer.run(forces, 3, 1)
+        outside["total_forces_translation_residual"] = float(
+            dR.sum(dim=0).abs().max() / dR.abs().max())
     line = {
         "metric": "H+density integration GFLOP/s and ms per SCF step (fastest form within 1e-6 Ha "
                   "of FP64; mixed forms reported beside it)" if not backward else
@@ -245,7 +258,7 @@ def bench_single(args, torch, inst, backward=False):
                          "speedup_vs_fp64": res["fp64"]["ms_per_step"] / res[fastest]["ms_per_step"]},
         "kernels": {p: r["kernels"] for p, r in res.items()},
         "autotuned": {p: (p not in fixed and not args.no_autotune) for p in forms},
-        "outside_step": {"setup_s": setup_s, "ms_integrate_h_with_S_fp64": ms_S},
+        "outside_step": outside,
         "roofline": _roofline(hr["kernels"], head, args.steps, args.workload, hr["tuning"]),
     }
     if args.cpu_chunks > 0:

@@ -135,6 +135,39 @@ aims_status aims_integrate_h_backward(aims_grid *g, aims_precision prec, const d
                                       double *dE_dP_or_null, double *dE_dv_or_null,
                                       double *dE_dR_or_null);
 
+/* Moving-grid model of one system, for the total energy gradient (host arrays, copied):
+ * every grid point belongs to the atom-centred grid of an owner atom and moves with it, its
+ * weight is pt_wgrid times the Stratmann-Scuseria-Frisch partition with parameter
+ * partition_a (Chem. Phys. Lett. 257, 213 (1996)), and the potential is the nuclear model
+ * v(p) = sum_a -Z_a erf(|p - R_a| / nuc_sigma) / |p - R_a|.  The setup weights pt_w must be
+ * pt_wgrid times that partition (exact products over all atoms).
+ *   pt_owner   [n_points] owner atom, 0..n_atoms-1 of the system (caller point order)
+ *   pt_wgrid   [n_points] radial x angular weight of the owner's grid (before the partition)
+ *   atom_Z     [n_atoms]  nuclear charges
+ * Errors: AIMS_ERR_ARG for out-of-range owners, non-finite values, sigma <= 0 or a outside
+ * (0, 1). */
+typedef struct {
+  const int32_t *pt_owner;
+  const double *pt_wgrid;
+  const double *atom_Z;
+  double nuc_sigma;
+  double partition_a;
+} aims_moving_grid;
+aims_status aims_grid_set_moving(aims_grid *g, int32_t sys, const aims_moving_grid *m);
+
+/* Total gradient (the extension of the backward to moving grids) of
+ *     E(R) = sum_p w_p(R) [ v(p; R) n(p; R) + sum_ij P_ij phi_i(p) tphi_j(p) ]
+ * at the setup positions, where the grid points, their partition weights, the nuclear model
+ * potential and the basis centres all follow the atoms (P fixed):
+ *     dE_dR[a] = gE * dE/dR_a = (Pulay term of aims_integrate_h_backward)
+ *                + the point-motion, partition-weight and potential terms.
+ * Every system needs aims_grid_set_moving first.  P: DEVICE [nb][nb]; gE: DEVICE [1];
+ * dE_dR: DEVICE [n_atoms][3], overwritten; sums_out_or_null: DEVICE [n_sys][3] receives
+ * (N, E_V, E_T) of that energy (v = the model potential).  AIMS_FP64 and AIMS_FP32 only
+ * (AIMS_ERR_UNSUPPORTED otherwise); at most 2730 atoms per system. */
+aims_status aims_total_forces(aims_grid *g, aims_precision prec, const double *P, const double *gE,
+                              double *sums_out_or_null, double *dE_dR);
+
 /* One s.c.f. step (density update followed by H integration, setup positions) captured once
  * into a HIP graph on the handle's stream; aims_step_graph_launch replays it.  The buffers are
  * baked into the graph and must outlive it; update their contents in place between replays. */

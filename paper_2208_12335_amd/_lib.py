@@ -41,6 +41,11 @@ class AimsTuning(ctypes.Structure):
                 ("h_flops_per_atomic", c_int32)]
 
 
+class AimsMovingGrid(ctypes.Structure):
+    _fields_ = [("pt_owner", POINTER(c_int32)), ("pt_wgrid", POINTER(c_double)),
+                ("atom_Z", POINTER(c_double)), ("nuc_sigma", c_double), ("partition_a", c_double)]
+
+
 # every symbol the header declares, with its signature
 SIGNATURES = {
     "aims_grid_setup": (c_int, [POINTER(AimsSystem), c_int, c_void_p, POINTER(c_void_p)]),
@@ -49,6 +54,8 @@ SIGNATURES = {
     "aims_integrate_h": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
     "aims_integrate_h_backward": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
                                           c_void_p, c_void_p, c_void_p]),
+    "aims_grid_set_moving": (c_int, [c_void_p, c_int32, POINTER(AimsMovingGrid)]),
+    "aims_total_forces": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
     "aims_step_graph_create": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
                                        c_void_p, POINTER(c_void_p)]),
     "aims_step_graph_launch": (c_int, [c_void_p]),

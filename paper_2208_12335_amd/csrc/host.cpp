@@ -232,6 +232,24 @@ struct aims_grid {
   double* d_ntmp = nullptr;           // backward: n in caller order (not returned)
   double* d_sums_tmp = nullptr;
 
+  // moving-grid model of each system (total energy gradient)
+  std::vector<int32_t> perm_host;            // batch-ordered point -> caller index
+  std::vector<char> moving;                  // per system: model set
+  std::vector<double> sys_model;             // [n_sys][2]: sigma, partition a
+  std::vector<int32_t> owner_host;           // batch order: owner atom (handle-global)
+  std::vector<double> wgrid_host;            // batch order: weight before the partition
+  std::vector<double> Z_host;                // per handle-global atom
+  std::vector<int32_t> pt_sys_host;          // batch order: system of the point
+  int32_t* d_owner = nullptr;
+  double* d_wgrid = nullptr;
+  double* d_Z = nullptr;
+  double* d_sys_model = nullptr;
+  int32_t* d_sys_natoms = nullptr;
+  int32_t* d_pt_sys = nullptr;
+  double* d_vmodel = nullptr;                // model potential, caller order
+  double* d_dsorted = nullptr;               // kinetic density per point, batch order
+  double* d_gpt = nullptr;                   // point-motion sums, batch order [n][3]
+
   ~aims_grid() {
     if (!owned.empty()) {
       (void)hipSetDevice(device);
@@ -673,6 +691,7 @@ aims_grid* build(const aims_system* sys, int n_sys, int device, void* stream) {
     caller_base += s.n_points;
   }
   g->n_points = (int64_t)g->pts_sorted.size();
+  g->perm_host = perm;
 
   // ---- upload of the shared state, then the density partition ---------------------------
   hipchk(hipSetDevice(device), "hipSetDevice");
@@ -1087,6 +1106,163 @@ aims_status aims_integrate_h_backward(aims_grid* g, aims_precision prec, const d
     }
     if (dE_dv_or_null)
       hipchk(launch_dv(g->dens.dv, dE_dv_or_null, g->d_n_sorted, g->n_points, gE, st), "dE/dv");
+  });
+}
+
+aims_status aims_grid_set_moving(aims_grid* g, int32_t sys, const aims_moving_grid* m) {
+  return guarded(g, [&] {
+    if (!m) fail(AIMS_ERR_ARG, "null moving-grid description");
+    if (sys < 0 || sys >= g->n_sys) fail(AIMS_ERR_ARG, "system %d out of range", sys);
+    if (!(m->nuc_sigma > 0.0) || !std::isfinite(m->nuc_sigma)) fail(AIMS_ERR_ARG, "nuc_sigma must be > 0");
+    if (!(m->partition_a > 0.0 && m->partition_a < 1.0)) fail(AIMS_ERR_ARG, "partition_a must be in (0, 1)");
+    const int64_t p0 = g->sys_pt_range[2 * sys], p1 = g->sys_pt_range[2 * sys + 1];
+    const int a0 = (int)g->sys_atom_range[2 * sys], a1 = (int)g->sys_atom_range[2 * sys + 1];
+    if (p1 > p0 && (!m->pt_owner || !m->pt_wgrid)) fail(AIMS_ERR_ARG, "null point arrays");
+    if (!m->atom_Z) fail(AIMS_ERR_ARG, "null atom_Z");
+    if (!finite_all(m->atom_Z, (size_t)(a1 - a0))) fail(AIMS_ERR_ARG, "non-finite atom_Z");
+    if (p1 > p0 && !finite_all(m->pt_wgrid, (size_t)(p1 - p0))) fail(AIMS_ERR_ARG, "non-finite pt_wgrid");
+    for (int64_t i = 0; i < p1 - p0; ++i)
+      if (m->pt_owner[i] < 0 || m->pt_owner[i] >= a1 - a0)
+        fail(AIMS_ERR_ARG, "pt_owner[%lld] = %d out of range", (long long)i, m->pt_owner[i]);
+    const size_t n = (size_t)g->n_points;
+    if (g->moving.empty()) {
+      g->moving.assign(g->n_sys, 0);
+      g->sys_model.assign(2 * (size_t)g->n_sys, 0.0);
+      g->owner_host.assign(n, 0);
+      g->wgrid_host.assign(n, 0.0);
+      g->Z_host.assign(g->n_atoms, 0.0);
+      g->pt_sys_host.assign(n, 0);
+      for (int k = 0; k < g->n_sys; ++k)
+        for (int64_t i = g->sys_pt_range[2 * k]; i < g->sys_pt_range[2 * k + 1]; ++i) g->pt_sys_host[i] = k;
+      g->d_owner = (int32_t*)g->alloc(std::max<size_t>(1, n) * sizeof(int32_t));
+      g->d_wgrid = (double*)g->alloc(std::max<size_t>(1, n) * sizeof(double));
+      g->d_Z = (double*)g->alloc(std::max(1, g->n_atoms) * sizeof(double));
+      g->d_sys_model = (double*)g->alloc(2 * (size_t)g->n_sys * sizeof(double));
+      g->d_pt_sys = g->upload(g->pt_sys_host);
+      std::vector<int32_t> natoms(g->n_sys);
+      for (int k = 0; k < g->n_sys; ++k) natoms[k] = (int32_t)(g->sys_atom_range[2 * k + 1] - g->sys_atom_range[2 * k]);
+      g->d_sys_natoms = g->upload(natoms);
+      g->d_vmodel = (double*)g->alloc(std::max<size_t>(1, n) * sizeof(double));
+      g->d_dsorted = (double*)g->alloc(std::max<size_t>(1, n) * sizeof(double));
+      g->d_gpt = (double*)g->alloc(3 * std::max<size_t>(1, n) * sizeof(double));
+    }
+    for (int64_t i = p0; i < p1; ++i) {
+      const int64_t q = g->perm_host[i] - p0;     // caller index within the system
+      g->owner_host[i] = a0 + m->pt_owner[q];
+      g->wgrid_host[i] = m->pt_wgrid[q];
+    }
+    for (int a = a0; a < a1; ++a) g->Z_host[a] = m->atom_Z[a - a0];
+    g->sys_model[2 * sys] = m->nuc_sigma;
+    g->sys_model[2 * sys + 1] = m->partition_a;
+    g->moving[sys] = 1;
+    hipchk(hipMemcpy(g->d_owner, g->owner_host.data(), n * sizeof(int32_t), hipMemcpyHostToDevice), "upload");
+    hipchk(hipMemcpy(g->d_wgrid, g->wgrid_host.data(), n * sizeof(double), hipMemcpyHostToDevice), "upload");
+    hipchk(hipMemcpy(g->d_Z, g->Z_host.data(), g->Z_host.size() * sizeof(double), hipMemcpyHostToDevice), "upload");
+    hipchk(hipMemcpy(g->d_sys_model, g->sys_model.data(), g->sys_model.size() * sizeof(double),
+                     hipMemcpyHostToDevice), "upload");
+  });
+}
+
+aims_status aims_total_forces(aims_grid* g, aims_precision prec, const double* P, const double* gE,
+                              double* sums_out_or_null, double* dE_dR) {
+  return guarded(g, [&] {
+    check_prec(prec);
+    if (prec == AIMS_BF16X3) fail(AIMS_ERR_UNSUPPORTED, "total forces support AIMS_FP64 and AIMS_FP32");
+    if (g->moving.empty()) fail(AIMS_ERR_ARG, "no moving-grid model set (aims_grid_set_moving)");
+    for (int k = 0; k < g->n_sys; ++k)
+      if (!g->moving[k]) fail(AIMS_ERR_ARG, "system %d has no moving-grid model", k);
+    require_device(P, "P");
+    require_device(gE, "gE");
+    require_device(dE_dR, "dE_dR");
+    if (sums_out_or_null) require_device(sums_out_or_null, "sums_out");
+    set_positions(g, nullptr);
+    if (g->moved) fail(AIMS_ERR_ARG, "total forces are taken at the setup positions");
+    int max_na = 1;
+    for (int k = 0; k < g->n_sys; ++k)
+      max_na = std::max(max_na, (int)(g->sys_atom_range[2 * k + 1] - g->sys_atom_range[2 * k]));
+    if (3 * (size_t)max_na * sizeof(double) > 64 * 1024)
+      fail(AIMS_ERR_UNSUPPORTED, "total forces support up to %d atoms per system", (int)(64 * 1024 / 24));
+    hipStream_t st = g->stream;
+    BatchSet& bs = g->dens;
+    if (g->slab_cap34 < bs.slab_elems) {
+      if (g->d_slab3) g->release(g->d_slab3);
+      if (g->d_slab4) g->release(g->d_slab4);
+      g->d_slab3 = g->d_slab4 = nullptr;
+      g->slab_cap34 = 0;
+      g->d_slab3 = g->alloc(bs.slab_elems * sizeof(double));
+      g->d_slab4 = g->alloc(bs.slab_elems * sizeof(double));
+      g->slab_cap34 = bs.slab_elems;
+    }
+    if (!g->d_ntmp) {
+      g->d_ntmp = (double*)g->alloc(std::max<int64_t>(1, g->n_points) * sizeof(double));
+      g->d_sums_tmp = (double*)g->alloc(3 * (size_t)g->n_sys * sizeof(double));
+    }
+    const size_t n = (size_t)g->n_points;
+    const bool mixed = prec != AIMS_FP64;
+    hipchk(launch_vext(bs.dv, g->n_points, g->d_pt_sys, g->d_sys_natoms, g->d_Z, g->d_sys_model,
+                       g->d_vmodel, st), "model potential");
+    if (mixed) hipchk(launch_convert_f32(P, g->d_P32, (size_t)g->mat_total, st), "convert P");
+    hipchk(launch_fill(g->d_n_sorted, n, 0.0, st), "fill n");
+    hipchk(launch_fill(g->d_dsorted, n, 0.0, st), "fill D");
+    hipchk(launch_fill(g->d_gpt, 3 * n, 0.0, st), "fill point sums");
+    hipchk(launch_fill(g->d_et_batch, bs.batches.size(), 0.0, st), "fill E_T");
+    hipchk(launch_fill(dE_dR, 3 * (size_t)g->n_atoms, 0.0, st), "fill dE/dR");
+    const double* v = g->d_vmodel;
+    const ItemList& L = items_for(g, bs, g->d_pblocks[prec]);
+    for (size_t gi = 0; gi < bs.groups.size(); ++gi) {
+      const auto& gr = bs.groups[gi];
+      const int nbt = gr.b1 - gr.b0;
+      if (!mixed) {
+        double *s1 = (double*)g->d_slab1, *s2 = (double*)g->d_slab2;
+        double *s3 = (double*)g->d_slab3, *s4 = (double*)g->d_slab4;
+        timed(g, kProfPhi, 0.0, "phi_eval", [&] {
+          return launch_phi_eval<double>(bs.dv, gr.b0, nbt, kModeDensity, nullptr, s1, s2, st);
+        });
+        for (const auto& run : L.runs[gi]) {
+          const int nit = (int)(run.i1 - run.i0);
+          timed(g, kProfBackward, gr.flops / L.runs[gi].size(), "X", [&] {
+            return launch_density<double>(bs.dv, run.nbn, L.d_items + run.i0, nit, P, s1, s2,
+                                          g->d_n_sorted, g->d_et_batch, st, s3, Queue(), g->d_dsorted);
+          });
+          timed(g, kProfBackward, gr.flops / L.runs[gi].size(), "Y", [&] {
+            return launch_density<double>(bs.dv, run.nbn, L.d_items + run.i0, nit, P, s2, s2, nullptr,
+                                          nullptr, st, s4);
+          });
+        }
+        timed(g, kProfBackward, 0.0, "pulay", [&] {
+          return launch_pulay<double>(bs.dv, gr.b0, nbt, v, s3, s4, gE, dE_dR, st, g->d_gpt);
+        });
+      } else {
+        float *s1 = (float*)g->d_slab1, *s2 = (float*)g->d_slab2;
+        float *s3 = (float*)g->d_slab3, *s4 = (float*)g->d_slab4;
+        timed(g, kProfPhi, 0.0, "phi_eval", [&] {
+          return launch_phi_eval<float>(bs.dv, gr.b0, nbt, kModeDensity, nullptr, s1, s2, st);
+        });
+        for (const auto& run : L.runs[gi]) {
+          const int nit = (int)(run.i1 - run.i0);
+          timed(g, kProfBackward, gr.flops / L.runs[gi].size(), "X", [&] {
+            return launch_density<float>(bs.dv, run.nbn, L.d_items + run.i0, nit, g->d_P32, s1, s2,
+                                         g->d_n_sorted, g->d_et_batch, st, s3, Queue(), g->d_dsorted);
+          });
+          timed(g, kProfBackward, gr.flops / L.runs[gi].size(), "Y", [&] {
+            return launch_density<float>(bs.dv, run.nbn, L.d_items + run.i0, nit, g->d_P32, s2, s2,
+                                         nullptr, nullptr, st, s4);
+          });
+        }
+        timed(g, kProfBackward, 0.0, "pulay", [&] {
+          return launch_pulay<float>(bs.dv, gr.b0, nbt, v, s3, s4, gE, dE_dR, st, g->d_gpt);
+        });
+      }
+    }
+    timed(g, kProfBackward, 0.0, "grid", [&] {
+      return launch_gridforce(bs.dv, (int)bs.batches.size(), max_na, g->d_sys_natoms, g->d_Z,
+                              g->d_sys_model, g->d_owner, g->d_wgrid, g->d_vmodel, g->d_n_sorted,
+                              g->d_dsorted, g->d_gpt, gE, dE_dR, st);
+    });
+    if (sums_out_or_null) {
+      hipchk(launch_density_finish(bs.dv, g->d_n_sorted, v, g->d_ntmp, g->d_part, g->nblk_finish,
+                                   g->d_et_batch, sums_out_or_null, st), "sums");
+    }
   });
 }
 

@@ -48,17 +48,32 @@ hipError_t launch_phi_eval_bf16(const DeviceView& dv, int b0, int nbatch, int mo
                                 void* slab1, void* slab2, hipStream_t st);
 // nbn: point tile = 32 * nbn points (2..5)
 // xout != NULL: store X^T = P_b slab1 into xout (function-major slab); n and the E_T partials
-// are formed as well unless n_sorted is NULL
+// are formed as well unless n_sorted is NULL.  d_sorted != NULL: also the unweighted kinetic
+// density D(p) = sum_j X_pj tphi_j(p) per point (batch order), added atomically.
 template <typename T>
 hipError_t launch_density(const DeviceView& dv, int nbn, const TileItem* items, int n_items, const T* P,
                           const T* slab1, const T* slab2, double* n_sorted, double* et_batch,
-                          hipStream_t st, T* xout = nullptr, Queue q = Queue());
+                          hipStream_t st, T* xout = nullptr, Queue q = Queue(),
+                          double* d_sorted = nullptr);
 hipError_t launch_density_bf16(const DeviceView& dv, int nbn, const TileItem* items, int n_items,
                                const float* P, const void* slab1, const void* slab2, double* n_sorted,
                                double* et_batch, hipStream_t st, float* xout = nullptr, Queue q = Queue());
+// gpt != NULL: also the per-point sum over atoms of the same terms (3 doubles per point,
+// batch order, added atomically): the gradient of the integrand with respect to the point.
 template <typename T>
 hipError_t launch_pulay(const DeviceView& dv, int b0, int nbatch, const double* v, const T* X,
-                        const T* Y, const double* gE, double* dE_dR, hipStream_t st);
+                        const T* Y, const double* gE, double* dE_dR, hipStream_t st,
+                        double* gpt = nullptr);
+// Moving-grid terms: the nuclear model potential on the grid (caller order) and the
+// partition-weight, potential and point-motion terms of the total gradient.
+hipError_t launch_vext(const DeviceView& dv, int64_t n, const int32_t* pt_sys,
+                       const int32_t* sys_natoms, const double* atom_Z, const double* sys_model,
+                       double* v_out, hipStream_t st);
+hipError_t launch_gridforce(const DeviceView& dv, int nbatch, int max_sys_atoms,
+                            const int32_t* sys_natoms, const double* atom_Z, const double* sys_model,
+                            const int32_t* pt_owner, const double* pt_wgrid, const double* v_model,
+                            const double* n_sorted, const double* d_sorted, const double* gpt,
+                            const double* gE, double* dE_dR, hipStream_t st);
 hipError_t launch_scale(double* y, const double* x, size_t n, const double* gE, hipStream_t st);
 hipError_t launch_dv(const DeviceView& dv, double* dE_dv, const double* n_sorted, int64_t n,
                      const double* gE, hipStream_t st);

@@ -264,27 +264,39 @@ __device__ __forceinline__ void load4<float>(const float* __restrict__ p, float 
 // and the lane's energy partial se, reduce over the tile's rows and add into n (FP64 atomics,
 // one per point and tile) and into the batch's E_T partial.
 template <int NBN>
-__device__ __forceinline__ void density_epilogue(double (&sn)[NBN], double se, int lane, int wave,
-                                                 int wm, int wn, int p0, int n_p, int pt_off,
-                                                 double (*red_n)[32 * NBN], double* red_e,
+__device__ __forceinline__ void density_epilogue(double (&sn)[NBN], double (&sd)[NBN], double se,
+                                                 int lane, int wave, int wm, int wn, int p0, int n_p,
+                                                 int pt_off, double (*red_n)[32 * NBN],
+                                                 double (*red_d)[32 * NBN], double* red_e,
                                                  double* __restrict__ n_sorted,
+                                                 double* __restrict__ d_sorted,
                                                  double* __restrict__ et_batch, int batch) {
   constexpr int PT = 32 * NBN;
 #pragma unroll
   for (int ni = 0; ni < NBN; ++ni) {
     sn[ni] += __shfl_xor(sn[ni], 16);
     sn[ni] += __shfl_xor(sn[ni], 32);
+    if (d_sorted) {
+      sd[ni] += __shfl_xor(sd[ni], 16);
+      sd[ni] += __shfl_xor(sd[ni], 32);
+    }
   }
   for (int off = 32; off > 0; off >>= 1) se += __shfl_xor(se, off);
   if (lane < 16) {
 #pragma unroll
-    for (int ni = 0; ni < NBN; ++ni) red_n[wm][wn * 16 * NBN + ni * 16 + lane] = sn[ni];
+    for (int ni = 0; ni < NBN; ++ni) {
+      red_n[wm][wn * 16 * NBN + ni * 16 + lane] = sn[ni];
+      if (d_sorted) red_d[wm][wn * 16 * NBN + ni * 16 + lane] = sd[ni];
+    }
   }
   if (lane == 0) red_e[wave] = se;
   __syncthreads();
   for (int t = threadIdx.x; t < PT; t += blockDim.x) {
     const int p = p0 + t;
-    if (p < n_p) unsafeAtomicAdd(n_sorted + pt_off + p, red_n[0][t] + red_n[1][t]);
+    if (p < n_p) {
+      unsafeAtomicAdd(n_sorted + pt_off + p, red_n[0][t] + red_n[1][t]);
+      if (d_sorted) unsafeAtomicAdd(d_sorted + pt_off + p, red_d[0][t] + red_d[1][t]);
+    }
   }
   if (threadIdx.x == 0)
     unsafeAtomicAdd(et_batch + batch, (red_e[0] + red_e[1]) + (red_e[2] + red_e[3]));
@@ -299,7 +311,7 @@ density_tile(int item, const TileItem* __restrict__ items, int n_items, const Ba
                const int32_t* __restrict__ batch_cols, const T* __restrict__ Pmat,
                const T* __restrict__ slab1, const T* __restrict__ slab2,
                double* __restrict__ n_sorted, double* __restrict__ et_batch,
-               T* __restrict__ xout) {
+               T* __restrict__ xout, double* __restrict__ d_sorted) {
   constexpr int PT = 32 * NBN;          // points per tile
   constexpr int LDN = PT + 16;          // N-contiguous LDS rows
   constexpr int BW = PT / 4;            // 4-element units per B row
@@ -319,6 +331,7 @@ density_tile(int item, const TileItem* __restrict__ items, int n_items, const Ba
   __shared__ T As[2][kTile * kLdK];   // P_b[j][i], i contiguous
   __shared__ T Bs[2][kKC * LDN];      // Phi^T[i][p], p contiguous
   __shared__ double red_n[2][PT];
+  __shared__ double red_d[2][PT];
   __shared__ double red_e[4];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -447,7 +460,7 @@ density_tile(int item, const TileItem* __restrict__ items, int n_items, const Ba
     if (!n_sorted) return;      // else also the density epilogue below
   }
   // epilogue: column sums of X^T o Phi^T (density) and of w X^T o tPhi^T (kinetic energy)
-  double sn[NBN], se = 0.0;
+  double sn[NBN], sd[NBN], se = 0.0;
 #pragma unroll
   for (int ni = 0; ni < NBN; ++ni) {
     const int p = p0 + wn * 16 * NBN + ni * 16 + (lane & 15);
@@ -464,13 +477,16 @@ density_tile(int item, const TileItem* __restrict__ items, int n_items, const Ba
             acce += x * (double)S2[(size_t)j * ldp + p];
           }
         }
+      sd[ni] = acce;
       acce *= pts[d.pt_off + p].w;
+    } else {
+      sd[ni] = 0.0;
     }
     sn[ni] = accn;
     se += acce;
   }
-  density_epilogue<NBN>(sn, se, lane, wave, wm, wn, p0, d.n_p, d.pt_off, red_n, red_e, n_sorted,
-                        et_batch, it.batch);
+  density_epilogue<NBN>(sn, sd, se, lane, wave, wm, wn, p0, d.n_p, d.pt_off, red_n, red_d, red_e,
+                        n_sorted, d_sorted, et_batch, it.batch);
 }
 
 template <typename T, int NBN>
@@ -480,10 +496,10 @@ density_kernel(const TileItem* __restrict__ items, int n_items, const BatchDesc*
                const int32_t* __restrict__ batch_cols, const T* __restrict__ Pmat,
                const T* __restrict__ slab1, const T* __restrict__ slab2,
                double* __restrict__ n_sorted, double* __restrict__ et_batch,
-               T* __restrict__ xout,
+               T* __restrict__ xout, double* __restrict__ d_sorted,
     int* __restrict__ queue) {
   run_items(n_items, queue, [&](int item) {
-    density_tile<T, NBN>(item, items, n_items, batches, systems, pts, batch_cols, Pmat, slab1, slab2, n_sorted, et_batch, xout);
+    density_tile<T, NBN>(item, items, n_items, batches, systems, pts, batch_cols, Pmat, slab1, slab2, n_sorted, et_batch, xout, d_sorted);
   });
 }
 
@@ -801,8 +817,9 @@ density_tile_bf16(int item, const TileItem* __restrict__ items, int n_items, con
     sn[ni] = accn;
     se += acce;
   }
-  density_epilogue<NBN>(sn, se, lane, wave, wm, wn, p0, d.n_p, d.pt_off, red_n, red_e, n_sorted,
-                        et_batch, it.batch);
+  double sd[NBN];
+  density_epilogue<NBN>(sn, sd, se, lane, wave, wm, wn, p0, d.n_p, d.pt_off, red_n, red_n, red_e,
+                        n_sorted, nullptr, et_batch, it.batch);
 }
 
 template <int NBN>
@@ -976,7 +993,7 @@ pulay_kernel(const BatchDesc* __restrict__ batches, int b0, const double4* __res
              const int32_t* __restrict__ atom_species, const SpeciesDesc* __restrict__ species,
              const int32_t* __restrict__ shell_l, const T* __restrict__ spline, RadialGrid rg,
              const double* __restrict__ v, const T* __restrict__ Xs, const T* __restrict__ Ys,
-             const double* __restrict__ gE, double* __restrict__ dE_dR) {
+             const double* __restrict__ gE, double* __restrict__ dE_dR, double* __restrict__ gpt) {
   const int bi = blockIdx.x / kPhiSlices;
   const int wave = __builtin_amdgcn_readfirstlane((int)(blockIdx.x % kPhiSlices) * 4 + (int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
@@ -1019,6 +1036,11 @@ pulay_kernel(const BatchDesc* __restrict__ batches, int b0, const double4* __res
       sx += P4.w * (double)gx;
       sy += P4.w * (double)gy;
       sz += P4.w * (double)gz;
+      if (gpt) {     // the same terms summed over atoms per point: the point-motion term
+        unsafeAtomicAdd(gpt + 3 * (size_t)(d.pt_off + p), P4.w * (double)gx);
+        unsafeAtomicAdd(gpt + 3 * (size_t)(d.pt_off + p) + 1, P4.w * (double)gy);
+        unsafeAtomicAdd(gpt + 3 * (size_t)(d.pt_off + p) + 2, P4.w * (double)gz);
+      }
     }
     for (int off = 32; off > 0; off >>= 1) {
       sx += __shfl_xor(sx, off);
@@ -1031,6 +1053,181 @@ pulay_kernel(const BatchDesc* __restrict__ batches, int b0, const double4* __res
       unsafeAtomicAdd(dE_dR + 3 * atom + 2, -ge * sz);
     }
   }
+}
+
+// ------------------------------------------------------------------------------------------
+// Moving-grid terms of the total energy gradient.  Every grid point p belongs to the
+// atom-centred grid of an owner atom o and moves with it; its weight is
+//   w_p = g_p S_o(p) / sum_b S_b(p),  S_b = prod_{c != b} s(mu_bc),
+//   mu_bc = (|p - R_b| - |p - R_c|) / |R_b - R_c|,  s(mu) = (1 - z(mu / a)) / 2,
+//   z(x) = (35 x - 35 x^3 + 21 x^5 - 5 x^7) / 16 on [-1, 1], sign(x) beyond
+// (Stratmann, Scuseria and Frisch), and the potential is v(p) = sum_a -Z_a erf(r_a / sigma) / r_a.
+// ------------------------------------------------------------------------------------------
+
+// v at every point (batch order in, caller order out) for the nuclear model of its system.
+__global__ void __launch_bounds__(256)
+vext_kernel(const double4* __restrict__ pts, const int32_t* __restrict__ perm, int64_t n,
+            const int32_t* __restrict__ pt_sys, const SystemDesc* __restrict__ systems,
+            const int32_t* __restrict__ sys_natoms, const double* __restrict__ atom_xyz,
+            const double* __restrict__ atom_Z, const double* __restrict__ sys_model,
+            double* __restrict__ v_out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double4 P4 = pts[i];
+    const int sy = pt_sys[i];
+    const int a0 = systems[sy].atom_off, na = sys_natoms[sy];
+    const double sigma = sys_model[2 * sy];
+    double v = 0.0;
+    for (int a = a0; a < a0 + na; ++a) {
+      const double dx = P4.x - atom_xyz[3 * a], dy = P4.y - atom_xyz[3 * a + 1],
+                   dz = P4.z - atom_xyz[3 * a + 2];
+      const double r = sqrt(dx * dx + dy * dy + dz * dz);
+      // r -> 0 limit 2 / (sigma sqrt(pi)); grid points never sit on a nucleus
+      v -= atom_Z[a] * (r > 1e-12 ? erf(r / sigma) / r : 2.0 / (sigma * 1.7724538509055160273));
+    }
+    v_out[perm[i]] = v;
+  }
+}
+
+// Switching function s(x) = (1 - z(x)) / 2 of the partition on (-1, 1), with
+// z(x) = (35 x - 35 x^3 + 21 x^5 - 5 x^7) / 16, written as (1 - x)^4 p(x) / 32 with
+// p(x) = 16 + 29 x + 20 x^2 + 5 x^3 (> 0 on [-1, 1]): no cancellation as x -> 1, so s stays
+// positive wherever x < 1.
+__device__ __forceinline__ double switch_p(double x) { return 16.0 + x * (29.0 + x * (20.0 + 5.0 * x)); }
+__device__ __forceinline__ double switch_s(double x) {
+  const double u = 1.0 - x, u2 = u * u;
+  return u2 * u2 * switch_p(x) * (1.0 / 32.0);
+}
+// s'(x) / s(x) = -35 (1 + x)^3 / ((1 - x) p(x)), finite for x < 1 (no division by s)
+__device__ __forceinline__ double switch_dlns(double x) {
+  const double v = 1.0 + x;
+  return -35.0 * v * v * v / ((1.0 - x) * switch_p(x));
+}
+
+// One workgroup per batch, one thread per point (strided).  For a point p with owner o and
+// F_p = v_p n_p + D_p (D_p = sum_ij P_ij phi_i tphi_j at p):
+//   partition:  F_p dw_p/dR_a for every atom, with the point's own motion credited to o;
+//   potential:  w_p n_p dv_p/dR_a likewise (for a != o the atom's own term, for o the others');
+//   basis:      the point-motion sum G_p (from the Pulay pass) credited to o.
+// Per-atom sums of the workgroup are kept in LDS and added to dE/dR (times gE) at the end.
+__global__ void __launch_bounds__(256)
+gridforce_kernel(const BatchDesc* __restrict__ batches, const double4* __restrict__ pts,
+                 const int32_t* __restrict__ perm, const SystemDesc* __restrict__ systems,
+                 const int32_t* __restrict__ sys_natoms, const double* __restrict__ atom_xyz,
+                 const double* __restrict__ atom_Z, const double* __restrict__ sys_model,
+                 const int32_t* __restrict__ pt_owner, const double* __restrict__ pt_wgrid,
+                 const double* __restrict__ v_model, const double* __restrict__ n_sorted,
+                 const double* __restrict__ d_sorted, const double* __restrict__ gpt,
+                 const double* __restrict__ gE, double* __restrict__ dE_dR) {
+  extern __shared__ double acc[];          // [na][3] of this batch's system
+  const BatchDesc d = batches[blockIdx.x];
+  const int a0 = systems[d.sys].atom_off, na = sys_natoms[d.sys];
+  const double sigma = sys_model[2 * d.sys], pa = sys_model[2 * d.sys + 1];
+  const double q = (1.0 + pa) / (1.0 - pa);
+  for (int t = threadIdx.x; t < 3 * na; t += blockDim.x) acc[t] = 0.0;
+  __syncthreads();
+  const double* X = atom_xyz + 3 * (size_t)a0;
+  const double* Z = atom_Z + a0;
+  for (int p = threadIdx.x; p < d.n_p; p += blockDim.x) {
+    const int i = d.pt_off + p;
+    const double4 P4 = pts[i];
+    const int o = pt_owner[i] - a0;
+    const double n = n_sorted[i], F = v_model[perm[i]] * n + d_sorted[i];
+    double go[3] = {0.0, 0.0, 0.0};      // owner's share (the point's own motion)
+    // ---- potential: grad_p of each atom's term -Z erf(r/sigma)/r
+    {
+      const double wn = P4.w * n;
+      for (int a = 0; a < na; ++a) {
+        const double dx = P4.x - X[3 * a], dy = P4.y - X[3 * a + 1], dz = P4.z - X[3 * a + 2];
+        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        if (!(r > 1e-12)) continue;
+        const double e = erf(r / sigma);
+        const double dfr = (1.1283791670955125739 / sigma) * exp(-(r * r) / (sigma * sigma)) / r - e / (r * r);
+        const double c = -Z[a] * dfr / r * wn;     // w n grad_p(v_a) = c (p - R_a)
+        const double gx = c * dx, gy = c * dy, gz = c * dz;
+        if (a != o) {
+          atomicAdd(&acc[3 * a], -gx);
+          atomicAdd(&acc[3 * a + 1], -gy);
+          atomicAdd(&acc[3 * a + 2], -gz);
+          go[0] += gx;
+          go[1] += gy;
+          go[2] += gz;
+        }
+      }
+    }
+    // ---- partition weights: only atoms closer than dmin (1 + a) / (1 - a) have S_b > 0
+    if (na > 1 && F != 0.0) {
+      double dmin = 1e300;
+      for (int b = 0; b < na; ++b) {
+        const double dx = P4.x - X[3 * b], dy = P4.y - X[3 * b + 1], dz = P4.z - X[3 * b + 2];
+        dmin = fmin(dmin, sqrt(dx * dx + dy * dy + dz * dz));
+      }
+      auto S_of = [&](int b, double rb) {      // prod_{c != b} s(mu_bc)
+        double S = 1.0;
+        for (int c = 0; c < na && S > 0.0; ++c) {
+          if (c == b) continue;
+          const double cx = P4.x - X[3 * c], cy = P4.y - X[3 * c + 1], cz = P4.z - X[3 * c + 2];
+          const double rc_ = sqrt(cx * cx + cy * cy + cz * cz);
+          const double ex = X[3 * b] - X[3 * c], ey = X[3 * b + 1] - X[3 * c + 1], ez = X[3 * b + 2] - X[3 * c + 2];
+          const double x = (rb - rc_) / sqrt(ex * ex + ey * ey + ez * ez) / pa;
+          S *= x >= 1.0 ? 0.0 : (x <= -1.0 ? 1.0 : switch_s(x));
+        }
+        return S;
+      };
+      double Ssum = 0.0, So = 0.0;
+      for (int b = 0; b < na; ++b) {
+        const double bx = P4.x - X[3 * b], by = P4.y - X[3 * b + 1], bz = P4.z - X[3 * b + 2];
+        const double rb = sqrt(bx * bx + by * by + bz * bz);
+        if (!(rb < dmin * q)) continue;
+        const double S = S_of(b, rb);
+        Ssum += S;
+        if (b == o) So = S;
+      }
+      const double w = P4.w;        // = g_p So / Ssum, the weight the energy used
+      if (w != 0.0 && So > 0.0 && Ssum > 0.0) {
+        // dw = w sum_b (delta_bo - S_b / Ssum) dln S_b,  dln S_b = sum_c (s'/s)(mu_bc) dmu_bc
+        for (int b = 0; b < na; ++b) {
+          const double bx = P4.x - X[3 * b], by = P4.y - X[3 * b + 1], bz = P4.z - X[3 * b + 2];
+          const double rb = sqrt(bx * bx + by * by + bz * bz);
+          if (!(rb < dmin * q)) continue;
+          const double Sb = S_of(b, rb);
+          if (Sb <= 0.0) continue;
+          const double kap = w * F * ((b == o ? 1.0 : 0.0) - Sb / Ssum);
+          if (kap == 0.0) continue;
+          const double ub[3] = {bx / rb, by / rb, bz / rb};
+          for (int c = 0; c < na; ++c) {
+            if (c == b) continue;
+            const double cx = P4.x - X[3 * c], cy = P4.y - X[3 * c + 1], cz = P4.z - X[3 * c + 2];
+            const double rc_ = sqrt(cx * cx + cy * cy + cz * cz);
+            const double e3[3] = {X[3 * b] - X[3 * c], X[3 * b + 1] - X[3 * c + 1], X[3 * b + 2] - X[3 * c + 2]};
+            const double Rbc = sqrt(e3[0] * e3[0] + e3[1] * e3[1] + e3[2] * e3[2]);
+            const double mu = (rb - rc_) / Rbc;
+            const double x = mu / pa;
+            if (x <= -1.0 || x >= 1.0) continue;             // s is constant there (s' = 0)
+            const double t = kap * switch_dlns(x) / (pa * Rbc);
+            const double uc[3] = {cx / rc_, cy / rc_, cz / rc_};
+            for (int m = 0; m < 3; ++m) {
+              const double e = e3[m] / Rbc;
+              go[m] += t * (ub[m] - uc[m]);                      // via the point (moves with o)
+              atomicAdd(&acc[3 * b + m], t * (-ub[m] - mu * e));  // via R_b
+              atomicAdd(&acc[3 * c + m], t * (uc[m] + mu * e));   // via R_c
+            }
+          }
+        }
+      }
+    }
+    // ---- basis point motion (summed over all functions in the Pulay pass)
+    go[0] += gpt[3 * (size_t)i];
+    go[1] += gpt[3 * (size_t)i + 1];
+    go[2] += gpt[3 * (size_t)i + 2];
+    atomicAdd(&acc[3 * o], go[0]);
+    atomicAdd(&acc[3 * o + 1], go[1]);
+    atomicAdd(&acc[3 * o + 2], go[2]);
+  }
+  __syncthreads();
+  const double ge = gE[0];
+  for (int t = threadIdx.x; t < 3 * na; t += blockDim.x)
+    if (acc[t] != 0.0) unsafeAtomicAdd(dE_dR + 3 * (size_t)a0 + t, ge * acc[t]);
 }
 
 // y[i] = gE * x[i]
@@ -1217,22 +1414,22 @@ hipError_t launch_phi_eval_bf16(const DeviceView& dv, int b0, int nbatch, int mo
 template <typename T, int NBN>
 static void density_launch_nbn(const DeviceView& dv, const TileItem* items, int n_items, const T* P,
                                const T* slab1, const T* slab2, double* n_sorted, double* et_batch,
-                               T* xout, const Queue& q, hipStream_t st) {
+                               T* xout, double* d_sorted, const Queue& q, hipStream_t st) {
   hipLaunchKernelGGL((density_kernel<T, NBN>), dim3(tile_grid(n_items, q, (const void*)density_kernel<T, NBN>)), dim3(256), 0,
                      st, items, n_items, dv.batches, dv.systems, dv.pts, dv.batch_cols, P, slab1, slab2,
-                     n_sorted, et_batch, xout, q.counters);
+                     n_sorted, et_batch, xout, d_sorted, q.counters);
 }
 
 template <typename T>
 hipError_t launch_density(const DeviceView& dv, int nbn, const TileItem* items, int n_items, const T* P,
                           const T* slab1, const T* slab2, double* n_sorted, double* et_batch,
-                          hipStream_t st, T* xout, Queue q) {
+                          hipStream_t st, T* xout, Queue q, double* d_sorted) {
   if (n_items == 0) return hipSuccess;
   switch (nbn) {
-    case 2: density_launch_nbn<T, 2>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, q, st); break;
-    case 3: density_launch_nbn<T, 3>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, q, st); break;
-    case 4: density_launch_nbn<T, 4>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, q, st); break;
-    case 5: density_launch_nbn<T, 5>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, q, st); break;
+    case 2: density_launch_nbn<T, 2>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, d_sorted, q, st); break;
+    case 3: density_launch_nbn<T, 3>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, d_sorted, q, st); break;
+    case 4: density_launch_nbn<T, 4>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, d_sorted, q, st); break;
+    case 5: density_launch_nbn<T, 5>(dv, items, n_items, P, slab1, slab2, n_sorted, et_batch, xout, d_sorted, q, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1273,12 +1470,12 @@ hipError_t launch_density_bf16(const DeviceView& dv, int nbn, const TileItem* it
 
 template <typename T>
 hipError_t launch_pulay(const DeviceView& dv, int b0, int nbatch, const double* v, const T* X,
-                        const T* Y, const double* gE, double* dE_dR, hipStream_t st) {
+                        const T* Y, const double* gE, double* dE_dR, hipStream_t st, double* gpt) {
   if (nbatch == 0) return hipSuccess;
   const T* spline = (const T*)(sizeof(T) == 8 ? (const void*)dv.spline64 : (const void*)dv.spline32);
   hipLaunchKernelGGL(pulay_kernel<T>, dim3(nbatch * kPhiSlices), dim3(256), 0, st, dv.batches, b0, dv.pts,
                      dv.perm, dv.batch_atoms, dv.batch_acol, dv.atom_xyz, dv.atom_species,
-                     dv.species, dv.shell_l, spline, dv.rg, v, X, Y, gE, dE_dR);
+                     dv.species, dv.shell_l, spline, dv.rg, v, X, Y, gE, dE_dR, gpt);
   return hipGetLastError();
 }
 
@@ -1305,6 +1502,28 @@ hipError_t launch_hs_bf16(const DeviceView& dv, const TileItem* items, int n_ite
   return hipGetLastError();
 }
 
+hipError_t launch_vext(const DeviceView& dv, int64_t n, const int32_t* pt_sys,
+                       const int32_t* sys_natoms, const double* atom_Z, const double* sys_model,
+                       double* v_out, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(vext_kernel, dim3(grid_for((size_t)n, 256)), dim3(256), 0, st, dv.pts, dv.perm,
+                     n, pt_sys, dv.systems, sys_natoms, dv.atom_xyz, atom_Z, sys_model, v_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gridforce(const DeviceView& dv, int nbatch, int max_sys_atoms,
+                            const int32_t* sys_natoms, const double* atom_Z, const double* sys_model,
+                            const int32_t* pt_owner, const double* pt_wgrid, const double* v_model,
+                            const double* n_sorted, const double* d_sorted, const double* gpt,
+                            const double* gE, double* dE_dR, hipStream_t st) {
+  if (nbatch == 0) return hipSuccess;
+  const size_t lds = 3 * (size_t)max_sys_atoms * sizeof(double);
+  hipLaunchKernelGGL(gridforce_kernel, dim3(nbatch), dim3(256), lds, st, dv.batches, dv.pts, dv.perm,
+                     dv.systems, sys_natoms, dv.atom_xyz, atom_Z, sys_model, pt_owner, pt_wgrid,
+                     v_model, n_sorted, d_sorted, gpt, gE, dE_dR);
+  return hipGetLastError();
+}
+
 hipError_t launch_density_finish(const DeviceView& dv, const double* n_sorted, const double* v,
                                  double* n_out, double* part, int nblk, const double* et_batch,
                                  double* sums_out, hipStream_t st) {
@@ -1323,14 +1542,14 @@ template hipError_t launch_phi_eval<float>(const DeviceView&, int, int, int, con
                                            float*, float*, hipStream_t);
 template hipError_t launch_density<double>(const DeviceView&, int, const TileItem*, int, const double*,
                                            const double*, const double*, double*, double*,
-                                           hipStream_t, double*, Queue);
+                                           hipStream_t, double*, Queue, double*);
 template hipError_t launch_density<float>(const DeviceView&, int, const TileItem*, int, const float*,
                                           const float*, const float*, double*, double*,
-                                          hipStream_t, float*, Queue);
+                                          hipStream_t, float*, Queue, double*);
 template hipError_t launch_pulay<double>(const DeviceView&, int, int, const double*, const double*,
-                                         const double*, const double*, double*, hipStream_t);
+                                         const double*, const double*, double*, hipStream_t, double*);
 template hipError_t launch_pulay<float>(const DeviceView&, int, int, const double*, const float*,
-                                        const float*, const double*, double*, hipStream_t);
+                                        const float*, const double*, double*, hipStream_t, double*);
 template hipError_t launch_hs<double>(const DeviceView&, const TileItem*, int, const double*,
                                       const double*, double*, hipStream_t, Queue);
 template hipError_t launch_hs<float>(const DeviceView&, const TileItem*, int, const float*,

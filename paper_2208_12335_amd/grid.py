@@ -14,7 +14,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import PRECISION, AimsError, AimsSystem, AimsTuning
+from ._lib import PRECISION, AimsError, AimsMovingGrid, AimsSystem, AimsTuning
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -78,6 +78,7 @@ class AimsGrid:
         if st != 0:
             raise AimsError(st, self._L.aims_last_error(None).decode())
         self._h = h
+        self._systems = list(systems)
         self.n_sys = len(systems)
         self.nb_sys = [self._nb_of(s) for s in systems]
         self.n_basis = int(self._L.aims_n_basis(h))
@@ -129,6 +130,35 @@ class AimsGrid:
                 self._h, PRECISION[prec], self._xyz(atom_xyz), _ptr(P), _ptr(v), _ptr(gE),
                 _ptr(dP), _ptr(dv), _ptr(dR)))
         return dP, dv, dR
+
+    def set_moving_grid(self, systems=None, sigma: float = 0.3, partition_a: float = 0.64):
+        """Moving-grid model of each system for ``total_forces``: the owner atom and the
+        pre-partition weight of every point (``pt_atom``, ``pt_wgrid`` of the systems), the
+        nuclear charges (``atom_Z``), the erf width and the partition parameter."""
+        systems = self._systems if systems is None else systems
+        for k, s in enumerate(systems):
+            owner = np.ascontiguousarray(s.pt_atom, dtype=np.int32)
+            wgrid = np.ascontiguousarray(s.pt_wgrid, dtype=np.float64)
+            Z = np.ascontiguousarray(s.atom_Z, dtype=np.float64)
+            m = AimsMovingGrid()
+            m.pt_owner = _np_ptr(owner, c_int32)
+            m.pt_wgrid = _np_ptr(wgrid, c_double)
+            m.atom_Z = _np_ptr(Z, c_double)
+            m.nuc_sigma = float(sigma)
+            m.partition_a = float(partition_a)
+            self._check(self._L.aims_grid_set_moving(self._h, k, byref(m)))
+
+    def total_forces(self, P: torch.Tensor, gE: Optional[torch.Tensor] = None, prec: str = "fp64",
+                     sums_out=None):
+        """(dE/dR [n_atoms, 3], sums [n_sys, 3]) of the moving-grid energy (grid points,
+        partition weights, nuclear potential and basis centres all follow the atoms)."""
+        gE = torch.ones(1, dtype=torch.float64, device=self.device) if gE is None else gE
+        dR = self._new(self.n_atoms, 3)
+        sums = self._new(self.n_sys, 3) if sums_out is None else sums_out
+        with torch.cuda.device(self.device):
+            self._check(self._L.aims_total_forces(self._h, PRECISION[prec], _ptr(P), _ptr(gE),
+                                                  _ptr(sums), _ptr(dR)))
+        return dR, sums
 
     def blocks(self, flat: torch.Tensor):
         """Views of a flat matrix buffer as one nb_s x nb_s matrix per system."""

@@ -89,5 +89,7 @@ def test_null_arguments(lib, c1):
     assert lib.aims_work_stats(None, None, None, None) == -1
     assert lib.aims_n_basis(None) == -1
     assert lib.aims_step_graph_launch(None) == -1
+    assert lib.aims_grid_set_moving(None, 0, None) == -1
+    assert lib.aims_total_forces(None, 0, None, None, None, None) == -1
     lib.aims_grid_destroy(None)
     lib.aims_step_graph_destroy(None)
