@@ -37,7 +37,8 @@
  * Environment (read at setup): AIMS_SCRATCH_MB sets the scratch budget that bounds a group of
  * batches (default 1024, minimum 16); AIMS_H_MERGE sets the initial h_merge of every precision
  * (0..4); AIMS_FAIL_ALLOC=1 makes every device allocation fail with AIMS_ERR_OOM (to test the
- * error path).
+ * error path); AIMS_FORCES_THREAD_PATH=1 makes aims_total_forces use its thread-per-point kernel
+ * (otherwise taken only above 512 atoms per system) for every system size.
  */
 #ifndef AIMS_GRID_H
 #define AIMS_GRID_H

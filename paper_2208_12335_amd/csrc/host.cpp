@@ -249,6 +249,17 @@ struct aims_grid {
   double* d_vmodel = nullptr;                // model potential, caller order
   double* d_dsorted = nullptr;               // kinetic density per point, batch order
   double* d_gpt = nullptr;                   // point-motion sums, batch order [n][3]
+  // wave-per-point force kernel: 1 / (a R_bc) tables, batch ranges and per-range slots
+  bool force_thread_path = false;           // AIMS_FORCES_THREAD_PATH=1: thread-per-point kernel
+  bool gf_ready = false;
+  int gf_k = 0;
+  int gf_nranges = 0;
+  ForceRange* d_franges = nullptr;
+  double* d_inv_aR = nullptr;
+  int64_t* d_pair_off = nullptr;
+  double* d_fpart = nullptr;
+  int64_t* d_fpart_off = nullptr;
+  int32_t* d_fnrange = nullptr;
 
   ~aims_grid() {
     if (!owned.empty()) {
@@ -606,6 +617,7 @@ aims_grid* build(const aims_system* sys, int n_sys, int device, void* stream) {
     const int m = std::max(0, std::min(4, atoi(e)));
     for (int p = 0; p < 3; ++p) g->h_merge[p] = m;
   }
+  if (const char* e = getenv("AIMS_FORCES_THREAD_PATH")) g->force_thread_path = atoi(e) != 0;
 
   // ---- species, splines, atoms ----------------------------------------------------------
   std::vector<SpeciesDesc> species;
@@ -1155,12 +1167,91 @@ aims_status aims_grid_set_moving(aims_grid* g, int32_t sys, const aims_moving_gr
     g->sys_model[2 * sys] = m->nuc_sigma;
     g->sys_model[2 * sys + 1] = m->partition_a;
     g->moving[sys] = 1;
+    g->gf_ready = false;
     hipchk(hipMemcpy(g->d_owner, g->owner_host.data(), n * sizeof(int32_t), hipMemcpyHostToDevice), "upload");
     hipchk(hipMemcpy(g->d_wgrid, g->wgrid_host.data(), n * sizeof(double), hipMemcpyHostToDevice), "upload");
     hipchk(hipMemcpy(g->d_Z, g->Z_host.data(), g->Z_host.size() * sizeof(double), hipMemcpyHostToDevice), "upload");
     hipchk(hipMemcpy(g->d_sys_model, g->sys_model.data(), g->sys_model.size() * sizeof(double),
                      hipMemcpyHostToDevice), "upload");
   });
+}
+
+// Tables of the wave-per-point force kernel (setup positions, current partition parameters):
+// 1 / (a |R_b - R_c|) per system, and runs of consecutive batches of one system holding about
+// the same number of points, about kForceRanges of them in all.
+constexpr int kForceRanges = 4096;
+constexpr int kForceWaveMaxAtoms = 512;
+
+void build_force_tables(aims_grid* g, int max_na) {
+  int k = 1;
+  while (64 * k < max_na) k *= 2;
+  std::vector<int64_t> pair_off(g->n_sys);
+  int64_t tot = 0;
+  for (int s = 0; s < g->n_sys; ++s) {
+    const int64_t na = g->sys_atom_range[2 * s + 1] - g->sys_atom_range[2 * s];
+    pair_off[s] = tot;
+    tot += na * na;
+  }
+  std::vector<double> inv(std::max<int64_t>(1, tot), 0.0);
+  for (int s = 0; s < g->n_sys; ++s) {
+    const int a0 = (int)g->sys_atom_range[2 * s], na = (int)(g->sys_atom_range[2 * s + 1] - a0);
+    const double a = g->sys_model[2 * s + 1];
+    const double* X = g->atom_xyz0.data() + 3 * (size_t)a0;
+    for (int b = 0; b < na; ++b)
+      for (int c = 0; c < na; ++c) {
+        if (b == c) continue;
+        const double dx = X[3 * b] - X[3 * c], dy = X[3 * b + 1] - X[3 * c + 1], dz = X[3 * b + 2] - X[3 * c + 2];
+        const double r = std::sqrt(dx * dx + dy * dy + dz * dz);
+        if (!(r > 0.0)) fail(AIMS_ERR_ARG, "system %d: atoms %d and %d coincide", s, b, c);
+        inv[pair_off[s] + (int64_t)b * na + c] = 1.0 / (a * r);
+      }
+  }
+  const BatchSet& bs = g->dens;
+  const int64_t nb_all = (int64_t)bs.batches.size();
+  std::vector<ForceRange> ranges;
+  std::vector<int64_t> part_off(g->n_sys, 0);
+  std::vector<int32_t> nrange(g->n_sys, 0);
+  int64_t cursor = 0;
+  for (int s = 0; s < g->n_sys; ++s) {
+    const int na = (int)(g->sys_atom_range[2 * s + 1] - g->sys_atom_range[2 * s]);
+    const int64_t B0 = bs.sys_batch_range[2 * s], B1 = bs.sys_batch_range[2 * s + 1];
+    part_off[s] = cursor;
+    if (B1 <= B0) continue;
+    int64_t npts = 0;
+    for (int64_t b = B0; b < B1; ++b) npts += bs.batches[b].n_p;
+    const int64_t want = std::max<int64_t>(1, std::min<int64_t>(B1 - B0, (kForceRanges * (B1 - B0) + nb_all - 1) / nb_all));
+    const double per = (double)npts / (double)want;
+    int64_t b = B0, acc = 0;
+    for (int64_t r = 0; r < want && b < B1; ++r) {
+      const int64_t start = b;
+      const double goal = per * (double)(r + 1);
+      while (b < B1 && (b == start || (double)(acc + bs.batches[b].n_p) <= goal + 0.5 * per)) acc += bs.batches[b++].n_p;
+      if (r == want - 1) while (b < B1) acc += bs.batches[b++].n_p;
+      ranges.push_back(ForceRange{(int32_t)start, (int32_t)b, s, 0, cursor});
+      cursor += 3 * (int64_t)na;
+      ++nrange[s];
+    }
+  }
+  auto drop = [&](auto*& ptr) {
+    if (ptr) g->release(ptr);
+    ptr = nullptr;
+  };
+  drop(g->d_franges);
+  drop(g->d_inv_aR);
+  drop(g->d_pair_off);
+  drop(g->d_fpart);
+  drop(g->d_fpart_off);
+  drop(g->d_fnrange);
+  g->d_inv_aR = g->upload(inv);
+  g->d_pair_off = g->upload(pair_off);
+  if (ranges.empty()) ranges.push_back(ForceRange{0, 0, 0, 0, 0});     // a valid (unused) entry
+  g->d_franges = g->upload(ranges);
+  g->gf_nranges = (int)(ranges.size() == 1 && ranges[0].b1 == 0 ? 0 : ranges.size());
+  g->d_fpart = (double*)g->alloc(std::max<int64_t>(1, cursor) * sizeof(double));
+  g->d_fpart_off = g->upload(part_off);
+  g->d_fnrange = g->upload(nrange);
+  g->gf_k = k;
+  g->gf_ready = true;
 }
 
 aims_status aims_total_forces(aims_grid* g, aims_precision prec, const double* P, const double* gE,
@@ -1182,6 +1273,7 @@ aims_status aims_total_forces(aims_grid* g, aims_precision prec, const double* P
       max_na = std::max(max_na, (int)(g->sys_atom_range[2 * k + 1] - g->sys_atom_range[2 * k]));
     if (3 * (size_t)max_na * sizeof(double) > 64 * 1024)
       fail(AIMS_ERR_UNSUPPORTED, "total forces support up to %d atoms per system", (int)(64 * 1024 / 24));
+    if (max_na <= kForceWaveMaxAtoms && !g->gf_ready) build_force_tables(g, max_na);
     hipStream_t st = g->stream;
     BatchSet& bs = g->dens;
     if (g->slab_cap34 < bs.slab_elems) {
@@ -1254,11 +1346,21 @@ aims_status aims_total_forces(aims_grid* g, aims_precision prec, const double* P
         });
       }
     }
-    timed(g, kProfBackward, 0.0, "grid", [&] {
-      return launch_gridforce(bs.dv, (int)bs.batches.size(), max_na, g->d_sys_natoms, g->d_Z,
-                              g->d_sys_model, g->d_owner, g->d_wgrid, g->d_vmodel, g->d_n_sorted,
-                              g->d_dsorted, g->d_gpt, gE, dE_dR, st);
-    });
+    if (max_na <= kForceWaveMaxAtoms && !g->force_thread_path) {
+      timed(g, kProfBackward, 0.0, "grid", [&] {
+        return launch_gridforce_wave(bs.dv, g->gf_k, g->d_franges, g->gf_nranges, max_na,
+                                     g->d_sys_natoms, g->d_Z, g->d_sys_model, g->d_pair_off,
+                                     g->d_inv_aR, g->d_owner, g->d_vmodel, g->d_n_sorted,
+                                     g->d_dsorted, g->d_gpt, g->d_fpart, g->d_fpart_off,
+                                     g->d_fnrange, gE, dE_dR, st);
+      });
+    } else {
+      timed(g, kProfBackward, 0.0, "grid", [&] {
+        return launch_gridforce(bs.dv, (int)bs.batches.size(), max_na, g->d_sys_natoms, g->d_Z,
+                                g->d_sys_model, g->d_owner, g->d_wgrid, g->d_vmodel, g->d_n_sorted,
+                                g->d_dsorted, g->d_gpt, gE, dE_dR, st);
+      });
+    }
     if (sums_out_or_null) {
       hipchk(launch_density_finish(bs.dv, g->d_n_sorted, v, g->d_ntmp, g->d_part, g->nblk_finish,
                                    g->d_et_batch, sums_out_or_null, st), "sums");

@@ -74,6 +74,24 @@ hipError_t launch_gridforce(const DeviceView& dv, int nbatch, int max_sys_atoms,
                             const int32_t* pt_owner, const double* pt_wgrid, const double* v_model,
                             const double* n_sorted, const double* d_sorted, const double* gpt,
                             const double* gE, double* dE_dR, hipStream_t st);
+// Wave-per-point form for systems of at most 64 k_chunks atoms (k_chunks in 1, 2, 4, 8):
+// `ranges` are runs of consecutive batches of one system, each with its slot of 3 n_a doubles in
+// `part` (the slots of system s start at sys_part_off[s], sys_nrange[s] of them); a second kernel
+// adds them, in slot order, times gE into dE_dR.
+struct ForceRange {
+  int32_t b0, b1;     // batches [b0, b1)
+  int32_t sys;
+  int32_t pad;
+  int64_t part_off;   // element offset of this range's slot in `part`
+};
+hipError_t launch_gridforce_wave(const DeviceView& dv, int k_chunks, const ForceRange* ranges,
+                                 int n_ranges, int max_sys_atoms, const int32_t* sys_natoms,
+                                 const double* atom_Z, const double* sys_model,
+                                 const int64_t* sys_pair_off, const double* inv_aR,
+                                 const int32_t* pt_owner, const double* v_model,
+                                 const double* n_sorted, const double* d_sorted, const double* gpt,
+                                 double* part, const int64_t* sys_part_off, const int32_t* sys_nrange,
+                                 const double* gE, double* dE_dR, hipStream_t st);
 hipError_t launch_scale(double* y, const double* x, size_t n, const double* gE, hipStream_t st);
 hipError_t launch_dv(const DeviceView& dv, double* dE_dv, const double* n_sorted, int64_t n,
                      const double* gE, hipStream_t st);

@@ -34,11 +34,15 @@ def _gpu_forces(inst, gpu, prec="fp64"):
     return g, dR.cpu().numpy(), s[1] + s[2]
 
 
+@pytest.mark.parametrize("path", ["wave", "thread"])
 @pytest.mark.parametrize("which", ["triatomic", "grown5"])
-def test_total_forces_match_oracle(gpu, which):
+def test_total_forces_match_oracle(gpu, which, path, monkeypatch):
+    # the thread-per-point kernel serves systems above 512 atoms; the switch (read at setup)
+    # runs it on small systems too
+    monkeypatch.setenv("AIMS_FORCES_THREAD_PATH", "1" if path == "thread" else "0")
     inst = (synth.make_instance("c1") if which == "triatomic" else
             synth.make_molecule_set(n_mol=1, seed=3, n_min=5, n_max=5)[0])
-    print(f"[forces] {which}: {inst.n_points} points, {inst.n_atoms} atoms", flush=True)
+    print(f"[forces] {which} ({path}): {inst.n_points} points, {inst.n_atoms} atoms", flush=True)
     g, F, E = _gpu_forces(inst, gpu)
     E_ref, F_ref = moving_grid_gradient(GridOracle(inst), inst.P)
     err = np.max(np.abs(F - F_ref)) / np.max(np.abs(F_ref))
@@ -52,7 +56,7 @@ def test_total_forces_match_oracle(gpu, which):
     assert np.max(np.abs(dRp.cpu().numpy() - F)) > 1e-4 * np.max(np.abs(F))
 
 
-def test_total_forces_cluster_invariance_and_finite_differences(gpu):
+def test_total_forces_cluster_invariance_and_finite_differences(gpu, monkeypatch):
     with synth.generator_device(gpu):
         inst = synth.make_instance("c2", n_atoms=10, box=7.5, seed=4)
     print(f"[forces] cluster: {inst.n_points} points, {inst.n_atoms} atoms", flush=True)
@@ -67,6 +71,15 @@ def test_total_forces_cluster_invariance_and_finite_differences(gpu):
           flush=True)
     assert err <= 1e-9
     assert abs(E - E_ref) <= 1e-10 * abs(E_ref)
+    # repeatability: the moving-grid sums are added in a fixed order, the Pulay pass's per-point
+    # atomics may still change the last bits
+    _, F2, _ = _gpu_forces(inst, gpu)
+    assert np.max(np.abs(F2 - F)) <= 1e-13 * Fmax
+    monkeypatch.setenv("AIMS_FORCES_THREAD_PATH", "1")
+    _, F3, _ = _gpu_forces(inst, gpu)
+    monkeypatch.delenv("AIMS_FORCES_THREAD_PATH")
+    print(f"[forces] cluster thread vs wave kernel: {np.max(np.abs(F3 - F)) / Fmax:.2e}", flush=True)
+    assert np.max(np.abs(F3 - F)) <= 1e-12 * Fmax
 
     P = torch.from_numpy(inst.P).to(gpu).reshape(-1)
 
@@ -91,6 +104,27 @@ def test_total_forces_cluster_invariance_and_finite_differences(gpu):
         an = float(F[a] @ u)
         print(f"[forces] atom {a}: analytic {an:.9f}, finite difference {fd:.9f}", flush=True)
         assert abs(an - fd) <= 1e-7 * Fmax
+
+
+def test_total_forces_grouped_molecules(gpu):
+    """One handle over several molecules: per-system ranges and slots, each system against its
+    own oracle gradient."""
+    mols = synth.make_molecule_set(n_mol=4, seed=11, n_min=2, n_max=6)
+    g = AimsGrid(mols, device=gpu.index)
+    g.set_moving_grid()
+    P = torch.cat([torch.from_numpy(m.P).reshape(-1) for m in mols]).to(gpu)
+    dR, sums = g.total_forces(P)
+    dR = dR.cpu().numpy()
+    sums = sums.cpu().numpy()
+    a = 0
+    for k, m in enumerate(mols):
+        E_ref, F_ref = moving_grid_gradient(GridOracle(m), m.P)
+        F = dR[a:a + m.n_atoms]
+        a += m.n_atoms
+        err = np.max(np.abs(F - F_ref)) / np.max(np.abs(F_ref))
+        print(f"[forces] molecule {k} ({m.n_atoms} atoms): max|dF|/max|F| = {err:.2e}", flush=True)
+        assert err <= 1e-9
+        assert abs(sums[k, 1] + sums[k, 2] - E_ref) <= 1e-10 * abs(E_ref)
 
 
 def test_total_forces_fp32_stated_and_errors(gpu):
