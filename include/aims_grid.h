@@ -35,7 +35,7 @@
  * happens on the host before any launch, and aims_last_error() holds the message.
  *
  * Environment (read at setup): AIMS_SCRATCH_MB sets the scratch budget that bounds a group of
- * batches (default 1024, minimum 16); AIMS_H_MERGE sets the initial h_merge of every precision
+ * batches (default 4096, minimum 16); AIMS_H_MERGE sets the initial h_merge of every precision
  * (0..4); AIMS_FAIL_ALLOC=1 makes every device allocation fail with AIMS_ERR_OOM (to test the
  * error path); AIMS_FORCES_THREAD_PATH=1 makes aims_total_forces use its thread-per-point kernel
  * (otherwise taken only above 512 atoms per system) for every system size.
@@ -102,7 +102,8 @@ aims_status aims_grid_setup(const aims_system *sys, int device, void *hip_stream
  * paper's "Concluding Remarks" describe, here on one GPU).  Their batches are processed
  * together in every call.  Per-system arrays passed to later calls are concatenated in system
  * order: points (n, v, dE/dv), atoms (atom_xyz, dE/dR), and the dense nb_s x nb_s matrices
- * (P, H, S, dE/dP) one after another at offsets sum_{t<s} nb_t^2. */
+ * (P, H, S, dE/dP) one after another at offsets sum_{t<s} nb_t^2.  At most 65535 systems
+ * (AIMS_ERR_UNSUPPORTED beyond). */
 aims_status aims_grid_setup_many(const aims_system *sys, int32_t n_sys, int device,
                                  void *hip_stream, aims_grid **out);
 
