@@ -23,6 +23,9 @@ harmonics without the Condon-Shortley phase, built from the general real-solid-h
 with the atoms (atom-centred grid points, Stratmann partition weights, the erf nuclear
 potential, the basis centres): the total analytic gradient, by torch autograd.
 
+``scf.density_matrix`` takes the step after the H integration: the generalised eigenproblem of
+the symmetric part of H against S, aufbau or Fermi-Dirac occupations, and P = C diag(f) C^T.
+
 Parity status: every function here is pinned by closed forms, invariants, library routines,
 brute force or finite differences in ``tests/test_oracle_*.py``; none is "parity unpinned".
 """
@@ -30,3 +33,4 @@ from .harmonics import real_ylm, real_ylm_grad, ylm_terms  # noqa: F401
 from .radial import RadialSplines  # noqa: F401
 from .integrate import GridOracle  # noqa: F401
 from .forces import moving_grid_gradient  # noqa: F401
+from .scf import density_matrix  # noqa: F401
