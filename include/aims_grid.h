@@ -170,6 +170,31 @@ aims_status aims_grid_set_moving(aims_grid *g, int32_t sys, const aims_moving_gr
 aims_status aims_total_forces(aims_grid *g, aims_precision prec, const double *P, const double *gE,
                               double *sums_out_or_null, double *dE_dR);
 
+/* Density matrix of the occupied subspace: the step after the H integration in an s.c.f.
+ * iteration, the eigensolver stage that the paper names as the bottleneck of large systems
+ * (Development Priorities).  Per system s (basis size nb_s):
+ *     H_sym = (H + H^T) / 2,   H_sym C = S C diag(eps),   C^T S C = I,   P = C diag(f) C^T
+ * with spin-restricted occupations 0 <= f_k <= 2, sum f_k = n_electrons[s]: aufbau for kT = 0
+ * (the lowest floor(N/2) states full, a remaining fraction in the next), Fermi-Dirac
+ * f_k = 2 / (1 + exp((eps_k - mu) / kT)) for kT > 0 with mu fixed by the electron count.
+ * method AIMS_DM_EIGEN: generalised eigensolver (rocSOLVER sygvd), eigenvalues available.
+ * method AIMS_DM_PURIFY: Cholesky orthogonalisation and trace-correcting purification, GEMMs
+ *   only; needs kT = 0, an even electron count and a gap at the Fermi level; no eigenvalues
+ *   (eps_out must be NULL) and mu_out receives NaN.
+ * H, S: DEVICE, the concatenated nb_s x nb_s blocks as aims_integrate_h writes them (H need not
+ * be symmetric; S must be symmetric positive definite).  n_electrons: HOST [n_sys].  P_out:
+ * DEVICE, same layout, symmetric.  eps_out_or_null: DEVICE [sum nb_s], ascending per system.
+ * mu_out_or_null: HOST [n_sys].  Synchronous (it reads eigenvalues or convergence data back).
+ * Errors: AIMS_ERR_ARG for counts that do not fit or an S that is not positive definite,
+ * AIMS_ERR_UNSUPPORTED for the purification limits above, AIMS_ERR_HIP if the purification
+ * does not converge. */
+typedef enum { AIMS_DM_EIGEN = 0, AIMS_DM_PURIFY = 1 } aims_dm_method;
+aims_status aims_density_matrix(aims_grid *g, int32_t method, const double *H, const double *S,
+                                const double *n_electrons, double kT, double *P_out,
+                                double *eps_out_or_null, double *mu_out_or_null);
+/* Matrix products of the last purification (of the last system); 0 after AIMS_DM_EIGEN. */
+int32_t aims_last_purify_products(const aims_grid *g);
+
 /* One s.c.f. step (density update followed by H integration, setup positions) captured once
  * into a HIP graph on the handle's stream; aims_step_graph_launch replays it.  The buffers are
  * baked into the graph and must outlive it; update their contents in place between replays. */

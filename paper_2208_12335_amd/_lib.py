@@ -13,6 +13,7 @@ AIMS_OK, AIMS_ERR_ARG, AIMS_ERR_OOM, AIMS_ERR_HIP, AIMS_ERR_STALE, AIMS_ERR_UNSU
 STATUS_NAMES = {0: "AIMS_OK", -1: "AIMS_ERR_ARG", -2: "AIMS_ERR_OOM", -3: "AIMS_ERR_HIP",
                 -4: "AIMS_ERR_STALE", -5: "AIMS_ERR_UNSUPPORTED"}
 PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+DM_METHOD = {"eigen": 0, "purify": 1}
 
 
 class AimsSystem(ctypes.Structure):
@@ -56,6 +57,9 @@ SIGNATURES = {
                                           c_void_p, c_void_p, c_void_p]),
     "aims_grid_set_moving": (c_int, [c_void_p, c_int32, POINTER(AimsMovingGrid)]),
     "aims_total_forces": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "aims_density_matrix": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, POINTER(c_double), c_double,
+                                    c_void_p, c_void_p, POINTER(c_double)]),
+    "aims_last_purify_products": (c_int32, [c_void_p]),
     "aims_step_graph_create": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
                                        c_void_p, POINTER(c_void_p)]),
     "aims_step_graph_launch": (c_int, [c_void_p]),

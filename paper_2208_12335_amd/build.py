@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libaimsgrid.so")
-SOURCES = ["kernels.hip", "forces.hip", "host.cpp"]
+SOURCES = ["kernels.hip", "forces.hip", "scf.hip", "scf.cpp", "host.cpp"]
 ARCH = os.environ.get("AIMS_OFFLOAD_ARCH", "gfx950")
 
 
@@ -35,12 +35,14 @@ def build(verbose: bool = False) -> str:
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     for src in SOURCES:
-        obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")
+        obj = os.path.join(bdir, src.replace(".", "_") + ".o")
         cmd = [hipcc, *flags, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
         _run(cmd, verbose)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"], verbose)
+    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
+          "-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-lpthread"],
+         verbose)
     os.replace(tmp, LIB)
     return LIB
 

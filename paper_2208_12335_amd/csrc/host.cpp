@@ -20,6 +20,7 @@
 #include "aims_grid.h"
 #include "aims_internal.h"
 #include "kernels.h"
+#include "scf.h"
 
 using namespace aims;
 
@@ -250,6 +251,7 @@ struct aims_grid {
   double* d_dsorted = nullptr;               // kinetic density per point, batch order
   double* d_gpt = nullptr;                   // point-motion sums, batch order [n][3]
   // wave-per-point force kernel: 1 / (a R_bc) tables, batch ranges and per-range slots
+  int dm_iterations = 0;                     // purification products of the last system
   bool force_thread_path = false;           // AIMS_FORCES_THREAD_PATH=1: thread-per-point kernel
   bool gf_ready = false;
   int gf_k = 0;
@@ -261,11 +263,12 @@ struct aims_grid {
   int64_t* d_fpart_off = nullptr;
   int32_t* d_fnrange = nullptr;
 
+  DmSolver dm;                                // density-matrix step (rocBLAS handle, work matrices)
+
   ~aims_grid() {
-    if (!owned.empty()) {
-      (void)hipSetDevice(device);
-      for (void* p : owned) (void)hipFree(p);
-    }
+    (void)hipSetDevice(device);
+    dm_release(dm);
+    for (void* p : owned) (void)hipFree(p);
   }
 
   void* alloc(size_t bytes) {
@@ -1370,6 +1373,48 @@ aims_status aims_total_forces(aims_grid* g, aims_precision prec, const double* P
   });
 }
 
+aims_status aims_density_matrix(aims_grid* g, int32_t method, const double* H, const double* S,
+                                const double* n_electrons, double kT, double* P_out,
+                                double* eps_out_or_null, double* mu_out_or_null) {
+  return guarded(g, [&] {
+    if (method != AIMS_DM_EIGEN && method != AIMS_DM_PURIFY) fail(AIMS_ERR_ARG, "unknown method %d", method);
+    if (!n_electrons) fail(AIMS_ERR_ARG, "null n_electrons");
+    if (!(kT >= 0.0) || !std::isfinite(kT)) fail(AIMS_ERR_ARG, "kT must be finite and >= 0");
+    require_device(H, "H");
+    require_device(S, "S");
+    require_device(P_out, "P_out");
+    if (eps_out_or_null) {
+      if (method == AIMS_DM_PURIFY) fail(AIMS_ERR_UNSUPPORTED, "purification computes no eigenvalues (eps_out must be NULL)");
+      require_device(eps_out_or_null, "eps_out");
+    }
+    for (int k = 0; k < g->n_sys; ++k) {
+      const double ne = n_electrons[k];
+      const int nb = g->systems[k].nb;
+      if (!std::isfinite(ne) || ne < 0.0 || ne > 2.0 * nb)
+        fail(AIMS_ERR_ARG, "system %d: %g electrons do not fit %d states", k, ne, nb);
+      if (method == AIMS_DM_PURIFY) {
+        if (kT != 0.0) fail(AIMS_ERR_UNSUPPORTED, "purification takes aufbau occupations (kT = 0)");
+        if (ne != 2.0 * std::floor(ne / 2.0))
+          fail(AIMS_ERR_UNSUPPORTED, "system %d: purification needs an even electron count (got %g)", k, ne);
+      }
+    }
+    g->dm.stream = g->stream;
+    int64_t eoff = 0;
+    for (int k = 0; k < g->n_sys; ++k) {
+      const int nb = g->systems[k].nb;
+      const int64_t off = g->systems[k].mat_off;
+      double mu = 0.0;
+      std::string err;
+      const int rc = dm_solve(g->dm, method, nb, H + off, S + off, n_electrons[k], kT, P_out + off,
+                              eps_out_or_null ? eps_out_or_null + eoff : nullptr, &mu, err);
+      if (rc) fail((aims_status)rc, "system %d: %s", k, err.c_str());
+      if (mu_out_or_null) mu_out_or_null[k] = mu;
+      eoff += nb;
+    }
+    g->dm_iterations = g->dm.last_iterations;
+  });
+}
+
 struct aims_step_graph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1487,6 +1532,8 @@ int64_t aims_n_points(const aims_grid* g) { return g ? g->n_points : -1; }
 int32_t aims_n_atoms(const aims_grid* g) { return g ? g->n_atoms : -1; }
 
 const char* aims_last_error(const aims_grid* g) { return g ? g->err.c_str() : g_setup_error.c_str(); }
+
+int32_t aims_last_purify_products(const aims_grid* g) { return g ? g->dm_iterations : 0; }
 
 void aims_grid_destroy(aims_grid* g) { delete g; }
 

@@ -14,7 +14,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import PRECISION, AimsError, AimsMovingGrid, AimsSystem, AimsTuning
+from ._lib import DM_METHOD, PRECISION, AimsError, AimsMovingGrid, AimsSystem, AimsTuning
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -159,6 +159,26 @@ class AimsGrid:
             self._check(self._L.aims_total_forces(self._h, PRECISION[prec], _ptr(P), _ptr(gE),
                                                   _ptr(sums), _ptr(dR)))
         return dR, sums
+
+    def density_matrix(self, H: torch.Tensor, S: torch.Tensor, n_electrons, kT: float = 0.0,
+                       method: str = "eigen", P_out=None, want_eps: bool = True):
+        """(P, eps or None, mu [n_sys]) of the occupied subspace: the generalised eigenproblem of
+        the symmetric part of H against S ("eigen"), or trace-correcting purification
+        ("purify", aufbau with an even electron count, no eigenvalues).  H, S, P hold the
+        concatenated per-system blocks; ``n_electrons`` has one count per system."""
+        ne = np.ascontiguousarray(np.broadcast_to(np.asarray(n_electrons, dtype=np.float64),
+                                                  (self.n_sys,)))
+        P = self._new(self.mat_elems) if P_out is None else P_out
+        eps = self._new(int(sum(self.nb_sys))) if (want_eps and method == "eigen") else None
+        mu = np.zeros(self.n_sys)
+        with torch.cuda.device(self.device):
+            self._check(self._L.aims_density_matrix(self._h, DM_METHOD[method], _ptr(H), _ptr(S),
+                                                    _np_ptr(ne, c_double), float(kT), _ptr(P),
+                                                    _ptr(eps), _np_ptr(mu, c_double)))
+        return P, eps, mu
+
+    def last_purify_products(self) -> int:
+        return int(self._L.aims_last_purify_products(self._h))
 
     def blocks(self, flat: torch.Tensor):
         """Views of a flat matrix buffer as one nb_s x nb_s matrix per system."""
