@@ -225,6 +225,32 @@ def bench_single(args, torch, inst, backward=False):
     g.set_tuning(prec="fp64", **res["fp64"]["tuning"])
     ms_S, _ = timer.run(lambda: g.integrate_h(v, prec="fp64", H_out=H, S_out=S, want_S=True), 3, 1)
     outside = {"setup_s": setup_s, "ms_integrate_h_with_S_fp64": ms_S}
+    if not backward:
+        # the step after H: the occupied-subspace density matrix (closed shell), and a whole
+        # s.c.f. iteration (density + H + density matrix) with the density-matrix share of it
+        n_e = float(np.sum(inst.atom_Z))
+        n_e -= n_e % 2
+        P_new = torch.empty(g.mat_elems, dtype=torch.float64, device=dev)
+        dm = {"n_electrons": n_e, "n_basis": inst.n_basis}
+        for meth in ("eigen", "purify"):
+            def solve():
+                g.density_matrix(H, S, n_e, method=meth, P_out=P_new, want_eps=False)
+            try:
+                ms_dm, _ = timer.run(solve, 3, 1)
+            except Exception as e:                 # e.g. no gap for the purification
+                dm[meth] = {"error": str(e)}
+                continue
+            r = {"ms": ms_dm}
+            if meth == "purify":
+                k = g.last_purify_products()
+                r["products"] = k
+                r["gemm_tflops"] = (k + 4) * 2.0 * inst.n_basis ** 3 / (ms_dm * 1e-3) / 1e12
+            ms_it = res["fp64"]["ms_per_step"] + ms_dm
+            r["scf_iteration_ms"] = ms_it
+            r["density_matrix_share"] = ms_dm / ms_it
+            dm[meth] = r
+            _log(f"density matrix ({meth}): {ms_dm:.2f} ms")
+        outside["density_matrix_fp64"] = dm
     if backward and inst.pt_wgrid is not None:
         # total (moving-grid) forces: Pulay + partition-weight + nuclear-potential + point motion
         g.set_moving_grid()
