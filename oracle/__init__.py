@@ -23,6 +23,9 @@ harmonics without the Condon-Shortley phase, built from the general real-solid-h
 with the atoms (atom-centred grid points, Stratmann partition weights, the erf nuclear
 potential, the basis centres): the total analytic gradient, by torch autograd.
 
+``xc.lda`` evaluates the exchange-correlation energy density and potential of the
+spin-unpolarised gas (Slater exchange + Perdew-Wang 1992 correlation) pointwise.
+
 ``scf.density_matrix`` takes the step after the H integration: the generalised eigenproblem of
 the symmetric part of H against S, aufbau or Fermi-Dirac occupations, and P = C diag(f) C^T.
 

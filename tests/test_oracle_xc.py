@@ -1,0 +1,78 @@
+"""Pins of the oracle's exchange-correlation (oracle/xc.py) against textbook constants and
+limits of the uniform electron gas, and its potential against finite differences; CPU only."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.xc import N_MIN, lda, lda_energy
+
+
+def _rs_to_n(rs):
+    return 3.0 / (4.0 * math.pi * np.asarray(rs, dtype=np.float64) ** 3)
+
+
+def test_slater_exchange_constant_and_scaling():
+    # Dirac-Slater: eps_x = -C_x n^(1/3) with C_x = (3/4)(3/pi)^(1/3) = 0.7385587663820224
+    n = np.array([1.0, 8.0, 1e-6, 123.0])
+    r = lda(n)
+    assert np.allclose(r["eps_x"], -0.7385587663820224 * np.cbrt(n), rtol=1e-15, atol=0)
+    # homogeneity of degree 1/3 (a wrong power fails)
+    assert np.allclose(lda(n * 27.0)["eps_x"], 3.0 * r["eps_x"], rtol=1e-14)
+
+
+def test_pw92_high_density_limit():
+    """eps_c = A ln rs + C + O(rs ln rs): A is the exact Gell-Mann-Brueckner coefficient
+    (1 - ln 2) / pi^2, C the second-order constant (about -0.0466 Ha)."""
+    rs = np.array([1e-10, 1e-9])
+    ec = lda(_rs_to_n(rs))["eps_c"]
+    slope = (ec[1] - ec[0]) / math.log(rs[1] / rs[0])
+    assert abs(slope / ((1.0 - math.log(2.0)) / math.pi ** 2) - 1.0) < 2e-5
+    const = ec[0] - slope * math.log(rs[0])
+    assert abs(const + 0.0466) < 3e-4
+
+
+def test_pw92_low_density_limit():
+    # Wigner: eps_c ~ -0.44 / rs for rs -> infinity (rs = 2e4 keeps n above the cutoff; the
+    # next term of the parametrisation is still ~2% there)
+    rs = 2e4
+    ec = lda(_rs_to_n([rs]))["eps_c"][0]
+    assert abs(ec * rs / -0.44 - 1.0) < 0.05
+
+
+def test_correlation_negative_and_monotone():
+    rs = np.geomspace(1e-3, 1e3, 200)
+    ec = lda(_rs_to_n(rs))["eps_c"]
+    assert np.all(ec < 0) and np.all(np.diff(ec) > 0)       # weaker as the gas thins
+
+
+def test_potential_is_the_derivative():
+    n = np.geomspace(1e-8, 1e3, 40)
+    v = lda(n)["v"]
+    for k in (0, 13, 27, 39):
+        h = 1e-5 * n[k]
+        f = lambda x: x * lda(np.array([x]))["eps"][0]
+        fd = (f(n[k] + h) - f(n[k] - h)) / (2 * h)
+        assert abs(v[k] - fd) < 1e-8 * abs(v[k])
+
+
+def test_empty_and_negative_density():
+    r = lda(np.array([0.0, -1e-3, N_MIN, 2 * N_MIN]))
+    assert np.all(r["eps"][:3] == 0.0) and np.all(r["v"][:3] == 0.0)
+    assert r["eps"][3] < 0.0
+    e = lda_energy(np.array([-1.0, 0.0]), np.array([1.0, 1.0]))
+    assert e["E_xc"] == 0.0 and e["nv"] == 0.0
+
+
+def test_hydrogen_exact_density_exchange():
+    """Exact 1s density n = e^{-2r}/pi: E_x^LDA = -C_x int n^(4/3) = -C_x 4 pi^(-1/3) 2 / (8/3)^3,
+    here by radial Gauss-Laguerre quadrature (an independent integral)."""
+    x, wx = np.polynomial.laguerre.laggauss(60)          # int_0^inf e^{-x} f(x) dx
+    r = x / 2.0
+    n = np.exp(-2.0 * r) / math.pi
+    w = 4.0 * math.pi * r * r * np.exp(x) * wx / 2.0
+    E = lda_energy(n, w)
+    c_x = 0.75 * (3.0 / math.pi) ** (1.0 / 3.0)
+    Ex = float(np.sum(w * n * lda(n)["eps_x"]))
+    assert abs(Ex + c_x * 4.0 * math.pi ** (-1.0 / 3.0) * 2.0 / (8.0 / 3.0) ** 3) < 1e-12
+    assert E["E_xc"] < Ex < 0.0                          # correlation lowers it further
