@@ -170,6 +170,19 @@ aims_status aims_grid_set_moving(aims_grid *g, int32_t sys, const aims_moving_gr
 aims_status aims_total_forces(aims_grid *g, aims_precision prec, const double *P, const double *gE,
                               double *sums_out_or_null, double *dE_dR);
 
+/* Exchange-correlation potential on the grid, the step between the density and the H
+ * integration of an s.c.f. iteration for the semilocal functionals the paper names
+ * (Background and Current Status).  Spin-unpolarised LDA: Slater exchange
+ * eps_x = -(3/4)(3 n/pi)^(1/3) and the Perdew-Wang 1992 correlation eps_c(rs), rs =
+ * (3/(4 pi n))^(1/3); v_xc = d(n eps_xc)/dn.  Points with n <= 1e-14 (including negative
+ * densities) get eps = v = 0.
+ * n: DEVICE [n_points] (caller order, e.g. aims_update_density's output); v_xc_out: DEVICE
+ * [n_points]; sums_out_or_null: DEVICE [n_sys][2] = (E_xc = sum_p w_p n_p eps_xc, sum_p w_p n_p
+ * v_xc).  Asynchronous on the handle's stream. */
+typedef enum { AIMS_XC_LDA_PW92 = 0 } aims_xc_functional;
+aims_status aims_xc(aims_grid *g, int32_t functional, const double *n, double *v_xc_out,
+                    double *sums_out_or_null);
+
 /* Density matrix of the occupied subspace: the step after the H integration in an s.c.f.
  * iteration, the eigensolver stage that the paper names as the bottleneck of large systems
  * (Development Priorities).  Per system s (basis size nb_s):

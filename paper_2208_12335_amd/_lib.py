@@ -14,6 +14,7 @@ STATUS_NAMES = {0: "AIMS_OK", -1: "AIMS_ERR_ARG", -2: "AIMS_ERR_OOM", -3: "AIMS_
                 -4: "AIMS_ERR_STALE", -5: "AIMS_ERR_UNSUPPORTED"}
 PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 DM_METHOD = {"eigen": 0, "purify": 1}
+XC_FUNCTIONAL = {"lda": 0}
 
 
 class AimsSystem(ctypes.Structure):
@@ -57,6 +58,7 @@ SIGNATURES = {
                                           c_void_p, c_void_p, c_void_p]),
     "aims_grid_set_moving": (c_int, [c_void_p, c_int32, POINTER(AimsMovingGrid)]),
     "aims_total_forces": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "aims_xc": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
     "aims_density_matrix": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, POINTER(c_double), c_double,
                                     c_void_p, c_void_p, POINTER(c_double)]),
     "aims_last_purify_products": (c_int32, [c_void_p]),

@@ -21,6 +21,7 @@
 #include "aims_internal.h"
 #include "kernels.h"
 #include "scf.h"
+#include "xc.h"
 
 using namespace aims;
 
@@ -251,6 +252,7 @@ struct aims_grid {
   double* d_dsorted = nullptr;               // kinetic density per point, batch order
   double* d_gpt = nullptr;                   // point-motion sums, batch order [n][3]
   // wave-per-point force kernel: 1 / (a R_bc) tables, batch ranges and per-range slots
+  double* d_xc_part = nullptr;               // per-block partial sums of the xc kernels
   int dm_iterations = 0;                     // purification products of the last system
   bool force_thread_path = false;           // AIMS_FORCES_THREAD_PATH=1: thread-per-point kernel
   bool gf_ready = false;
@@ -1412,6 +1414,18 @@ aims_status aims_density_matrix(aims_grid* g, int32_t method, const double* H, c
       eoff += nb;
     }
     g->dm_iterations = g->dm.last_iterations;
+  });
+}
+
+aims_status aims_xc(aims_grid* g, int32_t functional, const double* n, double* v_xc_out,
+                    double* sums_out_or_null) {
+  return guarded(g, [&] {
+    if (functional != AIMS_XC_LDA_PW92) fail(AIMS_ERR_UNSUPPORTED, "unknown functional %d", functional);
+    require_device(n, "n");
+    require_device(v_xc_out, "v_xc_out");
+    if (sums_out_or_null) require_device(sums_out_or_null, "sums_out");
+    if (!g->d_xc_part) g->d_xc_part = (double*)g->alloc(2 * (size_t)kXcBlocks * g->n_sys * sizeof(double));
+    hipchk(launch_lda(g->dens.dv, n, v_xc_out, g->d_xc_part, sums_out_or_null, g->stream), "xc");
   });
 }
 

@@ -1,0 +1,18 @@
+// Exchange-correlation step on the grid (xc.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace aims {
+
+constexpr int kXcBlocks = 256;   // blocks per system of the pointwise kernels
+
+// v_out[q] = v_xc(n[q]) (caller order) of the spin-unpolarised LDA (Slater + PW92); with
+// sums_or_null, sums[s] = (E_xc = sum w n eps_xc, sum w n v_xc) per system.  part: 2 kXcBlocks
+// n_sys doubles of scratch.
+hipError_t launch_lda(const DeviceView& dv, const double* n, double* v_out, double* part,
+                      double* sums_or_null, hipStream_t st);
+
+}  // namespace aims

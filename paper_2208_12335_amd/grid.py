@@ -14,7 +14,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import DM_METHOD, PRECISION, AimsError, AimsMovingGrid, AimsSystem, AimsTuning
+from ._lib import DM_METHOD, PRECISION, XC_FUNCTIONAL, AimsError, AimsMovingGrid, AimsSystem, AimsTuning
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -159,6 +159,16 @@ class AimsGrid:
             self._check(self._L.aims_total_forces(self._h, PRECISION[prec], _ptr(P), _ptr(gE),
                                                   _ptr(sums), _ptr(dR)))
         return dR, sums
+
+    def xc(self, n: torch.Tensor, functional: str = "lda", v_out=None, sums_out=None):
+        """(v_xc [n_points], sums [n_sys, 2] = (E_xc, sum w n v_xc)) of the density n (caller
+        order)."""
+        v = self._new(self.n_points) if v_out is None else v_out
+        sums = self._new(self.n_sys, 2) if sums_out is None else sums_out
+        with torch.cuda.device(self.device):
+            self._check(self._L.aims_xc(self._h, XC_FUNCTIONAL[functional], _ptr(n), _ptr(v),
+                                        _ptr(sums)))
+        return v, sums
 
     def density_matrix(self, H: torch.Tensor, S: torch.Tensor, n_electrons, kT: float = 0.0,
                        method: str = "eigen", P_out=None, want_eps: bool = True):
