@@ -14,6 +14,9 @@ LDA = Slater exchange + the Perdew-Wang (1992) parametrisation of the correlatio
 Points with n <= N_MIN (including the negative densities of unphysical P) contribute nothing:
 eps = v = 0 there.  The derivative is taken by torch autograd in float64, not by a formula, so
 the oracle's potential is the exact derivative of its energy density.
+
+``density_gradient`` gives n and grad n = sum_ij P_ij grad(phi_i phi_j) at the grid points, the
+input of the gradient-corrected functionals, by autograd with respect to the point positions.
 """
 from __future__ import annotations
 
@@ -53,3 +56,27 @@ def lda_energy(n: np.ndarray, w: np.ndarray) -> Dict[str, float]:
     r = lda(n)
     n = np.asarray(n, dtype=np.float64)
     return {"E_xc": float(np.sum(w * n * r["eps"])), "nv": float(np.sum(w * n * r["v"]))}
+
+
+def density_gradient(oracle, P: np.ndarray, chunk: int = 2048):
+    """(n [n_points], grad n [n_points, 3]) of ``oracle.inst`` for the density matrix P:
+    n = sum_ij P_ij phi_i phi_j, differentiated with respect to each point's position through
+    the basis (torch autograd, float64)."""
+    import torch
+    inst = oracle.inst
+    R = torch.tensor(inst.atom_xyz, dtype=torch.float64)
+    Pt = torch.from_numpy(np.ascontiguousarray(P, dtype=np.float64))
+    n_all = np.zeros(inst.n_points)
+    g_all = np.zeros((inst.n_points, 3))
+    for s0 in range(0, inst.n_points, chunk):
+        idx = np.arange(s0, min(inst.n_points, s0 + chunk))
+        atoms = oracle.relevant_atoms(inst.pt_xyz[idx], inst.atom_xyz)
+        if atoms.size == 0:
+            continue
+        pts = torch.tensor(inst.pt_xyz[idx], dtype=torch.float64, requires_grad=True)
+        Phi, _, cols = oracle._basis_torch(pts, R[torch.from_numpy(atoms)], atoms)
+        n = ((Phi @ Pt[np.ix_(cols, cols)]) * Phi).sum(1)
+        (g,) = torch.autograd.grad(n.sum(), pts)
+        n_all[idx] = n.detach().numpy()
+        g_all[idx] = g.numpy()
+    return n_all, g_all

@@ -76,3 +76,49 @@ def test_hydrogen_exact_density_exchange():
     Ex = float(np.sum(w * n * lda(n)["eps_x"]))
     assert abs(Ex + c_x * 4.0 * math.pi ** (-1.0 / 3.0) * 2.0 / (8.0 / 3.0) ** 3) < 1e-12
     assert E["E_xc"] < Ex < 0.0                          # correlation lowers it further
+
+
+def _gauss_s(a):
+    # R = e^{-a r^2}, K = -1/2 (R'' + 2 R'/r) = -1/2 (4 a^2 r^2 - 6 a) e^{-a r^2}
+    return lambda r: (np.exp(-a * r * r), -0.5 * (4 * a * a * r * r - 6 * a) * np.exp(-a * r * r))
+
+
+def test_density_gradient_closed_form():
+    """One s Gaussian, phi = e^{-a r^2} Y_00: n = P00 e^{-2 a r^2} / (4 pi) and
+    grad n = -4 a (p - R) n."""
+    import synth
+    from oracle import GridOracle
+    from oracle.xc import density_gradient
+    a, P00 = 0.7, 1.3
+    centre = np.array([[0.3, -0.2, 0.5]])
+    inst = synth.custom_instance(centre, [0], [[0]], [_gauss_s(a)], n_log=1000, n_radial=30,
+                                 angular="gl110")
+    n, g = density_gradient(GridOracle(inst), np.array([[P00]]))
+    d = inst.pt_xyz - centre
+    r2 = (d * d).sum(1)
+    n_ref = P00 * np.exp(-2 * a * r2) / (4 * math.pi)
+    keep = r2 < 20.0                     # inside the tabulated range, away from the cutoff
+    assert np.max(np.abs(n - n_ref)[keep]) < 1e-8
+    assert np.max(np.abs(g + 4 * a * d * n_ref[:, None])[keep]) < 1e-7
+
+
+def test_density_gradient_finite_differences():
+    import synth
+    from oracle import GridOracle
+    from oracle.xc import density_gradient
+    inst = synth.make_instance("c1")
+    o = GridOracle(inst)
+    n, g = density_gradient(o, inst.P)
+    rng = np.random.default_rng(3)
+    for i in rng.choice(inst.n_points, 12, replace=False):
+        p = inst.pt_xyz[i]
+        for c in range(3):
+            h = 1e-5
+            e = np.zeros(3)
+            e[c] = h
+            vals = []
+            for q in (p + e, p - e):
+                Phi, _, cols = o.basis_values(q[None, :], atoms=np.arange(inst.n_atoms))
+                vals.append(float(Phi[0] @ inst.P[np.ix_(cols, cols)] @ Phi[0]))
+            fd = (vals[0] - vals[1]) / (2 * h)
+            assert abs(fd - g[i, c]) <= 1e-6 * max(1.0, np.abs(g[i]).max())
