@@ -170,6 +170,14 @@ aims_status aims_grid_set_moving(aims_grid *g, int32_t sys, const aims_moving_gr
 aims_status aims_total_forces(aims_grid *g, aims_precision prec, const double *P, const double *gE,
                               double *sums_out_or_null, double *dE_dR);
 
+/* Density and its gradient at every point, the input of gradient-corrected functionals:
+ *     n(p) = sum_ij P_ij phi_i(p) phi_j(p),   grad n(p) = 2 sum_ij P_ij phi_i(p) grad phi_j(p)
+ * (P symmetric, the caller's responsibility), FP64, at the setup positions.  P: DEVICE
+ * [nb][nb] blocks; grad_out: DEVICE [n_points][3] (caller order); n_out_or_null: DEVICE
+ * [n_points]. */
+aims_status aims_density_gradient(aims_grid *g, const double *P, double *n_out_or_null,
+                                  double *grad_out);
+
 /* Exchange-correlation potential on the grid, the step between the density and the H
  * integration of an s.c.f. iteration for the semilocal functionals the paper names
  * (Background and Current Status).  Spin-unpolarised LDA: Slater exchange

@@ -1417,6 +1417,55 @@ aims_status aims_density_matrix(aims_grid* g, int32_t method, const double* H, c
   });
 }
 
+aims_status aims_density_gradient(aims_grid* g, const double* P, double* n_out_or_null,
+                                  double* grad_out) {
+  return guarded(g, [&] {
+    require_device(P, "P");
+    require_device(grad_out, "grad_out", g->n_points > 0);
+    if (n_out_or_null) require_device(n_out_or_null, "n_out", g->n_points > 0);
+    set_positions(g, nullptr);
+    if (g->moved) fail(AIMS_ERR_ARG, "the density gradient is taken at the setup positions");
+    hipStream_t st = g->stream;
+    BatchSet& bs = g->dens;
+    if (g->slab_cap34 < bs.slab_elems) {
+      if (g->d_slab3) g->release(g->d_slab3);
+      if (g->d_slab4) g->release(g->d_slab4);
+      g->d_slab3 = g->d_slab4 = nullptr;
+      g->slab_cap34 = 0;
+      g->d_slab3 = g->alloc(bs.slab_elems * sizeof(double));
+      g->d_slab4 = g->alloc(bs.slab_elems * sizeof(double));
+      g->slab_cap34 = bs.slab_elems;
+    }
+    if (!g->d_ntmp) {
+      g->d_ntmp = (double*)g->alloc(std::max<int64_t>(1, g->n_points) * sizeof(double));
+      g->d_sums_tmp = (double*)g->alloc(3 * (size_t)g->n_sys * sizeof(double));
+    }
+    hipchk(launch_fill(g->d_n_sorted, (size_t)g->n_points, 0.0, st), "fill n");
+    hipchk(launch_fill(g->d_et_batch, bs.batches.size(), 0.0, st), "fill E_T");
+    const ItemList& L = items_for(g, bs, g->d_pblocks[AIMS_FP64]);
+    double *s1 = (double*)g->d_slab1, *s2 = (double*)g->d_slab2, *s3 = (double*)g->d_slab3;
+    for (size_t gi = 0; gi < bs.groups.size(); ++gi) {
+      const auto& gr = bs.groups[gi];
+      const int nbt = gr.b1 - gr.b0;
+      timed(g, kProfPhi, 0.0, "phi_eval", [&] {
+        return launch_phi_eval<double>(bs.dv, gr.b0, nbt, kModeDensity, nullptr, s1, s2, st);
+      });
+      for (const auto& run : L.runs[gi]) {
+        const int nit = (int)(run.i1 - run.i0);
+        timed(g, kProfDensity, gr.flops / L.runs[gi].size(), "X", [&] {
+          return launch_density<double>(bs.dv, run.nbn, L.d_items + run.i0, nit, P, s1, s2,
+                                        g->d_n_sorted, g->d_et_batch, st, s3);
+        });
+      }
+      hipchk(launch_gradn(bs.dv, gr.b0, nbt, s3, grad_out, st), "density gradient");
+    }
+    if (n_out_or_null)
+      hipchk(launch_density_finish(bs.dv, g->d_n_sorted, nullptr, n_out_or_null, g->d_part,
+                                   g->nblk_finish, g->d_et_batch, g->d_sums_tmp, st),
+             "density");
+  });
+}
+
 aims_status aims_xc(aims_grid* g, int32_t functional, const double* n, double* v_xc_out,
                     double* sums_out_or_null) {
   return guarded(g, [&] {

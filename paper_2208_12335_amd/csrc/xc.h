@@ -15,4 +15,9 @@ constexpr int kXcBlocks = 256;   // blocks per system of the pointwise kernels
 hipError_t launch_lda(const DeviceView& dv, const double* n, double* v_out, double* part,
                       double* sums_or_null, hipStream_t st);
 
+// grad_out[q] (caller order, 3 per point) = 2 sum_j X_pj grad phi_j(p) for the batches
+// [b0, b0 + nbatch) of dv, X^T being the function-major slab of the X pass (FP64)
+hipError_t launch_gradn(const DeviceView& dv, int b0, int nbatch, const double* X, double* grad_out,
+                        hipStream_t st);
+
 }  // namespace aims

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include "aims_internal.h"
+#include "basis.h"
 #include "kernels.h"
 #include "xc.h"
 
@@ -97,7 +98,101 @@ __global__ void __launch_bounds__(256) xc_sums_kernel(const double* __restrict__
   }
 }
 
+// Gradients of the 2L+1 functions of one shell at a point (u = (p - R_a)/r, ir = 1/r):
+//   grad phi = (R' - L R / r) Y_lm u + (R / r) grad S_lm(u)
+// handed to f(m, gx, gy, gz).
+template <int L, typename F>
+__device__ __forceinline__ void shell_grad(const double* __restrict__ c, double dt, double ir,
+                                           double ux, double uy, double uz, F&& f) {
+  const double R = cubic(c, dt), dR = cubic_d(c, dt) * ir;
+  double Yl[7], Gx[7], Gy[7], Gz[7];
+  ylm_l<double>(L, ux, uy, uz, Yl);
+  ylm_grad_l<double>(L, ux, uy, uz, Gx, Gy, Gz);
+  const double aR = dR - double(L) * R * ir, bR = R * ir;
+#pragma unroll
+  for (int m = 0; m < 2 * L + 1; ++m) {
+    const double a = aR * Yl[m];
+    f(m, a * ux + bR * Gx[m], a * uy + bR * Gy[m], a * uz + bR * Gz[m]);
+  }
+}
+
+// f(column of the function within the batch, grad phi) for every function of the batch's atom k
+// at point P4 (nothing beyond the cutoff)
+template <typename F>
+__device__ __forceinline__ void atom_grads(const BatchDesc& d, int k, double4 P4,
+                                           const int32_t* __restrict__ batch_atoms,
+                                           const int32_t* __restrict__ batch_acol,
+                                           const double* __restrict__ atom_xyz,
+                                           const int32_t* __restrict__ atom_species,
+                                           const SpeciesDesc* __restrict__ species,
+                                           const int32_t* __restrict__ shell_l,
+                                           const double* __restrict__ spline, const RadialGrid& rg,
+                                           F&& f) {
+  const int atom = batch_atoms[d.atom_off + k];
+  const int col0 = batch_acol[d.atom_off + k];
+  const SpeciesDesc sd = species[atom_species[atom]];
+  const double dx = P4.x - atom_xyz[3 * atom], dy = P4.y - atom_xyz[3 * atom + 1],
+               dz = P4.z - atom_xyz[3 * atom + 2];
+  const double r = sqrt(dx * dx + dy * dy + dz * dz);
+  if (!(r < rg.rc)) return;
+  const double rr = fmax(r, 1e-12), ir = 1.0 / rr;
+  const double ux = dx * ir, uy = dy * ir, uz = dz * ir;
+  const RadialPos rp = radial_pos(rr, rg);
+  const double* c = spline + sd.spline_off + (size_t)rp.k * sd.nshell * 8;
+  int col = col0;
+  for (int j = 0; j < sd.nshell; ++j) {
+    const int l = shell_l[sd.shell_l_off + j];
+    auto g = [&](int m, double gx, double gy, double gz) { f(col + m, gx, gy, gz); };
+    switch (l) {
+      case 0: shell_grad<0>(c + j * 8, rp.dt, ir, ux, uy, uz, g); break;
+      case 1: shell_grad<1>(c + j * 8, rp.dt, ir, ux, uy, uz, g); break;
+      case 2: shell_grad<2>(c + j * 8, rp.dt, ir, ux, uy, uz, g); break;
+      default: shell_grad<3>(c + j * 8, rp.dt, ir, ux, uy, uz, g); break;
+    }
+    col += 2 * l + 1;
+  }
+}
+
+// grad n(p) = 2 sum_j X_pj grad phi_j(p) with X^T = P_b Phi^T in the function-major slab Xs
+// (P symmetric).  One workgroup per batch, one thread per point, the batch's atoms in a loop:
+// every point's sum stays in registers and is written once, in caller order.
+__global__ void __launch_bounds__(256)
+gradn_kernel(const BatchDesc* __restrict__ batches, int b0, const double4* __restrict__ pts,
+             const int32_t* __restrict__ perm, const int32_t* __restrict__ batch_atoms,
+             const int32_t* __restrict__ batch_acol, const double* __restrict__ atom_xyz,
+             const int32_t* __restrict__ atom_species, const SpeciesDesc* __restrict__ species,
+             const int32_t* __restrict__ shell_l, const double* __restrict__ spline, RadialGrid rg,
+             const double* __restrict__ Xs, double* __restrict__ grad_out) {
+  const BatchDesc d = batches[b0 + blockIdx.x];
+  const double* X = Xs + d.slab_off;
+  for (int p = threadIdx.x; p < d.n_p; p += blockDim.x) {
+    const double4 P4 = pts[d.pt_off + p];
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+    for (int k = 0; k < d.n_atoms; ++k)
+      atom_grads(d, k, P4, batch_atoms, batch_acol, atom_xyz, atom_species, species, shell_l,
+                 spline, rg, [&](int col, double ax, double ay, double az) {
+                   const double xv = X[(size_t)col * d.ldp + p];
+                   gx += xv * ax;
+                   gy += xv * ay;
+                   gz += xv * az;
+                 });
+    const size_t q = (size_t)perm[d.pt_off + p];
+    grad_out[3 * q] = 2.0 * gx;
+    grad_out[3 * q + 1] = 2.0 * gy;
+    grad_out[3 * q + 2] = 2.0 * gz;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_gradn(const DeviceView& dv, int b0, int nbatch, const double* X, double* grad_out,
+                        hipStream_t st) {
+  if (nbatch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gradn_kernel, dim3(nbatch), dim3(256), 0, st, dv.batches, b0, dv.pts, dv.perm,
+                     dv.batch_atoms, dv.batch_acol, dv.atom_xyz, dv.atom_species, dv.species,
+                     dv.shell_l, dv.spline64, dv.rg, X, grad_out);
+  return hipGetLastError();
+}
 
 hipError_t launch_lda(const DeviceView& dv, const double* n, double* v_out, double* part,
                       double* sums_or_null, hipStream_t st) {

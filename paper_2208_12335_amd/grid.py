@@ -160,6 +160,14 @@ class AimsGrid:
                                                   _ptr(sums), _ptr(dR)))
         return dR, sums
 
+    def density_gradient(self, P: torch.Tensor, n_out=None, grad_out=None, want_n: bool = True):
+        """(n [n_points] or None, grad n [n_points, 3]) in caller order (FP64)."""
+        n = (self._new(self.n_points) if n_out is None else n_out) if want_n else None
+        grad = self._new(self.n_points, 3) if grad_out is None else grad_out
+        with torch.cuda.device(self.device):
+            self._check(self._L.aims_density_gradient(self._h, _ptr(P), _ptr(n), _ptr(grad)))
+        return n, grad
+
     def xc(self, n: torch.Tensor, functional: str = "lda", v_out=None, sums_out=None):
         """(v_xc [n_points], sums [n_sys, 2] = (E_xc, sum w n v_xc)) of the density n (caller
         order)."""

@@ -75,3 +75,31 @@ def test_lda_grouped(gpu):
         e = lda_energy(ns[k], m.pt_w)
         assert abs(sums[k, 0] - e["E_xc"]) <= 1e-12 * abs(e["E_xc"])
         off += m.n_points
+
+
+@pytest.mark.parametrize("which", ["triatomic", "cluster10"])
+def test_density_gradient_matches_oracle(gpu, which):
+    from oracle.xc import density_gradient
+    inst = (synth.make_instance("c1") if which == "triatomic" else
+            synth.make_instance("c2", n_atoms=10, box=7.5, seed=4))
+    g = AimsGrid(inst, device=gpu.index)
+    n, grad = g.density_gradient(torch.from_numpy(inst.P).to(gpu).reshape(-1))
+    n_ref, g_ref = density_gradient(GridOracle(inst), inst.P)
+    en = np.max(np.abs(n.cpu().numpy() - n_ref)) / np.max(np.abs(n_ref))
+    eg = np.max(np.abs(grad.cpu().numpy() - g_ref)) / np.max(np.abs(g_ref))
+    print(f"[xc] grad n {which}: n {en:.1e}, grad {eg:.1e}", flush=True)
+    assert en <= 1e-12 and eg <= 1e-12
+
+
+def test_density_gradient_grouped(gpu):
+    from oracle.xc import density_gradient
+    mols = synth.make_molecule_set(n_mol=3, seed=29, n_min=2, n_max=5)
+    g = AimsGrid(mols, device=gpu.index)
+    P = torch.cat([torch.from_numpy(m.P).reshape(-1) for m in mols]).to(gpu)
+    _, grad = g.density_gradient(P, want_n=False)
+    grad = grad.cpu().numpy()
+    off = 0
+    for m in mols:
+        _, g_ref = density_gradient(GridOracle(m), m.P)
+        assert np.max(np.abs(grad[off:off + m.n_points] - g_ref)) <= 1e-12 * np.max(np.abs(g_ref))
+        off += m.n_points
