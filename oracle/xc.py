@@ -17,6 +17,9 @@ the oracle's potential is the exact derivative of its energy density.
 
 ``density_gradient`` gives n and grad n = sum_ij P_ij grad(phi_i phi_j) at the grid points, the
 input of the gradient-corrected functionals, by autograd with respect to the point positions.
+
+``vector_term`` is the matrix B_ij = sum_p w_p phi_i(p) u_p . grad phi_j(p) of a vector field u
+on the grid: the gradient-corrected part of H is B + B^T with u = 2 v_sigma grad n.
 """
 from __future__ import annotations
 
@@ -80,3 +83,18 @@ def density_gradient(oracle, P: np.ndarray, chunk: int = 2048):
         n_all[idx] = n.detach().numpy()
         g_all[idx] = g.numpy()
     return n_all, g_all
+
+
+def vector_term(oracle, u: np.ndarray, chunk: int = 4096) -> np.ndarray:
+    """B [nb, nb] with B_ij = sum_p w_p phi_i(p) u_p . grad phi_j(p) (closed-form basis
+    gradients), for u [n_points, 3]."""
+    inst = oracle.inst
+    B = np.zeros((oracle.nb, oracle.nb))
+    for s0 in range(0, inst.n_points, chunk):
+        idx = np.arange(s0, min(inst.n_points, s0 + chunk))
+        Phi, _, cols, GPhi, _ = oracle.basis_values(inst.pt_xyz[idx], grad=True)
+        if cols.size == 0:
+            continue
+        D = np.einsum("pjc,pc->pj", GPhi, u[idx])
+        B[np.ix_(cols, cols)] += (Phi * inst.pt_w[idx][:, None]).T @ D
+    return B

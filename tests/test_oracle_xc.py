@@ -122,3 +122,43 @@ def test_density_gradient_finite_differences():
                 vals.append(float(Phi[0] @ inst.P[np.ix_(cols, cols)] @ Phi[0]))
             fd = (vals[0] - vals[1]) / (2 * h)
             assert abs(fd - g[i, c]) <= 1e-6 * max(1.0, np.abs(g[i]).max())
+
+
+def test_vector_term_two_gaussians_closed_form():
+    """phi_1 = e^{-a|r-A|^2} Y00, phi_2 = e^{-b|r-B|^2} Y00, constant field c:
+    B_12 = int phi_1 c.grad phi_2 = -(2ab/(a+b)) c.(A - B) S_12 and B_21 = -B_12 (orientation
+    and sign of the term)."""
+    import synth
+    from oracle import GridOracle
+    from oracle.xc import vector_term
+    a, b = 0.9, 1.3
+    A = np.array([0.0, 0.0, 0.0])
+    Bc = np.array([0.5, -0.7, 1.1])
+    inst = synth.custom_instance(np.array([A, Bc]), [0, 1], [[0], [0]],
+                                 [_gauss_s(a), _gauss_s(b)], n_log=1000, n_radial=75,
+                                 angular="lobatto302")
+    c = np.array([0.3, -0.8, 0.45])
+    M = vector_term(GridOracle(inst), np.tile(c, (inst.n_points, 1)))
+    g = a + b
+    R2 = float((A - Bc) @ (A - Bc))
+    S12 = (1 / (4 * math.pi)) * (math.pi / g) ** 1.5 * math.exp(-a * b * R2 / g)
+    B12 = -(2 * a * b / g) * float(c @ (A - Bc)) * S12
+    assert abs(M[0, 1] / B12 - 1) < 1e-5
+    assert abs(M[1, 0] / -B12 - 1) < 1e-5
+    assert abs(M[0, 0]) < 1e-5 * abs(B12) and abs(M[1, 1]) < 1e-5 * abs(B12)
+
+
+def test_vector_term_divergence():
+    """u = (x, 0, 0): B + B^T = int u.grad(phi_i phi_j) = -int (div u) phi_i phi_j = -S, to the
+    quadrature's accuracy on the triatomic grid (about 1%)."""
+    import synth
+    from oracle import GridOracle
+    from oracle.xc import vector_term
+    inst = synth.make_instance("c1")
+    o = GridOracle(inst)
+    _, S = o.integrate_h(inst.v)
+    u = np.zeros((inst.n_points, 3))
+    u[:, 0] = inst.pt_xyz[:, 0]
+    B = vector_term(o, u)
+    assert np.abs(B + B.T + S).max() < 0.02 * np.abs(S).max()
+    assert np.abs(B - B.T + S).max() > 0.1 * np.abs(S).max()       # not symmetric by itself
