@@ -170,6 +170,18 @@ aims_status aims_grid_set_moving(aims_grid *g, int32_t sys, const aims_moving_gr
 aims_status aims_total_forces(aims_grid *g, aims_precision prec, const double *P, const double *gE,
                               double *sums_out_or_null, double *dE_dR);
 
+/* H with a gradient term, for gradient-corrected functionals:
+ *     H_ij = sum_p w_p phi_i(p) [ v_p phi_j(p) + tphi_j(p) + u_p . grad phi_j(p) ]
+ * The exchange-correlation part of a GGA Hamiltonian is
+ *     sum_p w_p [ v_n phi_i phi_j + 2 v_sigma grad n . grad(phi_i phi_j) ] = V_n + B + B^T,
+ *     B_ij = sum_p w_p phi_i 2 v_sigma grad n . grad phi_j    (v_sigma = d f_xc / d |grad n|^2)
+ * and this raw form with v = v_nuc + v_n and u = 4 v_sigma grad n holds V_n + 2 B, whose
+ * symmetric part is the same (the density-matrix step uses the symmetric part).  v: DEVICE [n_points]; u: DEVICE
+ * [n_points][3] (caller order); H: DEVICE blocks as aims_integrate_h.  AIMS_FP64 or AIMS_FP32;
+ * setup positions. */
+aims_status aims_integrate_h_gga(aims_grid *g, aims_precision prec, const double *v,
+                                 const double *u, double *H);
+
 /* Density and its gradient at every point, the input of gradient-corrected functionals:
  *     n(p) = sum_ij P_ij phi_i(p) phi_j(p),   grad n(p) = 2 sum_ij P_ij phi_i(p) grad phi_j(p)
  * (P symmetric, the caller's responsibility), FP64, at the setup positions.  P: DEVICE

@@ -58,6 +58,7 @@ SIGNATURES = {
                                           c_void_p, c_void_p, c_void_p]),
     "aims_grid_set_moving": (c_int, [c_void_p, c_int32, POINTER(AimsMovingGrid)]),
     "aims_total_forces": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "aims_integrate_h_gga": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
     "aims_density_gradient": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "aims_xc": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
     "aims_density_matrix": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, POINTER(c_double), c_double,

@@ -899,7 +899,8 @@ void run_density(aims_grid* g, aims_precision prec, const T* P, const double* v,
 }
 
 template <typename T>
-void run_hs(aims_grid* g, aims_precision prec, int mode, const double* v, double* out) {
+void run_hs(aims_grid* g, aims_precision prec, int mode, const double* v, double* out,
+            const double* u = nullptr) {
   hipStream_t st = g->stream;
   BatchSet& bs = hset(g, g->h_merge[prec], g->h_ratio[prec]);
   const ItemList& L = items_for(g, bs, 0);
@@ -923,6 +924,10 @@ void run_hs(aims_grid* g, aims_precision prec, int mode, const double* v, double
         timed(g, kProfPhi, 0.0, "phi_eval", [&] {
           return launch_phi_eval<T>(bs.dv, gr.b0, nbt, mode, v, s1, s2, st);
         });
+        if (u)
+          timed(g, kProfPhi, 0.0, "vector term", [&] {
+            return launch_vector_term<T>(bs.dv, gr.b0, nbt, u, s2, st);
+          });
         timed(g, kProfHS, gr.flops, "hs", [&] {
           return launch_hs<T>(bs.dv, L.d_items + run.i0, nit, s1, s2, out, st, qs.next());
         });
@@ -942,9 +947,10 @@ void density_call(aims_grid* g, aims_precision prec, const double* P, const doub
   }
 }
 
-void hs_call(aims_grid* g, aims_precision prec, int mode, const double* v, double* out) {
-  if (prec == AIMS_FP64) run_hs<double>(g, prec, mode, v, out);
-  else run_hs<float>(g, prec, mode, v, out);
+void hs_call(aims_grid* g, aims_precision prec, int mode, const double* v, double* out,
+             const double* u = nullptr) {
+  if (prec == AIMS_FP64) run_hs<double>(g, prec, mode, v, out, u);
+  else run_hs<float>(g, prec, mode, v, out, u);
 }
 
 template <typename F>
@@ -1015,6 +1021,20 @@ aims_status aims_integrate_h(aims_grid* g, aims_precision prec, const double* at
     set_positions(g, atom_xyz);
     hs_call(g, prec, kModeH, v, H);
     if (S_or_null) hs_call(g, prec, kModeS, v, S_or_null);
+  });
+}
+
+aims_status aims_integrate_h_gga(aims_grid* g, aims_precision prec, const double* v,
+                                 const double* u, double* H) {
+  return guarded(g, [&] {
+    check_prec(prec);
+    if (prec == AIMS_BF16X3) fail(AIMS_ERR_UNSUPPORTED, "the gradient term supports AIMS_FP64 and AIMS_FP32");
+    require_device(v, "v", g->n_points > 0);
+    require_device(u, "u", g->n_points > 0);
+    require_device(H, "H");
+    set_positions(g, nullptr);
+    if (g->moved) fail(AIMS_ERR_ARG, "the gradient term is integrated at the setup positions");
+    hs_call(g, prec, kModeH, v, H, u);
   });
 }
 

@@ -20,4 +20,10 @@ hipError_t launch_lda(const DeviceView& dv, const double* n, double* v_out, doub
 hipError_t launch_gradn(const DeviceView& dv, int b0, int nbatch, const double* X, double* grad_out,
                         hipStream_t st);
 
+// slab2 += w_p u_p . grad phi_j(p) (the gradient term of the H integrand) for the batches
+// [b0, b0 + nbatch) of dv; u: [n_points][3] caller order
+template <typename T>
+hipError_t launch_vector_term(const DeviceView& dv, int b0, int nbatch, const double* u, T* slab2,
+                              hipStream_t st);
+
 }  // namespace aims

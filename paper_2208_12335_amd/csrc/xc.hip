@@ -183,7 +183,47 @@ gradn_kernel(const BatchDesc* __restrict__ batches, int b0, const double4* __res
   }
 }
 
+// The gradient term of the H integrand: slab2[col][p] += w_p u_p . grad phi_col(p) on top of
+// the basis evaluation's w (v phi + t phi), for the batches [b0, b0 + nbatch); u in caller
+// order.  One workgroup per batch, one thread per point; each slab entry has one writer.
+template <typename T>
+__global__ void __launch_bounds__(256)
+vector_term_kernel(const BatchDesc* __restrict__ batches, int b0, const double4* __restrict__ pts,
+                   const int32_t* __restrict__ perm, const int32_t* __restrict__ batch_atoms,
+                   const int32_t* __restrict__ batch_acol, const double* __restrict__ atom_xyz,
+                   const int32_t* __restrict__ atom_species, const SpeciesDesc* __restrict__ species,
+                   const int32_t* __restrict__ shell_l, const double* __restrict__ spline,
+                   RadialGrid rg, const double* __restrict__ u, T* __restrict__ slab2) {
+  const BatchDesc d = batches[b0 + blockIdx.x];
+  T* S2 = slab2 + d.slab_off;
+  for (int p = threadIdx.x; p < d.n_p; p += blockDim.x) {
+    const double4 P4 = pts[d.pt_off + p];
+    const size_t q = (size_t)perm[d.pt_off + p];
+    const double wx = P4.w * u[3 * q], wy = P4.w * u[3 * q + 1], wz = P4.w * u[3 * q + 2];
+    for (int k = 0; k < d.n_atoms; ++k)
+      atom_grads(d, k, P4, batch_atoms, batch_acol, atom_xyz, atom_species, species, shell_l,
+                 spline, rg, [&](int col, double ax, double ay, double az) {
+                   T& e = S2[(size_t)col * d.ldp + p];
+                   e = T((double)e + (wx * ax + wy * ay + wz * az));
+                 });
+  }
+}
+
 }  // namespace
+
+template <typename T>
+hipError_t launch_vector_term(const DeviceView& dv, int b0, int nbatch, const double* u, T* slab2,
+                              hipStream_t st) {
+  if (nbatch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(vector_term_kernel<T>, dim3(nbatch), dim3(256), 0, st, dv.batches, b0, dv.pts,
+                     dv.perm, dv.batch_atoms, dv.batch_acol, dv.atom_xyz, dv.atom_species,
+                     dv.species, dv.shell_l, dv.spline64, dv.rg, u, slab2);
+  return hipGetLastError();
+}
+template hipError_t launch_vector_term<double>(const DeviceView&, int, int, const double*, double*,
+                                               hipStream_t);
+template hipError_t launch_vector_term<float>(const DeviceView&, int, int, const double*, float*,
+                                              hipStream_t);
 
 hipError_t launch_gradn(const DeviceView& dv, int b0, int nbatch, const double* X, double* grad_out,
                         hipStream_t st) {

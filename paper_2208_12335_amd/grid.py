@@ -160,6 +160,14 @@ class AimsGrid:
                                                   _ptr(sums), _ptr(dR)))
         return dR, sums
 
+    def integrate_h_gga(self, v: torch.Tensor, u: torch.Tensor, prec: str = "fp64", H_out=None):
+        """H_ij = sum_p w phi_i (v phi_j + t phi_j + u . grad phi_j), u [n_points, 3]."""
+        H = self._new(self.mat_elems) if H_out is None else H_out
+        with torch.cuda.device(self.device):
+            self._check(self._L.aims_integrate_h_gga(self._h, PRECISION[prec], _ptr(v), _ptr(u),
+                                                     _ptr(H)))
+        return H
+
     def density_gradient(self, P: torch.Tensor, n_out=None, grad_out=None, want_n: bool = True):
         """(n [n_points] or None, grad n [n_points, 3]) in caller order (FP64)."""
         n = (self._new(self.n_points) if n_out is None else n_out) if want_n else None

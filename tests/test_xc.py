@@ -103,3 +103,22 @@ def test_density_gradient_grouped(gpu):
         _, g_ref = density_gradient(GridOracle(m), m.P)
         assert np.max(np.abs(grad[off:off + m.n_points] - g_ref)) <= 1e-12 * np.max(np.abs(g_ref))
         off += m.n_points
+
+
+@pytest.mark.parametrize("prec,bar", [("fp64", 1e-12), ("fp32", 2e-5)])
+def test_gradient_term_of_H(gpu, prec, bar):
+    """H with a vector field u on the grid against the oracle's H + B, B_ij = sum w phi_i
+    u.grad phi_j (FP32 form: the slabs and tiles in single precision)."""
+    from oracle.xc import vector_term
+    inst = synth.make_instance("c2", n_atoms=10, box=7.5, seed=4)
+    rng = np.random.default_rng(31)
+    u = rng.standard_normal((inst.n_points, 3)) * np.exp(-0.1 * np.abs(inst.pt_xyz))
+    g = AimsGrid(inst, device=gpu.index)
+    v = torch.from_numpy(inst.v).to(gpu)
+    H = g.integrate_h_gga(v, torch.from_numpy(u).to(gpu), prec=prec).cpu().numpy()
+    o = GridOracle(inst)
+    H0, _ = o.integrate_h(inst.v, want_S=False)
+    ref = (H0 + vector_term(o, u)).reshape(-1)
+    err = np.max(np.abs(H - ref)) / np.max(np.abs(ref))
+    print(f"[xc] gradient term of H ({prec}): {err:.1e}", flush=True)
+    assert err <= bar
