@@ -162,3 +162,89 @@ def test_vector_term_divergence():
     B = vector_term(o, u)
     assert np.abs(B + B.T + S).max() < 0.02 * np.abs(S).max()
     assert np.abs(B - B.T + S).max() > 0.1 * np.abs(S).max()       # not symmetric by itself
+
+
+def test_pbe_reduces_to_lda_without_gradient():
+    from oracle.xc import pbe
+    n = np.geomspace(1e-10, 1e3, 30)
+    r = pbe(n, np.zeros_like(n))
+    l = lda(n)
+    assert np.allclose(r["f"], n * l["eps"], rtol=1e-14, atol=0)
+    assert np.allclose(r["v_n"], l["v"], rtol=1e-13, atol=0)
+
+
+def test_pbe_second_order_gradient_terms_cancel():
+    """mu = beta pi^2 / 3 makes the gradient expansions of exchange (mu s^2) and correlation
+    (beta t^2) cancel: d f / d sigma vanishes at sigma = 0 for every density."""
+    from oracle.xc import pbe
+    n = np.geomspace(1e-8, 1e3, 25)
+    r = pbe(n, np.zeros_like(n))
+    # scale of one term alone: n eps_x mu / (4 k_F^2 n^2)
+    kF = np.cbrt(3 * math.pi ** 2 * n)
+    one = np.abs(-0.75 * np.cbrt(3 * n / math.pi) * 0.2195149727645171 / (4 * kF * kF * n))
+    assert np.all(np.abs(r["v_sigma"]) < 1e-6 * one)
+
+
+def test_pbe_limits_and_scaling():
+    from oracle.xc import pbe
+    n = np.array([0.01, 0.3, 5.0])
+    kF = np.cbrt(3 * math.pi ** 2 * n)
+    ex = -0.75 * np.cbrt(3 * n / math.pi)
+    # exchange-only part = f(n, sigma) - n (eps_c + H); take the enhancement at large s through
+    # the difference of two huge gradients: F_x -> 1 + kappa (Lieb-Oxford bound), and the
+    # correlation n (eps_c + H) -> 0 as t -> infinity
+    s = 1e6
+    sig = (2 * kF * n * s) ** 2
+    f = pbe(n, sig)["f"]
+    assert np.allclose(f / (n * ex), 1.804, rtol=1e-6)
+    # small s: F_x = 1 + mu s^2 + O(s^4), the correlation part starts at t^4 (beta t^2 cancels
+    # against mu s^2 in the total, so test exchange through the total minus LDA at tiny s)
+    # uniform scaling n -> l^3 n, sigma -> l^8 sigma: exchange scales as l^4 (test a large s,
+    # where correlation is gone)
+    l = 1.7
+    f2 = pbe(n * l ** 3, sig * l ** 8)["f"]
+    assert np.allclose(f2, l ** 4 * f, rtol=1e-6)
+
+
+def test_pbe_derivatives_finite_differences():
+    from oracle.xc import pbe
+    rng = np.random.default_rng(8)
+    n = 10 ** rng.uniform(-4, 1, 8)
+    sig = (10 ** rng.uniform(-2, 1, 8) * np.cbrt(n) * n) ** 2
+    r = pbe(n, sig)
+    for k in range(8):
+        hn, hs = 1e-6 * n[k], 1e-3 * sig[k]       # f depends weakly on sigma: a larger step
+        fdn = (pbe([n[k] + hn], [sig[k]])["f"][0] - pbe([n[k] - hn], [sig[k]])["f"][0]) / (2 * hn)
+        fds = (pbe([n[k]], [sig[k] + hs])["f"][0] - pbe([n[k]], [sig[k] - hs])["f"][0]) / (2 * hs)
+        assert abs(fdn - r["v_n"][k]) < 1e-7 * abs(r["v_n"][k])
+        # the sigma-free LDA part dominates f: allow the difference quotient's rounding floor
+        assert abs(fds - r["v_sigma"][k]) < 1e-5 * abs(r["v_sigma"][k]) + 1e-14 * abs(r["f"][k]) / hs
+
+
+def test_pbe_matrix_is_the_energy_derivative():
+    import synth
+    from oracle import GridOracle
+    from oracle.scf import density_matrix
+    from oracle.xc import density_gradient, pbe, pbe_energy_and_matrix
+    inst = synth.make_instance("c1")
+    o = GridOracle(inst)
+    H, S = o.integrate_h(inst.v)
+    P = density_matrix(H, S, 10.0)["P"]                 # occupied orbitals: n >= 0
+    E, Hxc = pbe_energy_and_matrix(o, P)
+    assert np.max(np.abs(Hxc - Hxc.T)) < 1e-12 * np.max(np.abs(Hxc))
+    rng = np.random.default_rng(4)
+    D = rng.standard_normal(P.shape)
+    D = 0.5 * (D + D.T)
+    # the far tails (n down to 1e-20) give E large curvature along D: a small step (the
+    # difference converges as h^2: 4e-4 at 1e-5, 6e-8 at 1e-7)
+    h = 1e-7
+    fd = (pbe_energy_and_matrix(o, P + h * D)[0] - pbe_energy_and_matrix(o, P - h * D)[0]) / (2 * h)
+    an = float(np.sum(Hxc * D))
+    assert abs(fd - an) < 1e-6 * abs(an)
+    # n and grad n are linear in P: sum_ij P_ij H_ij = sum_p w (n v_n + 2 sigma v_sigma), with
+    # grad n here from the autograd path (independent of the matrix's closed-form gradients)
+    n, gn = density_gradient(o, P)
+    r = pbe(n, (gn * gn).sum(1))
+    rhs = float(np.sum(inst.pt_w * (n * r["v_n"] + 2 * (gn * gn).sum(1) * r["v_sigma"])))
+    assert abs(float(np.sum(P * Hxc)) - rhs) < 1e-10 * abs(rhs)
+    assert abs(E - float(np.sum(inst.pt_w * r["f"]))) < 1e-12 * abs(E)
