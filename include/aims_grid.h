@@ -199,9 +199,19 @@ aims_status aims_density_gradient(aims_grid *g, const double *P, double *n_out_o
  * n: DEVICE [n_points] (caller order, e.g. aims_update_density's output); v_xc_out: DEVICE
  * [n_points]; sums_out_or_null: DEVICE [n_sys][2] = (E_xc = sum_p w_p n_p eps_xc, sum_p w_p n_p
  * v_xc).  Asynchronous on the handle's stream. */
-typedef enum { AIMS_XC_LDA_PW92 = 0 } aims_xc_functional;
+typedef enum { AIMS_XC_LDA_PW92 = 0, AIMS_XC_PBE = 1 } aims_xc_functional;
 aims_status aims_xc(aims_grid *g, int32_t functional, const double *n, double *v_xc_out,
                     double *sums_out_or_null);
+/* Gradient-corrected exchange-correlation (AIMS_XC_PBE, spin-unpolarised, PW92 correlation):
+ * with sigma = |grad n|^2, s^2 = sigma / (4 k_F^2 n^2), t^2 = sigma / (4 k_s^2 n^2),
+ *     f(n, sigma) = n eps_x(n) F_x(s) + n (eps_c(n) + H(rs, t))
+ * (kappa = 0.804, beta = 0.06672455060314922, mu = beta pi^2 / 3).  Outputs per point (caller
+ * order): v_out = df/dn, u_out [n_points][3] = 4 (df/dsigma) grad n, the vector field that
+ * aims_integrate_h_gga takes; sums_out_or_null: DEVICE [n_sys][2] = (E_xc = sum w f,
+ * sum w (n v_n + 2 sigma v_sigma) = tr(P H_xc)).  n, grad_n: DEVICE (aims_density_gradient's
+ * output); n <= 1e-14 gives zeros. */
+aims_status aims_xc_gga(aims_grid *g, int32_t functional, const double *n, const double *grad_n,
+                        double *v_out, double *u_out, double *sums_out_or_null);
 
 /* Density matrix of the occupied subspace: the step after the H integration in an s.c.f.
  * iteration, the eigensolver stage that the paper names as the bottleneck of large systems

@@ -14,7 +14,7 @@ STATUS_NAMES = {0: "AIMS_OK", -1: "AIMS_ERR_ARG", -2: "AIMS_ERR_OOM", -3: "AIMS_
                 -4: "AIMS_ERR_STALE", -5: "AIMS_ERR_UNSUPPORTED"}
 PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 DM_METHOD = {"eigen": 0, "purify": 1}
-XC_FUNCTIONAL = {"lda": 0}
+XC_FUNCTIONAL = {"lda": 0, "pbe": 1}
 
 
 class AimsSystem(ctypes.Structure):
@@ -61,6 +61,7 @@ SIGNATURES = {
     "aims_integrate_h_gga": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
     "aims_density_gradient": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "aims_xc": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    "aims_xc_gga": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "aims_density_matrix": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, POINTER(c_double), c_double,
                                     c_void_p, c_void_p, POINTER(c_double)]),
     "aims_last_purify_products": (c_int32, [c_void_p]),

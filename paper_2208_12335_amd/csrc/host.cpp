@@ -1437,6 +1437,21 @@ aims_status aims_density_matrix(aims_grid* g, int32_t method, const double* H, c
   });
 }
 
+aims_status aims_xc_gga(aims_grid* g, int32_t functional, const double* n, const double* grad_n,
+                        double* v_out, double* u_out, double* sums_out_or_null) {
+  return guarded(g, [&] {
+    if (functional != AIMS_XC_PBE) fail(AIMS_ERR_UNSUPPORTED, "aims_xc_gga takes AIMS_XC_PBE");
+    require_device(n, "n", g->n_points > 0);
+    require_device(grad_n, "grad_n", g->n_points > 0);
+    require_device(v_out, "v_out", g->n_points > 0);
+    require_device(u_out, "u_out", g->n_points > 0);
+    if (sums_out_or_null) require_device(sums_out_or_null, "sums_out");
+    if (!g->d_xc_part) g->d_xc_part = (double*)g->alloc(2 * (size_t)kXcBlocks * g->n_sys * sizeof(double));
+    hipchk(launch_pbe(g->dens.dv, n, grad_n, v_out, u_out, g->d_xc_part, sums_out_or_null, g->stream),
+           "xc");
+  });
+}
+
 aims_status aims_density_gradient(aims_grid* g, const double* P, double* n_out_or_null,
                                   double* grad_out) {
   return guarded(g, [&] {
@@ -1489,6 +1504,7 @@ aims_status aims_density_gradient(aims_grid* g, const double* P, double* n_out_o
 aims_status aims_xc(aims_grid* g, int32_t functional, const double* n, double* v_xc_out,
                     double* sums_out_or_null) {
   return guarded(g, [&] {
+    if (functional == AIMS_XC_PBE) fail(AIMS_ERR_UNSUPPORTED, "PBE needs the density gradient (aims_xc_gga)");
     if (functional != AIMS_XC_LDA_PW92) fail(AIMS_ERR_UNSUPPORTED, "unknown functional %d", functional);
     require_device(n, "n");
     require_device(v_xc_out, "v_xc_out");

@@ -1,5 +1,6 @@
 // gfx950 kernels of the exchange-correlation step on the grid (spin-unpolarised LDA: Slater
-// exchange + Perdew-Wang 1992 correlation).  One thread per point, batch order, with the
+// exchange + Perdew-Wang 1992 correlation; PBE), the density gradient and the gradient term of
+// the H integrand.  One thread per point, batch order, with the
 // caller-order density and potential reached through the point permutation; per-system sums
 // by fixed-order block partials.
 #include <hip/hip_runtime.h>
@@ -41,6 +42,57 @@ __device__ __forceinline__ void lda_point(double n, double& eps, double& v) {
   v = (4.0 / 3.0) * ex + ec - (rs / 3.0) * dec;
 }
 
+// ---- PBE (spin-unpolarised) by forward-mode differentiation -------------------------------
+// A value with its partial derivatives with respect to n and sigma = |grad n|^2: evaluating the
+// energy density once in this type gives f, df/dn and df/dsigma of the very same expression.
+struct Dual2 {
+  double v, dn, ds;
+};
+__device__ __forceinline__ Dual2 operator+(Dual2 a, Dual2 b) { return {a.v + b.v, a.dn + b.dn, a.ds + b.ds}; }
+__device__ __forceinline__ Dual2 operator-(Dual2 a, Dual2 b) { return {a.v - b.v, a.dn - b.dn, a.ds - b.ds}; }
+__device__ __forceinline__ Dual2 operator*(Dual2 a, Dual2 b) {
+  return {a.v * b.v, a.dn * b.v + a.v * b.dn, a.ds * b.v + a.v * b.ds};
+}
+__device__ __forceinline__ Dual2 operator/(Dual2 a, Dual2 b) {
+  const double q = a.v / b.v, ib = 1.0 / b.v;
+  return {q, (a.dn - q * b.dn) * ib, (a.ds - q * b.ds) * ib};
+}
+__device__ __forceinline__ Dual2 operator+(double c, Dual2 a) { return {c + a.v, a.dn, a.ds}; }
+__device__ __forceinline__ Dual2 operator-(double c, Dual2 a) { return {c - a.v, -a.dn, -a.ds}; }
+__device__ __forceinline__ Dual2 operator*(double c, Dual2 a) { return {c * a.v, c * a.dn, c * a.ds}; }
+__device__ __forceinline__ Dual2 operator/(double c, Dual2 a) {
+  const double q = c / a.v;
+  return {q, -q / a.v * a.dn, -q / a.v * a.ds};
+}
+__device__ __forceinline__ Dual2 chain(double f, double df, Dual2 a) { return {f, df * a.dn, df * a.ds}; }
+__device__ __forceinline__ Dual2 d_sqrt(Dual2 a) { const double r = sqrt(a.v); return chain(r, 0.5 / r, a); }
+__device__ __forceinline__ Dual2 d_cbrt(Dual2 a) { const double r = cbrt(a.v); return chain(r, r / (3.0 * a.v), a); }
+__device__ __forceinline__ Dual2 d_log1p(Dual2 a) { return chain(log1p(a.v), 1.0 / (1.0 + a.v), a); }
+__device__ __forceinline__ Dual2 d_expm1(Dual2 a) { const double e = expm1(a.v); return chain(e, e + 1.0, a); }
+
+constexpr double kKappa = 0.804, kBeta = 0.06672455060314922;
+
+// f(n, sigma) = n eps_x F_x(s) + n (eps_c + H(rs, t)) of PBE with PW92 correlation
+__device__ __forceinline__ Dual2 pbe_f(Dual2 n, Dual2 sigma) {
+  const double mu = kBeta * kPi * kPi / 3.0;
+  const double gamma = (1.0 - 0.69314718055994530942) / (kPi * kPi);
+  const Dual2 n13 = d_cbrt(n);
+  const Dual2 ex = (-0.75 * cbrt(3.0 / kPi)) * n13;
+  const Dual2 rs = cbrt(3.0 / (4.0 * kPi)) / n13;
+  const Dual2 srs = d_sqrt(rs);
+  const Dual2 Q = (2.0 * kA) * (kB1 * srs + kB2 * rs + kB3 * (rs * srs) + kB4 * (rs * rs));
+  const Dual2 ec = (-2.0 * kA) * ((1.0 + kA1 * rs) * d_log1p(1.0 / Q));
+  const Dual2 kF = cbrt(3.0 * kPi * kPi) * n13;
+  const Dual2 n2 = n * n;
+  const Dual2 s2 = sigma / (4.0 * (kF * kF * n2));
+  const Dual2 Fx = (1.0 + kKappa) - kKappa / (1.0 + (mu / kKappa) * s2);
+  const Dual2 t2 = sigma / (4.0 * ((4.0 / kPi) * kF * n2));
+  const Dual2 A = (kBeta / gamma) / d_expm1((-1.0 / gamma) * ec);
+  const Dual2 At2 = A * t2;
+  const Dual2 H = gamma * d_log1p((kBeta / gamma) * (t2 * (1.0 + At2) / (1.0 + At2 + At2 * At2)));
+  return n * ex * Fx + n * (ec + H);
+}
+
 template <int NT>
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -72,6 +124,48 @@ __global__ void __launch_bounds__(256) lda_kernel(const double4* __restrict__ pt
     v_out[q] = v;
     se += w * n * eps;
     sv += w * n * v;
+  }
+  se = block_sum<256>(se, sh);
+  sv = block_sum<256>(sv, sh);
+  if (threadIdx.x == 0) {
+    part[2 * ((size_t)s * nblk + blockIdx.x)] = se;
+    part[2 * ((size_t)s * nblk + blockIdx.x) + 1] = sv;
+  }
+}
+
+// PBE per point (batch order, caller-order arrays through perm): v_out = df/dn, u_out =
+// 4 df/dsigma grad n (the vector field of the raw GGA H), block partials of
+// (E_xc = sum w f, sum w (n v_n + 2 sigma v_sigma))
+__global__ void __launch_bounds__(256) pbe_kernel(const double4* __restrict__ pts,
+                                                  const int32_t* __restrict__ perm,
+                                                  const int64_t* __restrict__ sys_pt_range,
+                                                  const double* __restrict__ n_in,
+                                                  const double* __restrict__ grad_in,
+                                                  double* __restrict__ v_out,
+                                                  double* __restrict__ u_out,
+                                                  double* __restrict__ part) {
+  __shared__ double sh[4];
+  const int s = blockIdx.y, nblk = gridDim.x;
+  const int64_t p0 = sys_pt_range[2 * s], p1 = sys_pt_range[2 * s + 1];
+  double se = 0.0, sv = 0.0;
+  for (int64_t i = p0 + blockIdx.x * 256 + threadIdx.x; i < p1; i += (int64_t)nblk * 256) {
+    const size_t q = (size_t)perm[i];
+    const double n = n_in[q], w = pts[i].w;
+    const double gx = grad_in[3 * q], gy = grad_in[3 * q + 1], gz = grad_in[3 * q + 2];
+    double vn = 0.0, vs = 0.0, f = 0.0;
+    const double sigma = gx * gx + gy * gy + gz * gz;
+    if (n > kNMin) {
+      const Dual2 r = pbe_f(Dual2{n, 1.0, 0.0}, Dual2{sigma, 0.0, 1.0});
+      f = r.v;
+      vn = r.dn;
+      vs = r.ds;
+    }
+    v_out[q] = vn;
+    u_out[3 * q] = 4.0 * vs * gx;
+    u_out[3 * q + 1] = 4.0 * vs * gy;
+    u_out[3 * q + 2] = 4.0 * vs * gz;
+    se += w * f;
+    sv += w * (n * vn + 2.0 * sigma * vs);
   }
   se = block_sum<256>(se, sh);
   sv = block_sum<256>(sv, sh);
@@ -231,6 +325,17 @@ hipError_t launch_gradn(const DeviceView& dv, int b0, int nbatch, const double* 
   hipLaunchKernelGGL(gradn_kernel, dim3(nbatch), dim3(256), 0, st, dv.batches, b0, dv.pts, dv.perm,
                      dv.batch_atoms, dv.batch_acol, dv.atom_xyz, dv.atom_species, dv.species,
                      dv.shell_l, dv.spline64, dv.rg, X, grad_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pbe(const DeviceView& dv, const double* n, const double* grad, double* v_out,
+                      double* u_out, double* part, double* sums_or_null, hipStream_t st) {
+  hipLaunchKernelGGL(pbe_kernel, dim3(kXcBlocks, dv.n_sys), dim3(256), 0, st, dv.pts, dv.perm,
+                     dv.sys_pt_range, n, grad, v_out, u_out, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !sums_or_null) return e;
+  hipLaunchKernelGGL(xc_sums_kernel, dim3(dv.n_sys), dim3(256), 0, st, part, kXcBlocks,
+                     sums_or_null);
   return hipGetLastError();
 }
 

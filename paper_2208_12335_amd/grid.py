@@ -168,6 +168,18 @@ class AimsGrid:
                                                      _ptr(H)))
         return H
 
+    def xc_gga(self, n: torch.Tensor, grad_n: torch.Tensor, functional: str = "pbe"):
+        """(v [n_points], u [n_points, 3], sums [n_sys, 2]) of a gradient-corrected functional:
+        v = df/dn, u = 4 (df/dsigma) grad n (for ``integrate_h_gga``), sums = (E_xc,
+        tr(P H_xc))."""
+        v = self._new(self.n_points)
+        u = self._new(self.n_points, 3)
+        sums = self._new(self.n_sys, 2)
+        with torch.cuda.device(self.device):
+            self._check(self._L.aims_xc_gga(self._h, XC_FUNCTIONAL[functional], _ptr(n),
+                                            _ptr(grad_n), _ptr(v), _ptr(u), _ptr(sums)))
+        return v, u, sums
+
     def density_gradient(self, P: torch.Tensor, n_out=None, grad_out=None, want_n: bool = True):
         """(n [n_points] or None, grad n [n_points, 3]) in caller order (FP64)."""
         n = (self._new(self.n_points) if n_out is None else n_out) if want_n else None

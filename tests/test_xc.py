@@ -122,3 +122,55 @@ def test_gradient_term_of_H(gpu, prec, bar):
     err = np.max(np.abs(H - ref)) / np.max(np.abs(ref))
     print(f"[xc] gradient term of H ({prec}): {err:.1e}", flush=True)
     assert err <= bar
+
+
+def test_pbe_pointwise(gpu):
+    from oracle.xc import pbe
+    inst = synth.make_instance("c1")
+    g = AimsGrid(inst, device=gpu.index)
+    rng = np.random.default_rng(12)
+    n = 10.0 ** rng.uniform(-12, 2, inst.n_points)
+    s = rng.uniform(0, 10, inst.n_points) ** 2          # reduced gradient up to 10
+    kF = np.cbrt(3 * np.pi ** 2 * n)
+    gmag = 2 * kF * n * np.sqrt(s)
+    d = rng.standard_normal((inst.n_points, 3))
+    grad = d / np.linalg.norm(d, axis=1)[:, None] * gmag[:, None]
+    grad[:5] = 0.0
+    n[5] = 0.0
+    v, u, sums = g.xc_gga(torch.from_numpy(n).to(gpu), torch.from_numpy(grad).to(gpu))
+    ref = pbe(n, (grad * grad).sum(1))
+    v, u, sums = v.cpu().numpy(), u.cpu().numpy(), sums.cpu().numpy()[0]
+    ev = np.max(np.abs(v - ref["v_n"]) / np.maximum(np.abs(ref["v_n"]), 1e-300))
+    u_ref = 4 * ref["v_sigma"][:, None] * grad
+    eu = np.max(np.abs(u - u_ref)) / np.max(np.abs(u_ref))
+    w = inst.pt_w
+    E = float(np.sum(w * ref["f"]))
+    tr = float(np.sum(w * (n * ref["v_n"] + 2 * (grad * grad).sum(1) * ref["v_sigma"])))
+    print(f"[xc] pbe pointwise: v_n {ev:.1e}, u {eu:.1e}, E_xc {sums[0]:.12f} vs {E:.12f}", flush=True)
+    assert ev <= 1e-12 and eu <= 1e-12
+    assert abs(sums[0] - E) <= 1e-12 * abs(E) and abs(sums[1] - tr) <= 1e-12 * abs(tr)
+
+
+def test_gga_hamiltonian_end_to_end(gpu):
+    """Core H -> P (occupied) -> n, grad n -> PBE -> H with the gradient term, on each side:
+    the symmetric part of the library's raw H against the oracle's H_core + dE_xc/dP."""
+    from oracle.xc import pbe_energy_and_matrix
+    inst = synth.make_instance("c2", n_atoms=10, box=7.5, seed=4)
+    N = float(np.sum(inst.atom_Z))
+    g = AimsGrid(inst, device=gpu.index)
+    v_nuc = torch.from_numpy(inst.v).to(gpu)
+    H0, S = g.integrate_h(v_nuc, want_S=True)
+    P, _, _ = g.density_matrix(H0, S, N)
+    n, grad = g.density_gradient(P)
+    vn, u, sums = g.xc_gga(n, grad)
+    H = g.integrate_h_gga(v_nuc + vn, u).cpu().numpy().reshape(inst.n_basis, inst.n_basis)
+    o = GridOracle(inst)
+    Hr, Sr = o.integrate_h(inst.v)
+    Pr = dm_ref(Hr, Sr, N)["P"]
+    E_ref, Hxc = pbe_energy_and_matrix(o, Pr)
+    ref = 0.5 * (Hr + Hr.T) + Hxc
+    err = np.max(np.abs(0.5 * (H + H.T) - ref)) / np.max(np.abs(ref))
+    s = sums.cpu().numpy()[0]
+    print(f"[xc] GGA H: {err:.1e}; E_xc {s[0]:.10f} vs {E_ref:.10f}", flush=True)
+    assert err <= 1e-9
+    assert abs(s[0] - E_ref) <= 1e-9 * abs(E_ref)
