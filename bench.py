@@ -251,6 +251,28 @@ def bench_single(args, torch, inst, backward=False):
             dm[meth] = r
             _log(f"density matrix ({meth}): {ms_dm:.2f} ms")
         outside["density_matrix_fp64"] = dm
+        # the potential step of a semilocal s.c.f. iteration on the occupied density: n and
+        # grad n, LDA and PBE, H with the gradient term; with the density matrix, a whole GGA
+        # iteration (density + gradient, PBE, H, density matrix)
+        if "ms" in dm.get("eigen", {}):
+            g.density_matrix(H, S, n_e, method="eigen", P_out=P_new, want_eps=False)
+            nn = torch.empty(g.n_points, dtype=torch.float64, device=dev)
+            gr = torch.empty(g.n_points, 3, dtype=torch.float64, device=dev)
+            H2 = torch.empty(g.mat_elems, dtype=torch.float64, device=dev)
+            xc = {}
+            xc["ms_density_and_gradient"], _ = timer.run(
+                lambda: g.density_gradient(P_new, n_out=nn, grad_out=gr), 3, 1)
+            xc["ms_lda"], _ = timer.run(lambda: g.xc(nn), 3, 1)
+            vn, u, _ = g.xc_gga(nn, gr)
+            xc["ms_pbe"], _ = timer.run(lambda: g.xc_gga(nn, gr), 3, 1)
+            vt = v + vn
+            xc["ms_h_with_gradient_term"], _ = timer.run(
+                lambda: g.integrate_h_gga(vt, u, H_out=H2), 3, 1)
+            best_dm = min((r["ms"] for r in dm.values() if isinstance(r, dict) and "ms" in r))
+            xc["gga_iteration_ms"] = (xc["ms_density_and_gradient"] + xc["ms_pbe"] +
+                                      xc["ms_h_with_gradient_term"] + best_dm)
+            outside["xc_fp64"] = xc
+            _log(f"xc: {json.dumps({k: round(x, 3) for k, x in xc.items()})}")
     if backward and inst.pt_wgrid is not None:
         # total (moving-grid) forces: Pulay + partition-weight + nuclear-potential + point motion
         g.set_moving_grid()
