@@ -12,6 +12,7 @@ from .instances import (  # noqa: F401
     make_instance,
     make_molecule_set,
     regrid,
+    radial_shells,
     generator_device,
     custom_instance,
     becke_radial,

@@ -539,7 +539,8 @@ def _assemble(name, rng, atom_xyz, atom_Z, zset, rule, max_batch, pair_cutoff=No
                     pt_wgrid=np.ascontiguousarray(wgrid))
     nfn = inst.species_nfn()[atom_species]
     inst.P = random_density_matrix(rng, atom_xyz, nfn, pair_cutoff)
-    inst.meta.update({"rule": rule, "grid": g, "pair_cutoff": pair_cutoff})
+    inst.meta.update({"rule": rule, "grid": g, "pair_cutoff": pair_cutoff, "n_radial": g["n_radial"],
+                      "r_map": BECKE_RM})
     return inst
 
 
@@ -648,9 +649,28 @@ def custom_instance(atom_xyz: np.ndarray, atom_species: np.ndarray,
                     r0=r0, rc=rc, shell_R=R, shell_K=K, pt_xyz=np.ascontiguousarray(pts),
                     pt_w=np.ascontiguousarray(w), pt_atom=owner.astype(np.int32),
                     v=np.zeros(pts.shape[0]), P=np.zeros((0, 0)), max_batch=max_batch,
-                    meta={"custom": True}, pt_wgrid=np.ascontiguousarray(w0))
+                    meta={"custom": True, "n_radial": int(n_radial), "r_map": float(rm)},
+                    pt_wgrid=np.ascontiguousarray(w0))
     if potential is not None:
         inst.v = np.ascontiguousarray(potential(pts), dtype=np.float64)
     nb = inst.n_basis
     inst.P = np.zeros((nb, nb)) if P is None else np.ascontiguousarray(P, dtype=np.float64)
     return inst
+
+
+def radial_shells(inst: Instance):
+    """(pt_shell [n_pts] int32, n_radial, r_map): the index of each point's radial node on its
+    owner's Becke radial grid (nodes as ``becke_radial`` orders them), found from the point's
+    distance to its owner."""
+    n_radial = int(inst.meta["n_radial"])
+    rm = float(inst.meta.get("r_map", BECKE_RM))
+    r_nodes, _ = becke_radial(n_radial, rm)
+    d = np.linalg.norm(inst.pt_xyz - inst.atom_xyz[inst.pt_atom], axis=1)
+    order = np.argsort(r_nodes)
+    rs = r_nodes[order]
+    j = np.clip(np.searchsorted(rs, d), 1, n_radial - 1)
+    j = np.where(np.abs(rs[j - 1] - d) < np.abs(rs[j] - d), j - 1, j)
+    k = order[j]
+    if np.any(np.abs(r_nodes[k] - d) > 1e-9 * np.maximum(1.0, r_nodes[k])):
+        raise ValueError("points off the radial nodes")
+    return k.astype(np.int32), n_radial, rm
