@@ -213,6 +213,31 @@ aims_status aims_xc(aims_grid *g, int32_t functional, const double *n, double *v
 aims_status aims_xc_gga(aims_grid *g, int32_t functional, const double *n, const double *grad_n,
                         double *v_out, double *u_out, double *sums_out_or_null);
 
+/* Hartree potential of the grid density by an atom-centred multipole expansion of the
+ * partitioned density (the electrostatic step of an s.c.f. iteration, which the paper notes is
+ * not yet accelerated on GPUs; Development Priorities).  The grid must be atom-centred product
+ * grids on Becke's radial map r = r_map cot^2(theta/2), theta_k = (k+1) pi/(n_radial+1),
+ * k = 0..n_radial-1, whose point weights are (radial weight with r^2) x (angular weight) x
+ * (partition of the owner atom):
+ *   rho_{a,lm}(r_k) = sum over the points of node k of atom a of w n Y_lm(u) / W_k,
+ *   V_lm(r) = 4 pi/(2l+1) [ r^-(l+1) int_0^r rho_lm s^(l+2) ds + r^l int_r^inf rho_lm s^(1-l) ds ]
+ *   (natural cubic splines of rho_lm and V_lm in theta, 6-point Gauss-Legendre per interval,
+ *   exact exterior field beyond the outermost node, (r/r_min)^l inside the innermost),
+ *   v_H(p) = sum_a sum_lm V_{a,lm}(|p - R_a|) Y_lm(u),  E_H = 1/2 sum w n v_H.
+ * aims_grid_set_hartree: per point (caller order of the system) the owner atom and the radial
+ * node, plus n_radial, r_map and l_max (0..6, the same for every system of the handle).
+ * aims_hartree: n: DEVICE [n_points] (caller order); v_out: DEVICE [n_points];
+ * E_out_or_null: DEVICE [n_sys].  Setup positions. */
+typedef struct {
+  const int32_t *pt_owner;
+  const int32_t *pt_node;
+  int32_t n_radial;
+  double r_map;
+  int32_t l_max;
+} aims_hartree_grid;
+aims_status aims_grid_set_hartree(aims_grid *g, int32_t sys, const aims_hartree_grid *h);
+aims_status aims_hartree(aims_grid *g, const double *n, double *v_out, double *E_out_or_null);
+
 /* Density matrix of the occupied subspace: the step after the H integration in an s.c.f.
  * iteration, the eigensolver stage that the paper names as the bottleneck of large systems
  * (Development Priorities).  Per system s (basis size nb_s):

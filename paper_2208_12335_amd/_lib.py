@@ -43,6 +43,11 @@ class AimsTuning(ctypes.Structure):
                 ("h_flops_per_atomic", c_int32)]
 
 
+class AimsHartreeGrid(ctypes.Structure):
+    _fields_ = [("pt_owner", POINTER(c_int32)), ("pt_node", POINTER(c_int32)),
+                ("n_radial", c_int32), ("r_map", c_double), ("l_max", c_int32)]
+
+
 class AimsMovingGrid(ctypes.Structure):
     _fields_ = [("pt_owner", POINTER(c_int32)), ("pt_wgrid", POINTER(c_double)),
                 ("atom_Z", POINTER(c_double)), ("nuc_sigma", c_double), ("partition_a", c_double)]
@@ -60,6 +65,8 @@ SIGNATURES = {
     "aims_total_forces": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
     "aims_integrate_h_gga": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
     "aims_density_gradient": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "aims_grid_set_hartree": (c_int, [c_void_p, c_int32, POINTER(AimsHartreeGrid)]),
+    "aims_hartree": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "aims_xc": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
     "aims_xc_gga": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "aims_density_matrix": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, POINTER(c_double), c_double,

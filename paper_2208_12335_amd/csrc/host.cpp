@@ -22,6 +22,7 @@
 #include "kernels.h"
 #include "scf.h"
 #include "xc.h"
+#include "hartree.h"
 
 using namespace aims;
 
@@ -253,6 +254,14 @@ struct aims_grid {
   double* d_gpt = nullptr;                   // point-motion sums, batch order [n][3]
   // wave-per-point force kernel: 1 / (a R_bc) tables, batch ranges and per-range slots
   double* d_xc_part = nullptr;               // per-block partial sums of the xc kernels
+  // Hartree multipole expansion: per system radial grid, per point owner / radial node
+  int hartree_lmax = -1;
+  std::vector<int> h_K;                      // [n_sys] radial nodes (0 = not set)
+  std::vector<double> h_rmap;                // [n_sys]
+  std::vector<int32_t> h_owner;              // [n_points] global atom, batch order
+  std::vector<int32_t> h_node;               // [n_points] radial node, batch order
+  bool h_ready = false;
+  HartreeDev hd;
   int dm_iterations = 0;                     // purification products of the last system
   bool force_thread_path = false;           // AIMS_FORCES_THREAD_PATH=1: thread-per-point kernel
   bool gf_ready = false;
@@ -1434,6 +1443,163 @@ aims_status aims_density_matrix(aims_grid* g, int32_t method, const double* H, c
       eoff += nb;
     }
     g->dm_iterations = g->dm.last_iterations;
+  });
+}
+
+aims_status aims_grid_set_hartree(aims_grid* g, int32_t sys, const aims_hartree_grid* h) {
+  return guarded(g, [&] {
+    if (!h) fail(AIMS_ERR_ARG, "null Hartree grid description");
+    if (sys < 0 || sys >= g->n_sys) fail(AIMS_ERR_ARG, "system %d out of range", sys);
+    if (h->n_radial < 3 || h->n_radial > 4096) fail(AIMS_ERR_ARG, "n_radial must be in 3..4096");
+    if (!(h->r_map > 0.0) || !std::isfinite(h->r_map)) fail(AIMS_ERR_ARG, "r_map must be > 0");
+    if (h->l_max < 0 || h->l_max > kHartreeMaxL)
+      fail(AIMS_ERR_UNSUPPORTED, "l_max must be in 0..%d", kHartreeMaxL);
+    if (g->hartree_lmax >= 0 && h->l_max != g->hartree_lmax)
+      fail(AIMS_ERR_ARG, "every system of a handle takes the same l_max (%d)", g->hartree_lmax);
+    const int64_t p0 = g->sys_pt_range[2 * sys], p1 = g->sys_pt_range[2 * sys + 1];
+    const int a0 = (int)g->sys_atom_range[2 * sys], a1 = (int)g->sys_atom_range[2 * sys + 1];
+    if (p1 > p0 && (!h->pt_owner || !h->pt_node)) fail(AIMS_ERR_ARG, "null point arrays");
+    for (int64_t i = 0; i < p1 - p0; ++i) {
+      if (h->pt_owner[i] < 0 || h->pt_owner[i] >= a1 - a0)
+        fail(AIMS_ERR_ARG, "pt_owner[%lld] = %d out of range", (long long)i, h->pt_owner[i]);
+      if (h->pt_node[i] < 0 || h->pt_node[i] >= h->n_radial)
+        fail(AIMS_ERR_ARG, "pt_node[%lld] = %d out of range", (long long)i, h->pt_node[i]);
+    }
+    if (g->h_K.empty()) {
+      g->h_K.assign(g->n_sys, 0);
+      g->h_rmap.assign(g->n_sys, 0.0);
+      g->h_owner.assign(g->n_points, 0);
+      g->h_node.assign(g->n_points, 0);
+    }
+    for (int64_t i = p0; i < p1; ++i) {
+      const int64_t q = g->perm_host[i] - p0;     // caller index within the system
+      g->h_owner[i] = a0 + h->pt_owner[q];
+      g->h_node[i] = h->pt_node[q];
+    }
+    g->h_K[sys] = h->n_radial;
+    g->h_rmap[sys] = h->r_map;
+    g->hartree_lmax = h->l_max;
+    g->h_ready = false;
+  });
+}
+
+namespace {
+// Gauss-Legendre nodes and weights on [-1, 1]: Newton's iteration on P_n from the three-term
+// recurrence, w = 2 / ((1 - x^2) P_n'(x)^2)
+std::vector<double> gauss_legendre(int n) {
+  std::vector<double> out(2 * (size_t)n);
+  for (int i = 0; i < n; ++i) {
+    double x = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (x * p1 - p0) / (x * x - 1.0);
+      const double dx = p1 / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    out[n - 1 - i] = x;                                  // ascending
+    out[n + (n - 1 - i)] = 2.0 / ((1.0 - x * x) * dp * dp);
+  }
+  return out;
+}
+
+void build_hartree(aims_grid* g) {
+  const int L = g->hartree_lmax, nlm = (L + 1) * (L + 1);
+  int K_max = 0;
+  for (int k : g->h_K) K_max = std::max(K_max, k);
+  // shells: every (atom, node), points grouped by (atom, node) in batch-order indices
+  std::vector<HartreeShell> shells;
+  std::vector<int32_t> count((size_t)g->n_atoms * K_max, 0);
+  for (int64_t i = 0; i < g->n_points; ++i) ++count[(size_t)g->h_owner[i] * K_max + g->h_node[i]];
+  std::vector<int32_t> start(count.size() + 1, 0);
+  for (size_t c = 0; c < count.size(); ++c) start[c + 1] = start[c] + count[c];
+  std::vector<int32_t> pts_sorted(std::max<int64_t>(1, g->n_points));
+  std::vector<int32_t> fill(start.begin(), start.end() - 1);
+  for (int64_t i = 0; i < g->n_points; ++i)
+    pts_sorted[fill[(size_t)g->h_owner[i] * K_max + g->h_node[i]]++] = (int32_t)i;
+  std::vector<HartreeSys> hs(g->n_sys);
+  std::vector<double> cp, den;
+  std::vector<int32_t> natoms(g->n_sys);
+  for (int s = 0; s < g->n_sys; ++s) {
+    const int K = g->h_K[s];
+    const double rm = g->h_rmap[s];
+    hs[s] = HartreeSys{K, K_max, (int32_t)cp.size(), 0, rm};
+    // Thomas factors of M_{i-1} + 4 M_i + M_{i+1} = rhs_i (i = 1..K-2), natural ends
+    std::vector<double> c(K, 0.0), d(K, 1.0);
+    for (int i = 1; i <= K - 2; ++i) {
+      d[i] = i == 1 ? 4.0 : 4.0 - c[i - 1];
+      c[i] = 1.0 / d[i];
+    }
+    cp.insert(cp.end(), c.begin(), c.end());
+    den.insert(den.end(), d.begin(), d.end());
+    const int a0 = (int)g->sys_atom_range[2 * s], a1 = (int)g->sys_atom_range[2 * s + 1];
+    natoms[s] = a1 - a0;
+    for (int a = a0; a < a1; ++a)
+      for (int k = 0; k < K; ++k) {
+        // Becke radial weight with r^2: W = pi/(K+1) sin t 2 r_m/(1 - cos t)^2 r^2
+        const double t = (double)(k + 1) * M_PI / (double)(K + 1), x = std::cos(t);
+        const double r = rm * (1.0 + x) / (1.0 - x);
+        const double W = M_PI / (double)(K + 1) * std::sin(t) * 2.0 * rm / ((1.0 - x) * (1.0 - x)) * r * r;
+        const size_t cidx = (size_t)a * K_max + k;
+        shells.push_back(HartreeShell{a, start[cidx], start[cidx + 1], (int32_t)cidx, 1.0 / W});
+      }
+  }
+  HartreeDev& hd = g->hd;
+  auto drop = [&](auto* p) {
+    if (p) g->release((void*)p);
+  };
+  drop(hd.shells);
+  drop(hd.shell_pts);
+  drop(hd.sys);
+  drop(hd.sys_natoms);
+  drop(hd.cp);
+  drop(hd.den);
+  drop(hd.gl);
+  drop(hd.rho);
+  drop(hd.Mr);
+  drop(hd.V);
+  drop(hd.MV);
+  drop(hd.q);
+  drop(hd.part);
+  hd = HartreeDev{};
+  hd.l_max = L;
+  hd.n_atoms = g->n_atoms;
+  hd.n_shells = (int)shells.size();
+  hd.shells = g->upload(shells);
+  hd.shell_pts = g->upload(pts_sorted);
+  hd.sys = g->upload(hs);
+  hd.sys_natoms = g->upload(natoms);
+  hd.cp = g->upload(cp);
+  hd.den = g->upload(den);
+  hd.gl = g->upload(gauss_legendre(kGauss));
+  const size_t nodes = std::max<size_t>(1, (size_t)g->n_atoms * K_max * nlm);
+  hd.rho = (double*)g->alloc(nodes * sizeof(double));
+  hd.Mr = (double*)g->alloc(nodes * sizeof(double));
+  hd.V = (double*)g->alloc(nodes * sizeof(double));
+  hd.MV = (double*)g->alloc(nodes * sizeof(double));
+  hd.q = (double*)g->alloc(std::max<size_t>(1, (size_t)g->n_atoms * nlm) * sizeof(double));
+  hd.part = (double*)g->alloc((size_t)g->n_sys * kHartreeBlocks * sizeof(double));
+  g->h_ready = true;
+}
+}  // namespace
+
+aims_status aims_hartree(aims_grid* g, const double* n, double* v_out, double* E_out_or_null) {
+  return guarded(g, [&] {
+    if (g->h_K.empty()) fail(AIMS_ERR_ARG, "no Hartree grid set (aims_grid_set_hartree)");
+    for (int k = 0; k < g->n_sys; ++k)
+      if (!g->h_K[k]) fail(AIMS_ERR_ARG, "system %d has no Hartree grid", k);
+    require_device(n, "n", g->n_points > 0);
+    require_device(v_out, "v_out", g->n_points > 0);
+    if (E_out_or_null) require_device(E_out_or_null, "E_out");
+    set_positions(g, nullptr);
+    if (g->moved) fail(AIMS_ERR_ARG, "the Hartree potential is taken at the setup positions");
+    if (!g->h_ready) build_hartree(g);
+    hipchk(launch_hartree(g->dens.dv, g->hd, n, v_out, E_out_or_null, g->stream), "Hartree");
   });
 }
 

@@ -14,7 +14,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import DM_METHOD, PRECISION, XC_FUNCTIONAL, AimsError, AimsMovingGrid, AimsSystem, AimsTuning
+from ._lib import (DM_METHOD, PRECISION, XC_FUNCTIONAL, AimsError, AimsHartreeGrid, AimsMovingGrid,
+                   AimsSystem, AimsTuning)
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -187,6 +188,31 @@ class AimsGrid:
         with torch.cuda.device(self.device):
             self._check(self._L.aims_density_gradient(self._h, _ptr(P), _ptr(n), _ptr(grad)))
         return n, grad
+
+    def set_hartree_grid(self, radial, l_max: int = 6, systems=None):
+        """Radial structure of every system's grid for ``hartree``: ``radial[k]`` = (pt_node,
+        n_radial, r_map) of system k, pt_node the radial node of each point (caller order) on
+        its owner's Becke grid; owners from the systems' ``pt_atom``."""
+        systems = self._systems if systems is None else systems
+        for k, s in enumerate(systems):
+            node, n_radial, r_map = radial[k]
+            owner = np.ascontiguousarray(s.pt_atom, dtype=np.int32)
+            node = np.ascontiguousarray(node, dtype=np.int32)
+            h = AimsHartreeGrid()
+            h.pt_owner = _np_ptr(owner, c_int32)
+            h.pt_node = _np_ptr(node, c_int32)
+            h.n_radial = int(n_radial)
+            h.r_map = float(r_map)
+            h.l_max = int(l_max)
+            self._check(self._L.aims_grid_set_hartree(self._h, k, byref(h)))
+
+    def hartree(self, n: torch.Tensor, v_out=None, E_out=None):
+        """(v_H [n_points], E_H [n_sys]) of the density n (caller order)."""
+        v = self._new(self.n_points) if v_out is None else v_out
+        E = self._new(self.n_sys) if E_out is None else E_out
+        with torch.cuda.device(self.device):
+            self._check(self._L.aims_hartree(self._h, _ptr(n), _ptr(v), _ptr(E)))
+        return v, E
 
     def xc(self, n: torch.Tensor, functional: str = "lda", v_out=None, sums_out=None):
         """(v_xc [n_points], sums [n_sys, 2] = (E_xc, sum w n v_xc)) of the density n (caller

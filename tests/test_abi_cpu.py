@@ -97,5 +97,7 @@ def test_null_arguments(lib, c1):
     assert lib.aims_density_gradient(None, None, None, None) == -1
     assert lib.aims_integrate_h_gga(None, 0, None, None, None) == -1
     assert lib.aims_xc_gga(None, 1, None, None, None, None, None) == -1
+    assert lib.aims_grid_set_hartree(None, 0, None) == -1
+    assert lib.aims_hartree(None, None, None, None) == -1
     lib.aims_grid_destroy(None)
     lib.aims_step_graph_destroy(None)
