@@ -273,6 +273,30 @@ def bench_single(args, torch, inst, backward=False):
                                       xc["ms_h_with_gradient_term"] + best_dm)
             outside["xc_fp64"] = xc
             _log(f"xc: {json.dumps({k: round(x, 3) for k, x in xc.items()})}")
+            # the electrostatic step and one whole LDA s.c.f. iteration (density, Hartree,
+            # exchange-correlation, H, density matrix)
+            import synth
+            g.set_hartree_grid([synth.radial_shells(inst)], l_max=6)
+            vh = torch.empty(g.n_points, dtype=torch.float64, device=dev)
+            EH = torch.empty(1, dtype=torch.float64, device=dev)
+            g.hartree(nn, v_out=vh, E_out=EH)                       # first call builds tables
+            it = {"l_max": 6}
+            it["ms_hartree"], _ = timer.run(lambda: g.hartree(nn, v_out=vh, E_out=EH), 3, 1)
+            vx = torch.empty(g.n_points, dtype=torch.float64, device=dev)
+
+            def scf_iteration():
+                g.update_density(P_new, v, prec="fp64", n_out=nn, sums_out=sums)
+                g.hartree(nn, v_out=vh, E_out=EH)
+                g.xc(nn, v_out=vx)
+                torch.add(vh, vx, out=vt)
+                vt.add_(v)
+                g.integrate_h(vt, prec="fp64", H_out=H2)
+                g.density_matrix(H2, S, n_e, method="purify", P_out=P_new, want_eps=False)
+            g.density_matrix(H, S, n_e, method="eigen", P_out=P_new, want_eps=False)
+            it["ms_lda_scf_iteration"], _ = timer.run(scf_iteration, 3, 1)
+            it["E_H"] = float(EH.item())
+            outside["hartree_fp64"] = it
+            _log(f"hartree: {json.dumps({k: round(x, 3) for k, x in it.items()})}")
     if backward and inst.pt_wgrid is not None:
         # total (moving-grid) forces: Pulay + partition-weight + nuclear-potential + point motion
         g.set_moving_grid()
