@@ -273,6 +273,21 @@ def bench_single(args, torch, inst, backward=False):
                                       xc["ms_h_with_gradient_term"] + best_dm)
             outside["xc_fp64"] = xc
             _log(f"xc: {json.dumps({k: round(x, 3) for k, x in xc.items()})}")
+            # the mixed forms' energy error on the occupied-orbital density matrix (physical P,
+            # n >= 0) next to the random-sign P of the workload
+            occ = {}
+            e64 = None
+            for prec in ("fp64", "fp32", "bf16x3"):
+                g.update_density(P_new, v, prec=prec, n_out=nn, sums_out=sums)
+                s_ = sums.cpu().numpy()[0]
+                e = float(s_[1] + s_[2])
+                if prec == "fp64":
+                    e64 = e
+                else:
+                    occ[prec] = {"abs_dE_Ha_vs_fp64": abs(e - e64), "meets_1e-6_Ha": abs(e - e64) <= 1e-6}
+            occ["E_fp64"] = e64
+            outside["mixed_forms_on_occupied_P"] = occ
+            _log(f"mixed forms on occupied P: {json.dumps(occ)}")
             # the electrostatic step and one whole LDA s.c.f. iteration (density, Hartree,
             # exchange-correlation, H, density matrix)
             import synth
