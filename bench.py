@@ -225,7 +225,7 @@ def bench_single(args, torch, inst, backward=False):
     g.set_tuning(prec="fp64", **res["fp64"]["tuning"])
     ms_S, _ = timer.run(lambda: g.integrate_h(v, prec="fp64", H_out=H, S_out=S, want_S=True), 3, 1)
     outside = {"setup_s": setup_s, "ms_integrate_h_with_S_fp64": ms_S}
-    if not backward:
+    if not backward and not args.step_only:
         # the step after H: the occupied-subspace density matrix (closed shell), and a whole
         # s.c.f. iteration (density + H + density matrix) with the density-matrix share of it
         n_e = float(np.sum(inst.atom_Z))
@@ -312,7 +312,7 @@ def bench_single(args, torch, inst, backward=False):
             it["E_H"] = float(EH.item())
             outside["hartree_fp64"] = it
             _log(f"hartree: {json.dumps({k: round(x, 3) for k, x in it.items()})}")
-    if backward and inst.pt_wgrid is not None:
+    if backward and inst.pt_wgrid is not None and not args.step_only:
         # total (moving-grid) forces: Pulay + partition-weight + nuclear-potential + point motion
         g.set_moving_grid()
         dR = torch.empty(inst.n_atoms, 3, dtype=torch.float64, device=dev)
@@ -460,6 +460,9 @@ def main():
                          '\'{"fp64": {"h_merge": 1, "density_pblocks": 2, "persistent": 1}}\'')
     ap.add_argument("--cpu-chunks", type=int, default=120,
                     help="point chunks of the oracle's CPU baseline sample (0 = skip)")
+    ap.add_argument("--step-only", action="store_true",
+                    help="time the step alone: skip the measurements outside it (density matrix, "
+                         "exchange-correlation, Hartree, total forces), e.g. for profiler runs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 launches): the reference "
                          "kernel that scales the HBM byte counters of a profiler run")

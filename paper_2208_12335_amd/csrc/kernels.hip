@@ -146,11 +146,13 @@ __device__ __forceinline__ void eval_atom_point(double dx, double dy, double dz,
   }
 }
 
-// Basis values of one batch: kPhiSlices workgroups of four waves per batch; wave w of the
-// batch (0 .. 4 kPhiSlices - 1) takes the batch's relevant atoms w, w + 4 kPhiSlices, ... and,
-// for each, sweeps the padded point range with its 64 lanes.  Every wave works on one atom at a
-// time, so the species, shell and table addressing is wave-uniform (scalar); lanes past the
-// batch's points write the zero padding of the atom's rows.
+// Basis values of one batch: kPhiSlices workgroups of four waves per batch; workgroup s takes
+// the batch's relevant atoms s, s + kPhiSlices, ..., and its four waves take the points
+// 64 w + lane (+ 256 ...) of the same atom together, so that each slab row (one function, the
+// batch's padded points) is written in one burst by the workgroup (measured faster than one
+// wave sweeping a row in four separate chunks).  The atom is workgroup-uniform, so the species,
+// shell and table addressing is scalar; lanes past the batch's points write the zero padding
+// of the atom's rows.
 constexpr int kPhiSlices = 4;
 
 template <typename T, int LAYOUT>
@@ -163,19 +165,20 @@ phi_eval_kernel(const BatchDesc* __restrict__ batches, int b0, const double4* __
                 const double* __restrict__ v, int mode, void* __restrict__ slab1,
                 void* __restrict__ slab2) {
   const int bi = blockIdx.x / kPhiSlices;
-  const int wave = __builtin_amdgcn_readfirstlane((int)(blockIdx.x % kPhiSlices) * 4 + (int)(threadIdx.x >> 6));
+  const int slice = (int)(blockIdx.x % kPhiSlices);
+  const int wq = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   const BatchDesc d = batches[b0 + bi];
   const int np = d.n_p, na = d.n_atoms, ldp = d.ldp;
   typedef typename std::conditional<LAYOUT == kLayoutDense, T, bf16_t>::type S;
   const int64_t off = (LAYOUT == kLayoutDense ? 1 : 2) * d.slab_off;
   SlabStore<T, LAYOUT> store{(S*)slab1 + off, (S*)slab2 + off, ldp};
-  for (int k = wave; k < na; k += 4 * kPhiSlices) {
+  for (int k = slice; k < na; k += kPhiSlices) {
     const int atom = batch_atoms[d.atom_off + k];
     const int col0 = batch_acol[d.atom_off + k];
     const SpeciesDesc sd = species[atom_species[atom]];
     const double ax = atom_xyz[3 * atom], ay = atom_xyz[3 * atom + 1], az = atom_xyz[3 * atom + 2];
-    for (int p = lane; p < ldp; p += 64) {
+    for (int p = 64 * wq + lane; p < ldp; p += 256) {
       if (p < np) {
         const double4 P4 = pts[d.pt_off + p];
         double wv = 0.0;
