@@ -979,6 +979,187 @@ aims_status guarded(aims_grid* g, F&& f) {
   }
 }
 
+// Tables of the wave-per-point force kernel (setup positions, current partition parameters):
+// 1 / (a |R_b - R_c|) per system, and runs of consecutive batches of one system holding about
+// the same number of points, about kForceRanges of them in all.
+constexpr int kForceRanges = 4096;
+constexpr int kForceWaveMaxAtoms = 512;
+
+void build_force_tables(aims_grid* g, int max_na) {
+  int k = 1;
+  while (64 * k < max_na) k *= 2;
+  std::vector<int64_t> pair_off(g->n_sys);
+  int64_t tot = 0;
+  for (int s = 0; s < g->n_sys; ++s) {
+    const int64_t na = g->sys_atom_range[2 * s + 1] - g->sys_atom_range[2 * s];
+    pair_off[s] = tot;
+    tot += na * na;
+  }
+  std::vector<double> inv(std::max<int64_t>(1, tot), 0.0);
+  for (int s = 0; s < g->n_sys; ++s) {
+    const int a0 = (int)g->sys_atom_range[2 * s], na = (int)(g->sys_atom_range[2 * s + 1] - a0);
+    const double a = g->sys_model[2 * s + 1];
+    const double* X = g->atom_xyz0.data() + 3 * (size_t)a0;
+    for (int b = 0; b < na; ++b)
+      for (int c = 0; c < na; ++c) {
+        if (b == c) continue;
+        const double dx = X[3 * b] - X[3 * c], dy = X[3 * b + 1] - X[3 * c + 1], dz = X[3 * b + 2] - X[3 * c + 2];
+        const double r = std::sqrt(dx * dx + dy * dy + dz * dz);
+        if (!(r > 0.0)) fail(AIMS_ERR_ARG, "system %d: atoms %d and %d coincide", s, b, c);
+        inv[pair_off[s] + (int64_t)b * na + c] = 1.0 / (a * r);
+      }
+  }
+  const BatchSet& bs = g->dens;
+  const int64_t nb_all = (int64_t)bs.batches.size();
+  std::vector<ForceRange> ranges;
+  std::vector<int64_t> part_off(g->n_sys, 0);
+  std::vector<int32_t> nrange(g->n_sys, 0);
+  int64_t cursor = 0;
+  for (int s = 0; s < g->n_sys; ++s) {
+    const int na = (int)(g->sys_atom_range[2 * s + 1] - g->sys_atom_range[2 * s]);
+    const int64_t B0 = bs.sys_batch_range[2 * s], B1 = bs.sys_batch_range[2 * s + 1];
+    part_off[s] = cursor;
+    if (B1 <= B0) continue;
+    int64_t npts = 0;
+    for (int64_t b = B0; b < B1; ++b) npts += bs.batches[b].n_p;
+    const int64_t want = std::max<int64_t>(1, std::min<int64_t>(B1 - B0, (kForceRanges * (B1 - B0) + nb_all - 1) / nb_all));
+    const double per = (double)npts / (double)want;
+    int64_t b = B0, acc = 0;
+    for (int64_t r = 0; r < want && b < B1; ++r) {
+      const int64_t start = b;
+      const double goal = per * (double)(r + 1);
+      while (b < B1 && (b == start || (double)(acc + bs.batches[b].n_p) <= goal + 0.5 * per)) acc += bs.batches[b++].n_p;
+      if (r == want - 1) while (b < B1) acc += bs.batches[b++].n_p;
+      ranges.push_back(ForceRange{(int32_t)start, (int32_t)b, s, 0, cursor});
+      cursor += 3 * (int64_t)na;
+      ++nrange[s];
+    }
+  }
+  auto drop = [&](auto*& ptr) {
+    if (ptr) g->release(ptr);
+    ptr = nullptr;
+  };
+  drop(g->d_franges);
+  drop(g->d_inv_aR);
+  drop(g->d_pair_off);
+  drop(g->d_fpart);
+  drop(g->d_fpart_off);
+  drop(g->d_fnrange);
+  g->d_inv_aR = g->upload(inv);
+  g->d_pair_off = g->upload(pair_off);
+  if (ranges.empty()) ranges.push_back(ForceRange{0, 0, 0, 0, 0});     // a valid (unused) entry
+  g->d_franges = g->upload(ranges);
+  g->gf_nranges = (int)(ranges.size() == 1 && ranges[0].b1 == 0 ? 0 : ranges.size());
+  g->d_fpart = (double*)g->alloc(std::max<int64_t>(1, cursor) * sizeof(double));
+  g->d_fpart_off = g->upload(part_off);
+  g->d_fnrange = g->upload(nrange);
+  g->gf_k = k;
+  g->gf_ready = true;
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1]: Newton's iteration on P_n from the three-term
+// recurrence, w = 2 / ((1 - x^2) P_n'(x)^2)
+std::vector<double> gauss_legendre(int n) {
+  std::vector<double> out(2 * (size_t)n);
+  for (int i = 0; i < n; ++i) {
+    double x = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (x * p1 - p0) / (x * x - 1.0);
+      const double dx = p1 / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    out[n - 1 - i] = x;                                  // ascending
+    out[n + (n - 1 - i)] = 2.0 / ((1.0 - x * x) * dp * dp);
+  }
+  return out;
+}
+
+void build_hartree(aims_grid* g) {
+  const int L = g->hartree_lmax, nlm = (L + 1) * (L + 1);
+  int K_max = 0;
+  for (int k : g->h_K) K_max = std::max(K_max, k);
+  // shells: every (atom, node), points grouped by (atom, node) in batch-order indices
+  std::vector<HartreeShell> shells;
+  std::vector<int32_t> count((size_t)g->n_atoms * K_max, 0);
+  for (int64_t i = 0; i < g->n_points; ++i) ++count[(size_t)g->h_owner[i] * K_max + g->h_node[i]];
+  std::vector<int32_t> start(count.size() + 1, 0);
+  for (size_t c = 0; c < count.size(); ++c) start[c + 1] = start[c] + count[c];
+  std::vector<int32_t> pts_sorted(std::max<int64_t>(1, g->n_points));
+  std::vector<int32_t> fill(start.begin(), start.end() - 1);
+  for (int64_t i = 0; i < g->n_points; ++i)
+    pts_sorted[fill[(size_t)g->h_owner[i] * K_max + g->h_node[i]]++] = (int32_t)i;
+  std::vector<HartreeSys> hs(g->n_sys);
+  std::vector<double> cp, den;
+  std::vector<int32_t> natoms(g->n_sys);
+  for (int s = 0; s < g->n_sys; ++s) {
+    const int K = g->h_K[s];
+    const double rm = g->h_rmap[s];
+    hs[s] = HartreeSys{K, K_max, (int32_t)cp.size(), 0, rm};
+    // Thomas factors of M_{i-1} + 4 M_i + M_{i+1} = rhs_i (i = 1..K-2), natural ends
+    std::vector<double> c(K, 0.0), d(K, 1.0);
+    for (int i = 1; i <= K - 2; ++i) {
+      d[i] = i == 1 ? 4.0 : 4.0 - c[i - 1];
+      c[i] = 1.0 / d[i];
+    }
+    cp.insert(cp.end(), c.begin(), c.end());
+    den.insert(den.end(), d.begin(), d.end());
+    const int a0 = (int)g->sys_atom_range[2 * s], a1 = (int)g->sys_atom_range[2 * s + 1];
+    natoms[s] = a1 - a0;
+    for (int a = a0; a < a1; ++a)
+      for (int k = 0; k < K; ++k) {
+        // Becke radial weight with r^2: W = pi/(K+1) sin t 2 r_m/(1 - cos t)^2 r^2
+        const double t = (double)(k + 1) * M_PI / (double)(K + 1), x = std::cos(t);
+        const double r = rm * (1.0 + x) / (1.0 - x);
+        const double W = M_PI / (double)(K + 1) * std::sin(t) * 2.0 * rm / ((1.0 - x) * (1.0 - x)) * r * r;
+        const size_t cidx = (size_t)a * K_max + k;
+        shells.push_back(HartreeShell{a, start[cidx], start[cidx + 1], (int32_t)cidx, 1.0 / W});
+      }
+  }
+  HartreeDev& hd = g->hd;
+  auto drop = [&](auto* p) {
+    if (p) g->release((void*)p);
+  };
+  drop(hd.shells);
+  drop(hd.shell_pts);
+  drop(hd.sys);
+  drop(hd.sys_natoms);
+  drop(hd.cp);
+  drop(hd.den);
+  drop(hd.gl);
+  drop(hd.rho);
+  drop(hd.Mr);
+  drop(hd.V);
+  drop(hd.MV);
+  drop(hd.q);
+  drop(hd.part);
+  hd = HartreeDev{};
+  hd.l_max = L;
+  hd.n_atoms = g->n_atoms;
+  hd.n_shells = (int)shells.size();
+  hd.shells = g->upload(shells);
+  hd.shell_pts = g->upload(pts_sorted);
+  hd.sys = g->upload(hs);
+  hd.sys_natoms = g->upload(natoms);
+  hd.cp = g->upload(cp);
+  hd.den = g->upload(den);
+  hd.gl = g->upload(gauss_legendre(kGauss));
+  const size_t nodes = std::max<size_t>(1, (size_t)g->n_atoms * K_max * nlm);
+  hd.rho = (double*)g->alloc(nodes * sizeof(double));
+  hd.Mr = (double*)g->alloc(nodes * sizeof(double));
+  hd.V = (double*)g->alloc(nodes * sizeof(double));
+  hd.MV = (double*)g->alloc(nodes * sizeof(double));
+  hd.q = (double*)g->alloc(std::max<size_t>(1, (size_t)g->n_atoms * nlm) * sizeof(double));
+  hd.part = (double*)g->alloc((size_t)g->n_sys * kHartreeBlocks * sizeof(double));
+  g->h_ready = true;
+}
+
 }  // namespace
 
 // -------------------------------------------------------------------------------------------------
@@ -1212,84 +1393,6 @@ aims_status aims_grid_set_moving(aims_grid* g, int32_t sys, const aims_moving_gr
   });
 }
 
-// Tables of the wave-per-point force kernel (setup positions, current partition parameters):
-// 1 / (a |R_b - R_c|) per system, and runs of consecutive batches of one system holding about
-// the same number of points, about kForceRanges of them in all.
-constexpr int kForceRanges = 4096;
-constexpr int kForceWaveMaxAtoms = 512;
-
-void build_force_tables(aims_grid* g, int max_na) {
-  int k = 1;
-  while (64 * k < max_na) k *= 2;
-  std::vector<int64_t> pair_off(g->n_sys);
-  int64_t tot = 0;
-  for (int s = 0; s < g->n_sys; ++s) {
-    const int64_t na = g->sys_atom_range[2 * s + 1] - g->sys_atom_range[2 * s];
-    pair_off[s] = tot;
-    tot += na * na;
-  }
-  std::vector<double> inv(std::max<int64_t>(1, tot), 0.0);
-  for (int s = 0; s < g->n_sys; ++s) {
-    const int a0 = (int)g->sys_atom_range[2 * s], na = (int)(g->sys_atom_range[2 * s + 1] - a0);
-    const double a = g->sys_model[2 * s + 1];
-    const double* X = g->atom_xyz0.data() + 3 * (size_t)a0;
-    for (int b = 0; b < na; ++b)
-      for (int c = 0; c < na; ++c) {
-        if (b == c) continue;
-        const double dx = X[3 * b] - X[3 * c], dy = X[3 * b + 1] - X[3 * c + 1], dz = X[3 * b + 2] - X[3 * c + 2];
-        const double r = std::sqrt(dx * dx + dy * dy + dz * dz);
-        if (!(r > 0.0)) fail(AIMS_ERR_ARG, "system %d: atoms %d and %d coincide", s, b, c);
-        inv[pair_off[s] + (int64_t)b * na + c] = 1.0 / (a * r);
-      }
-  }
-  const BatchSet& bs = g->dens;
-  const int64_t nb_all = (int64_t)bs.batches.size();
-  std::vector<ForceRange> ranges;
-  std::vector<int64_t> part_off(g->n_sys, 0);
-  std::vector<int32_t> nrange(g->n_sys, 0);
-  int64_t cursor = 0;
-  for (int s = 0; s < g->n_sys; ++s) {
-    const int na = (int)(g->sys_atom_range[2 * s + 1] - g->sys_atom_range[2 * s]);
-    const int64_t B0 = bs.sys_batch_range[2 * s], B1 = bs.sys_batch_range[2 * s + 1];
-    part_off[s] = cursor;
-    if (B1 <= B0) continue;
-    int64_t npts = 0;
-    for (int64_t b = B0; b < B1; ++b) npts += bs.batches[b].n_p;
-    const int64_t want = std::max<int64_t>(1, std::min<int64_t>(B1 - B0, (kForceRanges * (B1 - B0) + nb_all - 1) / nb_all));
-    const double per = (double)npts / (double)want;
-    int64_t b = B0, acc = 0;
-    for (int64_t r = 0; r < want && b < B1; ++r) {
-      const int64_t start = b;
-      const double goal = per * (double)(r + 1);
-      while (b < B1 && (b == start || (double)(acc + bs.batches[b].n_p) <= goal + 0.5 * per)) acc += bs.batches[b++].n_p;
-      if (r == want - 1) while (b < B1) acc += bs.batches[b++].n_p;
-      ranges.push_back(ForceRange{(int32_t)start, (int32_t)b, s, 0, cursor});
-      cursor += 3 * (int64_t)na;
-      ++nrange[s];
-    }
-  }
-  auto drop = [&](auto*& ptr) {
-    if (ptr) g->release(ptr);
-    ptr = nullptr;
-  };
-  drop(g->d_franges);
-  drop(g->d_inv_aR);
-  drop(g->d_pair_off);
-  drop(g->d_fpart);
-  drop(g->d_fpart_off);
-  drop(g->d_fnrange);
-  g->d_inv_aR = g->upload(inv);
-  g->d_pair_off = g->upload(pair_off);
-  if (ranges.empty()) ranges.push_back(ForceRange{0, 0, 0, 0, 0});     // a valid (unused) entry
-  g->d_franges = g->upload(ranges);
-  g->gf_nranges = (int)(ranges.size() == 1 && ranges[0].b1 == 0 ? 0 : ranges.size());
-  g->d_fpart = (double*)g->alloc(std::max<int64_t>(1, cursor) * sizeof(double));
-  g->d_fpart_off = g->upload(part_off);
-  g->d_fnrange = g->upload(nrange);
-  g->gf_k = k;
-  g->gf_ready = true;
-}
-
 aims_status aims_total_forces(aims_grid* g, aims_precision prec, const double* P, const double* gE,
                               double* sums_out_or_null, double* dE_dR) {
   return guarded(g, [&] {
@@ -1483,110 +1586,6 @@ aims_status aims_grid_set_hartree(aims_grid* g, int32_t sys, const aims_hartree_
   });
 }
 
-namespace {
-// Gauss-Legendre nodes and weights on [-1, 1]: Newton's iteration on P_n from the three-term
-// recurrence, w = 2 / ((1 - x^2) P_n'(x)^2)
-std::vector<double> gauss_legendre(int n) {
-  std::vector<double> out(2 * (size_t)n);
-  for (int i = 0; i < n; ++i) {
-    double x = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
-    for (int it = 0; it < 100; ++it) {
-      double p0 = 1.0, p1 = x;
-      for (int k = 2; k <= n; ++k) {
-        const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
-        p0 = p1;
-        p1 = p2;
-      }
-      dp = n * (x * p1 - p0) / (x * x - 1.0);
-      const double dx = p1 / dp;
-      x -= dx;
-      if (std::fabs(dx) < 1e-16) break;
-    }
-    out[n - 1 - i] = x;                                  // ascending
-    out[n + (n - 1 - i)] = 2.0 / ((1.0 - x * x) * dp * dp);
-  }
-  return out;
-}
-
-void build_hartree(aims_grid* g) {
-  const int L = g->hartree_lmax, nlm = (L + 1) * (L + 1);
-  int K_max = 0;
-  for (int k : g->h_K) K_max = std::max(K_max, k);
-  // shells: every (atom, node), points grouped by (atom, node) in batch-order indices
-  std::vector<HartreeShell> shells;
-  std::vector<int32_t> count((size_t)g->n_atoms * K_max, 0);
-  for (int64_t i = 0; i < g->n_points; ++i) ++count[(size_t)g->h_owner[i] * K_max + g->h_node[i]];
-  std::vector<int32_t> start(count.size() + 1, 0);
-  for (size_t c = 0; c < count.size(); ++c) start[c + 1] = start[c] + count[c];
-  std::vector<int32_t> pts_sorted(std::max<int64_t>(1, g->n_points));
-  std::vector<int32_t> fill(start.begin(), start.end() - 1);
-  for (int64_t i = 0; i < g->n_points; ++i)
-    pts_sorted[fill[(size_t)g->h_owner[i] * K_max + g->h_node[i]]++] = (int32_t)i;
-  std::vector<HartreeSys> hs(g->n_sys);
-  std::vector<double> cp, den;
-  std::vector<int32_t> natoms(g->n_sys);
-  for (int s = 0; s < g->n_sys; ++s) {
-    const int K = g->h_K[s];
-    const double rm = g->h_rmap[s];
-    hs[s] = HartreeSys{K, K_max, (int32_t)cp.size(), 0, rm};
-    // Thomas factors of M_{i-1} + 4 M_i + M_{i+1} = rhs_i (i = 1..K-2), natural ends
-    std::vector<double> c(K, 0.0), d(K, 1.0);
-    for (int i = 1; i <= K - 2; ++i) {
-      d[i] = i == 1 ? 4.0 : 4.0 - c[i - 1];
-      c[i] = 1.0 / d[i];
-    }
-    cp.insert(cp.end(), c.begin(), c.end());
-    den.insert(den.end(), d.begin(), d.end());
-    const int a0 = (int)g->sys_atom_range[2 * s], a1 = (int)g->sys_atom_range[2 * s + 1];
-    natoms[s] = a1 - a0;
-    for (int a = a0; a < a1; ++a)
-      for (int k = 0; k < K; ++k) {
-        // Becke radial weight with r^2: W = pi/(K+1) sin t 2 r_m/(1 - cos t)^2 r^2
-        const double t = (double)(k + 1) * M_PI / (double)(K + 1), x = std::cos(t);
-        const double r = rm * (1.0 + x) / (1.0 - x);
-        const double W = M_PI / (double)(K + 1) * std::sin(t) * 2.0 * rm / ((1.0 - x) * (1.0 - x)) * r * r;
-        const size_t cidx = (size_t)a * K_max + k;
-        shells.push_back(HartreeShell{a, start[cidx], start[cidx + 1], (int32_t)cidx, 1.0 / W});
-      }
-  }
-  HartreeDev& hd = g->hd;
-  auto drop = [&](auto* p) {
-    if (p) g->release((void*)p);
-  };
-  drop(hd.shells);
-  drop(hd.shell_pts);
-  drop(hd.sys);
-  drop(hd.sys_natoms);
-  drop(hd.cp);
-  drop(hd.den);
-  drop(hd.gl);
-  drop(hd.rho);
-  drop(hd.Mr);
-  drop(hd.V);
-  drop(hd.MV);
-  drop(hd.q);
-  drop(hd.part);
-  hd = HartreeDev{};
-  hd.l_max = L;
-  hd.n_atoms = g->n_atoms;
-  hd.n_shells = (int)shells.size();
-  hd.shells = g->upload(shells);
-  hd.shell_pts = g->upload(pts_sorted);
-  hd.sys = g->upload(hs);
-  hd.sys_natoms = g->upload(natoms);
-  hd.cp = g->upload(cp);
-  hd.den = g->upload(den);
-  hd.gl = g->upload(gauss_legendre(kGauss));
-  const size_t nodes = std::max<size_t>(1, (size_t)g->n_atoms * K_max * nlm);
-  hd.rho = (double*)g->alloc(nodes * sizeof(double));
-  hd.Mr = (double*)g->alloc(nodes * sizeof(double));
-  hd.V = (double*)g->alloc(nodes * sizeof(double));
-  hd.MV = (double*)g->alloc(nodes * sizeof(double));
-  hd.q = (double*)g->alloc(std::max<size_t>(1, (size_t)g->n_atoms * nlm) * sizeof(double));
-  hd.part = (double*)g->alloc((size_t)g->n_sys * kHartreeBlocks * sizeof(double));
-  g->h_ready = true;
-}
-}  // namespace
 
 aims_status aims_hartree(aims_grid* g, const double* n, double* v_out, double* E_out_or_null) {
   return guarded(g, [&] {

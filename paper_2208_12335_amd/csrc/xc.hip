@@ -49,7 +49,6 @@ struct Dual2 {
   double v, dn, ds;
 };
 __device__ __forceinline__ Dual2 operator+(Dual2 a, Dual2 b) { return {a.v + b.v, a.dn + b.dn, a.ds + b.ds}; }
-__device__ __forceinline__ Dual2 operator-(Dual2 a, Dual2 b) { return {a.v - b.v, a.dn - b.dn, a.ds - b.ds}; }
 __device__ __forceinline__ Dual2 operator*(Dual2 a, Dual2 b) {
   return {a.v * b.v, a.dn * b.v + a.v * b.dn, a.ds * b.v + a.v * b.ds};
 }
