@@ -43,6 +43,7 @@ struct HartreeDev {
   double* V = nullptr;
   double* MV = nullptr;
   double* q = nullptr;                      // [n_atoms][(l_max+1)^2]
+  double4* Vc = nullptr;                    // [n_atoms][K_max][(l_max+1)^2] cubic coefficients
   double* part = nullptr;                   // [n_sys][kHartreeBlocks]
 };
 

@@ -6,7 +6,8 @@
 //                     kGauss-point Gauss-Legendre per interval (nodes and weights from the host)
 //                     for the two radial Poisson integrals,
 //                     V_lm at the nodes and its own natural spline, and the moment q_lm
-//   potential_kernel  one thread per point: v_H = sum_atoms sum_lm V_lm(r) Y_lm(u), exterior
+//   potential_kernel  one thread per point: v_H = sum_atoms sum_lm V_lm(r) Y_lm(u) (the V spline
+//                     as per-interval cubic coefficients, one 32-byte load per term), exterior
 //                     form beyond the outermost node, (r/r_min)^l inside the innermost
 // Real orthonormal Y_lm without the Condon-Shortley phase, from the associated-Legendre
 // recurrence in z and the powers (x + i y)^m, generated m-outer / l-inner and consumed as they
@@ -46,7 +47,8 @@ __device__ __forceinline__ void for_each_ylm(double x, double y, double z, F&& v
       if (l == m) {
         q = qmm;
       } else {
-        q = ((double)(2 * l - 1) * z * q1 - (double)(l + m - 1) * q2) / (double)(l - m);
+        // multiply by the (compile-time) reciprocal: an FP64 division is a long sequence
+        q = ((double)(2 * l - 1) * z * q1 - (double)(l + m - 1) * q2) * (1.0 / (double)(l - m));
         q2 = q1;
         q1 = q;
         fr *= (double)(l - m) / (double)(l + m);
@@ -131,7 +133,7 @@ radial_kernel(int n_atoms, const int32_t* __restrict__ atom_sys, const HartreeSy
               const double* __restrict__ cp, const double* __restrict__ den,
               const double* __restrict__ gl,
               const double* __restrict__ rho, double* __restrict__ Mr, double* __restrict__ V,
-              double* __restrict__ MV, double* __restrict__ q) {
+              double* __restrict__ MV, double* __restrict__ q, double4* __restrict__ Vc) {
   constexpr int NLM = (L + 1) * (L + 1);
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_atoms * NLM) return;
@@ -187,6 +189,15 @@ radial_kernel(int n_atoms, const int32_t* __restrict__ atom_sys, const HartreeSy
     Vy[(size_t)k * NLM] = pref * (Vy[(size_t)k * NLM] * pow(rk, -(l + 1)) + outer * pow(rk, l));
   }
   natural_spline(Vy, MVy, NLM, K, h, cp + S.fac_off, den + S.fac_off);
+  // the same spline per interval as c0 + c1 b + c2 b^2 + c3 b^3 in the local b in [0, 1]:
+  // a y_k + b y_k+1 + ((a^3 - a) M_k + (b^3 - b) M_k+1) h^2/6 with a = 1 - b, expanded
+  double4* C = Vc + (size_t)a * S.K_max * NLM + c;
+  const double h26 = h * h / 6.0;
+  for (int k = 0; k + 1 < K; ++k) {
+    const double y0 = Vy[(size_t)k * NLM], y1 = Vy[(size_t)(k + 1) * NLM];
+    const double m0 = MVy[(size_t)k * NLM], m1 = MVy[(size_t)(k + 1) * NLM];
+    C[(size_t)k * NLM] = double4{y0, y1 - y0 - h26 * (2.0 * m0 + m1), 3.0 * h26 * m0, h26 * (m1 - m0)};
+  }
 }
 
 template <int L>
@@ -195,7 +206,7 @@ potential_kernel(const double4* __restrict__ pts, const int32_t* __restrict__ pe
                  const int64_t* __restrict__ sys_pt_range, const SystemDesc* __restrict__ systems,
                  const int32_t* __restrict__ sys_natoms, const double* __restrict__ atom_xyz,
                  const HartreeSys* __restrict__ hs, const double* __restrict__ V,
-                 const double* __restrict__ MV, const double* __restrict__ q,
+                 const double4* __restrict__ Vc, const double* __restrict__ q,
                  const double* __restrict__ n_in, double* __restrict__ v_out,
                  double* __restrict__ part) {
   constexpr int NLM = (L + 1) * (L + 1);
@@ -218,7 +229,6 @@ potential_kernel(const double4* __restrict__ pts, const int32_t* __restrict__ pe
       const double r = sqrt(dx * dx + dy * dy + dz * dz);
       const double ir = r > 0.0 ? 1.0 / r : 0.0;
       const double* Va = V + (size_t)a * S.K_max * NLM;
-      const double* Ma = MV + (size_t)a * S.K_max * NLM;
       if (r >= rmax) {                      // exterior: 4 pi q / ((2l+1) r^(l+1))
         const double* qa = q + (size_t)a * NLM;
         for_each_ylm<L>(dx * ir, dy * ir, dz * ir, [&](int l, int m, double Y) {
@@ -233,9 +243,10 @@ potential_kernel(const double4* __restrict__ pts, const int32_t* __restrict__ pe
         int k = (int)floor(t / h) - 1;      // interval [theta_k, theta_k+1], theta_k = (k+1) h
         k = k < 0 ? 0 : (k > K - 2 ? K - 2 : k);
         const double b = (t - h * (double)(k + 1)) / h;
+        const double4* Ck = Vc + ((size_t)a * S.K_max + k) * NLM;
         for_each_ylm<L>(dx * ir, dy * ir, dz * ir, [&](int l, int m, double Y) {
-          const int c = l * l + l + m;
-          v += spline_at(Va + c, Ma + c, NLM, k, b, h) * Y;
+          const double4 cf = Ck[l * l + l + m];
+          v += (((cf.w * b + cf.z) * b + cf.y) * b + cf.x) * Y;
         });
       }
     }
@@ -276,12 +287,13 @@ hipError_t launch_all(const DeviceView& dv, const HartreeDev& hd, const double* 
   }
   const int nt = hd.n_atoms * NLM;
   hipLaunchKernelGGL(radial_kernel<L>, dim3((nt + 255) / 256), dim3(256), 0, st, hd.n_atoms,
-                     dv.atom_sys, hd.sys, hd.cp, hd.den, hd.gl, hd.rho, hd.Mr, hd.V, hd.MV, hd.q);
+                     dv.atom_sys, hd.sys, hd.cp, hd.den, hd.gl, hd.rho, hd.Mr, hd.V, hd.MV, hd.q,
+                     hd.Vc);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(potential_kernel<L>, dim3(kHartreeBlocks, dv.n_sys), dim3(256), 0, st, dv.pts,
                      dv.perm, dv.sys_pt_range, dv.systems, hd.sys_natoms, dv.atom_xyz, hd.sys,
-                     hd.V, hd.MV, hd.q, n, v_out, hd.part);
+                     hd.V, hd.Vc, hd.q, n, v_out, hd.part);
   e = hipGetLastError();
   if (e != hipSuccess || !E_or_null) return e;
   hipLaunchKernelGGL(energy_kernel, dim3(dv.n_sys), dim3(256), 0, st, hd.part, kHartreeBlocks,

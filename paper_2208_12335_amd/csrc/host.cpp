@@ -1138,6 +1138,7 @@ void build_hartree(aims_grid* g) {
   drop(hd.V);
   drop(hd.MV);
   drop(hd.q);
+  drop(hd.Vc);
   drop(hd.part);
   hd = HartreeDev{};
   hd.l_max = L;
@@ -1156,6 +1157,7 @@ void build_hartree(aims_grid* g) {
   hd.V = (double*)g->alloc(nodes * sizeof(double));
   hd.MV = (double*)g->alloc(nodes * sizeof(double));
   hd.q = (double*)g->alloc(std::max<size_t>(1, (size_t)g->n_atoms * nlm) * sizeof(double));
+  hd.Vc = (double4*)g->alloc(nodes * sizeof(double4));
   hd.part = (double*)g->alloc((size_t)g->n_sys * kHartreeBlocks * sizeof(double));
   g->h_ready = true;
 }
