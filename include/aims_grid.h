@@ -95,6 +95,7 @@ typedef struct {
  * keeps per batch the atoms closer than rc + screen_margin to at least one of its points (and
  * so every basis function that can be nonzero on it), and uploads everything to `device`.
  * `hip_stream` (a hipStream_t, NULL = default stream) is used by every later call.
+ * At most 65535 basis functions per system (AIMS_ERR_UNSUPPORTED beyond).
  * On success *out receives a new handle. */
 aims_status aims_grid_setup(const aims_system *sys, int device, void *hip_stream, aims_grid **out);
 

@@ -22,6 +22,7 @@ constexpr int kMaxShells = 32;      // shells per species
 constexpr int kMaxBatch = 512;      // points per batch
 constexpr int kTile = 64;           // output tile edge of the MFMA kernels
 constexpr int kPad = 32;            // slab rows are padded to a multiple of this many points
+constexpr int kMaxBasis = 65535;    // basis functions per system (32-bit offsets into P)
 
 struct BatchDesc {
   int32_t pt_off;     // first point (batch order)

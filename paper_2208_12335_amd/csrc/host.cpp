@@ -344,6 +344,17 @@ void validate_system(const aims_system* s, int k) {
   for (int a = 0; a < s->n_atoms; ++a)
     if (s->atom_species[a] < 0 || s->atom_species[a] >= s->n_species)
       fail(AIMS_ERR_ARG, "system %d: atom %d has species %d out of range", k, a, s->atom_species[a]);
+  {
+    // the tiled kernels address a system's P with 32-bit element offsets (n_basis^2 < 2^32)
+    std::vector<int64_t> nfn(s->n_species, 0);
+    for (int i = 0, sh = 0; i < s->n_species; ++i)
+      for (int j = 0; j < s->species_nshell[i]; ++j, ++sh) nfn[i] += 2 * s->shell_l[sh] + 1;
+    int64_t nb = 0;
+    for (int a = 0; a < s->n_atoms; ++a) nb += nfn[s->atom_species[a]];
+    if (nb > kMaxBasis)
+      fail(AIMS_ERR_UNSUPPORTED, "system %d: %lld basis functions (at most %d)", k, (long long)nb,
+           kMaxBasis);
+  }
   if (!finite_all(s->atom_xyz, 3 * (size_t)s->n_atoms)) fail(AIMS_ERR_ARG, "system %d: non-finite atom_xyz", k);
   if (!finite_all(s->shell_R, (size_t)nsh * s->n_log) || !finite_all(s->shell_K, (size_t)nsh * s->n_log))
     fail(AIMS_ERR_ARG, "system %d: non-finite radial table", k);

@@ -196,8 +196,8 @@ phi_eval_kernel(const BatchDesc* __restrict__ batches, int b0, const double4* __
 // Tiled MFMA kernels: 256 threads = 4 waves in a 2 (rows) x 2 (columns) arrangement.  Each
 // wave owns 2 x NBN blocks of 16 x 16 outputs; blocks that lie wholly beyond the batch's rows
 // or points are skipped (a wave-uniform branch).  K is staged through LDS with a two-stage
-// pipeline (global -> registers for chunk c+1 while chunk c is multiplied), one barrier per
-// chunk.
+// pipeline (global -> registers for chunk c+1 while chunk c is multiplied; two chunks ahead in
+// the FP64 density kernel with 64-point tiles), one barrier per chunk.
 //
 // LDS layouts avoid bank conflicts on both the staging stores and the MFMA fragment reads:
 // operands whose K index is contiguous in HBM stay K-contiguous with an odd row stride
@@ -350,100 +350,151 @@ density_tile(int item, const TileItem* __restrict__ items, int n_items, const Ba
 
   // A staging: thread (kk = tid % 16, rr = tid / 16) stages P_b[j0 + rr + 16 c][kc + kk] for
   // c = 0..3, so that the 16 lanes of one row read consecutive basis columns (one or two cache
-  // lines per row and instruction); the column index is loaded one chunk ahead
+  // lines per row and instruction).
+  //
+  // FP64 with 64-point tiles: a two-deep register pipeline.  Chunk m is loaded into register
+  // set m & 1 two chunks before it is stashed, so its loads stay in flight across two
+  // multiplies.  Its column index (ci[m & 1]) is loaded before the data loads of chunk m - 1:
+  // memory loads retire in issue order, so waiting for an index never waits for the newer
+  // chunk's data.  The fragments are read in two halves, which frees the registers of the
+  // second set.  Other forms (FP32, FP64 with wider point tiles) have no registers to spare for
+  // a second set: one set, loaded one chunk ahead.
   const int kk = tid & 15, rr = tid >> 4;
-  const T* Prow[4];
+  uint32_t prow[4];                 // row offsets into the system's P (n_basis <= 65535)
   bool rok[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     const int j = j0 + rr + 16 * c;
     rok[c] = j < nb;
-    Prow[c] = Pm + (size_t)cols[rok[c] ? j : 0] * sys.nb;
+    prow[c] = (uint32_t)cols[rok[c] ? j : 0] * (uint32_t)sys.nb;
   }
-  int cidx;
-  T av[4], bv[BQ][4];
-  bool kval;
-  auto load_cols = [&](int kc) {     // unconditional load of a clamped index (no branch)
+  int ci[2];
+  bool kv[2];
+  T av[2][4], bv[2][BQ][4];
+  bool aok[2][4], bok[2][BQ];
+  auto load_cols = [&](auto S, int kc) {   // unconditional load of a clamped index (no branch)
+    constexpr int s = decltype(S)::value;
     const int k = kc + kk;
-    kval = k < nb;
-    cidx = cols[k < nb ? k : nb - 1];
+    kv[s] = k < nb;
+    ci[s] = cols[k < nb ? k : nb - 1];
   };
   // loads are issued unconditionally from clamped addresses (no branch, so they stay in flight
-  // across the multiply of the current chunk); invalid elements are zeroed when stashed
-  bool aok[4], bok[BQ];
-  auto fetch = [&](int kc) {
+  // across the multiplies); invalid elements are zeroed when stashed
+  auto fetch = [&](auto S, int kc) {
+    constexpr int s = decltype(S)::value;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      aok[c] = rok[c] && kval;
-      av[c] = Prow[c][cidx];
+      aok[s][c] = rok[c] && kv[s];
+      av[s][c] = Pm[prow[c] + (uint32_t)ci[s]];
     }
 #pragma unroll
     for (int q = 0; q < BQ; ++q) {
       const int u = tid + 256 * q;
       const int k = u / BW, n4 = u - k * BW;
-      bok[q] = u < BU && kc + k < nb && p0 + 4 * n4 < ldp;
-      load4<T>(S1 + (bok[q] ? (size_t)(kc + k) * ldp + p0 + 4 * n4 : 0), bv[q]);
+      bok[s][q] = u < BU && kc + k < nb && p0 + 4 * n4 < ldp;
+      load4<T>(S1 + (bok[s][q] ? (size_t)(kc + k) * ldp + p0 + 4 * n4 : 0), bv[s][q]);
     }
   };
-  auto stash = [&](int buf) {
+  auto stash = [&](auto S, int buf) {
+    constexpr int s = decltype(S)::value;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) As[buf][(rr + 16 * c) * kLdK + kk] = aok[c] ? av[c] : T(0);
+    for (int c = 0; c < 4; ++c) As[buf][(rr + 16 * c) * kLdK + kk] = aok[s][c] ? av[s][c] : T(0);
 #pragma unroll
     for (int q = 0; q < BQ; ++q) {
       const int u = tid + 256 * q;
       if (u < BU) {
         const int k = u / BW, n4 = u - k * BW;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) Bs[buf][k * LDN + 4 * n4 + c] = bok[q] ? bv[q][c] : T(0);
+        for (int c = 0; c < 4; ++c) Bs[buf][k * LDN + 4 * n4 + c] = bok[s][q] ? bv[s][q][c] : T(0);
       }
     }
   };
   const bool full = mrows >= 32 && ncols >= 16 * NBN;
+  constexpr bool kDeep = sizeof(T) == 8 && NBN == 2;
+  constexpr int kHalves = kDeep ? 2 : 1;   // fragment reads per chunk
+  constexpr int kS = 4 / kHalves;          // k-steps of 4 per fragment read
   auto multiply = [&](int buf) {
-    T a[4][2], b[4][NBN];
 #pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) {
-      const int kr = 4 * s4 + (lane >> 4);
+    for (int h = 0; h < kHalves; ++h) {
+      T a[kS][2], b[kS][NBN];
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi) a[s4][mi] = As[buf][(wm * 32 + mi * 16 + (lane & 15)) * kLdK + kr];
+      for (int s2 = 0; s2 < kS; ++s2) {
+        const int kr = 4 * (kS * h + s2) + (lane >> 4);
 #pragma unroll
-      for (int ni = 0; ni < NBN; ++ni) b[s4][ni] = Bs[buf][kr * LDN + wn * 16 * NBN + ni * 16 + (lane & 15)];
-    }
-    if (full) {
+        for (int mi = 0; mi < 2; ++mi) a[s2][mi] = As[buf][(wm * 32 + mi * 16 + (lane & 15)) * kLdK + kr];
 #pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4)
+        for (int ni = 0; ni < NBN; ++ni) b[s2][ni] = Bs[buf][kr * LDN + wn * 16 * NBN + ni * 16 + (lane & 15)];
+      }
+      if (full) {
 #pragma unroll
-        for (int mi = 0; mi < 2; ++mi)
+        for (int s2 = 0; s2 < kS; ++s2)
 #pragma unroll
-          for (int ni = 0; ni < NBN; ++ni) acc[mi][ni] = mfma16(a[s4][mi], b[s4][ni], acc[mi][ni]);
-    } else {
+          for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4)
+            for (int ni = 0; ni < NBN; ++ni) acc[mi][ni] = mfma16(a[s2][mi], b[s2][ni], acc[mi][ni]);
+      } else {
 #pragma unroll
-        for (int mi = 0; mi < 2; ++mi) {
-          if (16 * mi >= mrows) continue;
+        for (int s2 = 0; s2 < kS; ++s2)
 #pragma unroll
-          for (int ni = 0; ni < NBN; ++ni)
-            if (16 * ni < ncols) acc[mi][ni] = mfma16(a[s4][mi], b[s4][ni], acc[mi][ni]);
-        }
+          for (int mi = 0; mi < 2; ++mi) {
+            if (16 * mi >= mrows) continue;
+#pragma unroll
+            for (int ni = 0; ni < NBN; ++ni)
+              if (16 * ni < ncols) acc[mi][ni] = mfma16(a[s2][mi], b[s2][ni], acc[mi][ni]);
+          }
+      }
     }
   };
 
+  typedef std::integral_constant<int, 0> S0;
+  typedef std::integral_constant<int, 1> S1_;
   const int nchunk = (nb + kKC - 1) / kKC;
-  load_cols(0);
-  fetch(0);
-  stash(0);
-  load_cols(kKC);
-  __syncthreads();
-  for (int c = 0; c < nchunk; ++c) {
-    const int buf = c & 1;
-    if (c + 1 < nchunk) {
-      fetch((c + 1) * kKC);
-      load_cols((c + 2) * kKC);
+  if constexpr (kDeep) {
+    load_cols(S0{}, 0);
+    load_cols(S1_{}, kKC);
+    fetch(S0{}, 0);
+    stash(S0{}, 0);
+    if (nchunk > 1) {
+      load_cols(S0{}, 2 * kKC);
+      fetch(S1_{}, kKC);
     }
-    multiply(buf);
-    if (c + 1 < nchunk) stash(buf ^ 1);
+    if (nchunk > 2) {
+      load_cols(S1_{}, 3 * kKC);
+      fetch(S0{}, 2 * kKC);
+    }
     __syncthreads();
+    // iteration c: multiply chunk c, stash chunk c + 1 (register set (c + 1) & 1 = S) into the
+    // other buffer, then load the index of chunk c + 4 and the data of chunk c + 3 into set S
+    auto iter = [&](int c, auto S) {
+      constexpr int s = decltype(S)::value;
+      multiply(s ^ 1);
+      if (c + 1 < nchunk) stash(S, s);
+      if (c + 3 < nchunk) {
+        load_cols(std::integral_constant<int, s ^ 1>{}, (c + 4) * kKC);
+        fetch(S, (c + 3) * kKC);
+      }
+      __syncthreads();
+    };
+    for (int c = 0; c < nchunk; c += 2) {
+      iter(c, S1_{});
+      if (c + 1 < nchunk) iter(c + 1, S0{});
+    }
+  } else {
+    load_cols(S0{}, 0);
+    fetch(S0{}, 0);
+    stash(S0{}, 0);
+    load_cols(S0{}, kKC);
+    __syncthreads();
+    for (int c = 0; c < nchunk; ++c) {
+      const int buf = c & 1;
+      if (c + 1 < nchunk) {
+        fetch(S0{}, (c + 1) * kKC);
+        load_cols(S0{}, (c + 2) * kKC);
+      }
+      multiply(buf);
+      if (c + 1 < nchunk) stash(S0{}, buf ^ 1);
+      __syncthreads();
+    }
   }
 
   if (xout) {   // store mode (backward): X^T[j][p] into a function-major slab, and, with a

@@ -101,3 +101,29 @@ def test_null_arguments(lib, c1):
     assert lib.aims_hartree(None, None, None, None) == -1
     lib.aims_grid_destroy(None)
     lib.aims_step_graph_destroy(None)
+
+
+def test_basis_count_limit(lib):
+    """A system with more than 65535 basis functions is refused at set-up (the tiled kernels
+    address P with 32-bit offsets): 293 atoms of a species with 32 f shells, 224 functions
+    each, make 65,632."""
+    from paper_2208_12335_amd._lib import AimsSystem
+    n_atoms, nsh, n_log = 293, 32, 8
+    keep = {
+        "xyz": np.arange(3 * n_atoms, dtype=np.float64) * 3.0,
+        "sp": np.zeros(n_atoms, dtype=np.int32),
+        "ns": np.array([nsh], dtype=np.int32),
+        "l": np.full(nsh, 3, dtype=np.int32),
+        "R": np.zeros(nsh * n_log), "K": np.zeros(nsh * n_log),
+    }
+    dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    ip = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    s = AimsSystem()
+    s.n_atoms, s.n_species, s.n_log, s.r0, s.rc = n_atoms, 1, n_log, 1e-4, 9.45
+    s.atom_xyz, s.atom_species, s.species_nshell = dp(keep["xyz"]), ip(keep["sp"]), ip(keep["ns"])
+    s.shell_l, s.shell_R, s.shell_K = ip(keep["l"]), dp(keep["R"]), dp(keep["K"])
+    s.n_points, s.max_batch, s.screen_margin = 0, 256, 0.01
+    h = ctypes.c_void_p()
+    assert lib.aims_grid_setup(ctypes.byref(s), 0, None, ctypes.byref(h)) == -5
+    assert h.value is None
+    assert "basis functions" in lib.aims_last_error(None).decode()
