@@ -5,7 +5,9 @@ A step is one density update (n = sum_ij P_ij phi_i phi_j with the N, E_V, E_T s
 by one Hamiltonian integration (H_ij = sum_p w_p phi_i (v phi_j + t phi_j)), with inputs
 resident in HBM.  GFLOP/s use F = 4 sum_b n_p n_b^2 (the per-batch contractions, counted once,
 also for BF16x3).  The FP64 form and the mixed forms are timed; the headline ``value`` is the
-fastest form whose total energy stays within 1e-6 Ha of the FP64 form.  One JSON line on
+fastest form whose total energy stays within 1e-6 Ha of the FP64 form.  Every form carries its
+own roofline (dominant kernel, algorithmic flops against the MFMA peak of its type; BF16x3
+also states the fraction at three bf16 MFMA flops per algorithmic flop).  One JSON line on
 stdout.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--workload c2|c3|c4|c5]
@@ -137,7 +139,9 @@ def _roofline(kern, head, steps, workload=None, tuning=None):
             "traffic": _measured_traffic(workload, head, dom, tuning),
             "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
             "avg_launch_ms": kd["avg_launch_ms"], "launches_per_step": kd["launches"] / steps,
-            "work_flop_per_launch": kd["work_flop"] / kd["launches"]}
+            "work_flop_per_launch": kd["work_flop"] / kd["launches"],
+            **({"mfma_flop_per_flop": 3, "mfma_frac": 3.0 * achieved / PEAK_TFLOPS[head]}
+               if head == "bf16x3" else {})}
 
 
 def _forms_summary(res):
@@ -339,6 +343,7 @@ def bench_single(args, torch, inst, backward=False):
                                          "wall_ms_per_step", "gflops",
                                          "abs_dE_Ha_vs_fp64", "meets_1e-6_Ha", "rel_dN_vs_fp64",
                                          "tuning", "E", "N")}
+                     | {"roofline": _roofline(r["kernels"], p, args.steps, args.workload, r["tuning"])}
                   for p, r in res.items()},
         "fastest_form": {"form": fastest, "ms_per_step": res[fastest]["ms_per_step"],
                          "gflops": res[fastest]["gflops"],

@@ -1684,8 +1684,8 @@ aims_status aims_xc(aims_grid* g, int32_t functional, const double* n, double* v
   return guarded(g, [&] {
     if (functional == AIMS_XC_PBE) fail(AIMS_ERR_UNSUPPORTED, "PBE needs the density gradient (aims_xc_gga)");
     if (functional != AIMS_XC_LDA_PW92) fail(AIMS_ERR_UNSUPPORTED, "unknown functional %d", functional);
-    require_device(n, "n");
-    require_device(v_xc_out, "v_xc_out");
+    require_device(n, "n", g->n_points > 0);
+    require_device(v_xc_out, "v_xc_out", g->n_points > 0);
     if (sums_out_or_null) require_device(sums_out_or_null, "sums_out");
     if (!g->d_xc_part) g->d_xc_part = (double*)g->alloc(2 * (size_t)kXcBlocks * g->n_sys * sizeof(double));
     hipchk(launch_lda(g->dens.dv, n, v_xc_out, g->d_xc_part, sums_out_or_null, g->stream), "xc");

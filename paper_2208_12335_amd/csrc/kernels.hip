@@ -8,6 +8,10 @@
 //   hs_kernel         per (batch, i-tile, j-tile): C = Phi^T (second operand)^T on MFMA over the
 //                     batch's points, scatter-added in FP64 into the dense H (or S)
 //   finish kernels    caller-order scatter of n and deterministic FP64 sums N, E_V, E_T
+//   pulay_kernel      backward: per (point, relevant atom), gradients of phi and t phi
+//                     contracted with X = Phi P_b and Y = (t Phi) P_b (both from the density
+//                     kernel in store mode) into the Pulay-type dE/dR_a
+//   dv_kernel         backward: dE/dv_p = gE w_p n_p in caller order
 //
 // Precision policies: FP64 (double slabs, v_mfma_f64_16x16x4f64), FP32 (float slabs,
 // v_mfma_f32_16x16x4f32), BF16x3 (bf16 hi/lo splits of FP32 values, three

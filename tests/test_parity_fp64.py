@@ -145,6 +145,15 @@ def test_empty_grid(gpu, c1):
     H, S = g.integrate_h(v, want_S=True)
     assert n.numel() == 0 and torch.count_nonzero(sums).item() == 0
     assert torch.count_nonzero(H).item() == 0 and torch.count_nonzero(S).item() == 0
+    # exchange-correlation on the empty grid: empty outputs, zero sums, zero gradient term
+    vx, sx = g.xc(n)
+    n2, grad = g.density_gradient(P)
+    vn, u, sg = g.xc_gga(n2, grad)
+    Hg = g.integrate_h_gga(v, u)
+    torch.cuda.synchronize()
+    assert vx.numel() == 0 and grad.numel() == 0 and u.numel() == 0
+    assert torch.count_nonzero(sx).item() == 0 and torch.count_nonzero(sg).item() == 0
+    assert torch.count_nonzero(Hg).item() == 0
 
 
 @pytest.mark.parametrize("merge,ratio", [(0, 0), (1, 0), (2, 0), (3, 0), (0, 64), (0, 4096)])
