@@ -96,11 +96,32 @@ void natural_spline(const double* y, int n, double h, double* coef /* [(n-1)][4]
   }
 }
 
-// Recursive median bisection along the longest bounding-box axis (ties broken by index).
-void bisect(const double* xyz, std::vector<int32_t>& idx, int64_t lo, int64_t hi, int maxb,
-            std::vector<std::pair<int64_t, int64_t>>& out) {
-  if (hi - lo <= maxb) {
-    if (hi > lo) out.emplace_back(lo, hi);
+// The batch tree of one system.  A node [lo, hi) of batch-ordered points carries a leaf count
+// L: the root's is the smallest power of two with L x max_batch >= n (the depth of a plain
+// median bisection), each child takes max(1, L / 2), and a node is a batch once L = 1 and it
+// holds at most max_batch points.  A node splits at its median, moved to the nearest multiple
+// of kPad points from lo once it holds at least 2 kPad points (both halves stay non-empty).
+// Left children are then multiples of kPad, so every batch of a system but its last fills
+// whole kPad-point slab rows: no padded point columns to evaluate, store or multiply.
+int64_t tree_leaves(int64_t n, int64_t maxb) {
+  int64_t L = 1;
+  while (L * maxb < n) L <<= 1;
+  return L;
+}
+
+int64_t split_point(int64_t lo, int64_t hi) {
+  const int64_t n = hi - lo;
+  int64_t h = n / 2;
+  if (n >= 2 * kPad) h = (h + kPad / 2) / kPad * kPad;
+  return lo + h;
+}
+
+// Recursive bisection along the longest bounding-box axis at split_point (ties broken by index).
+void bisect(const double* xyz, std::vector<int32_t>& idx, int64_t lo, int64_t hi, int64_t L,
+            int maxb, std::vector<std::pair<int64_t, int64_t>>& out) {
+  if (hi <= lo) return;
+  if (L <= 1 && hi - lo <= maxb) {
+    out.emplace_back(lo, hi);
     return;
   }
   double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
@@ -112,13 +133,14 @@ void bisect(const double* xyz, std::vector<int32_t>& idx, int64_t lo, int64_t hi
   int ax = 0;
   for (int c = 1; c < 3; ++c)
     if (mx[c] - mn[c] > mx[ax] - mn[ax]) ax = c;
-  const int64_t mid = lo + (hi - lo) / 2;
+  const int64_t mid = split_point(lo, hi);
   std::nth_element(idx.begin() + lo, idx.begin() + mid, idx.begin() + hi, [&](int32_t a, int32_t b) {
     const double ca = xyz[3 * (int64_t)a + ax], cb = xyz[3 * (int64_t)b + ax];
     return ca < cb || (ca == cb && a < b);
   });
-  bisect(xyz, idx, lo, mid, maxb, out);
-  bisect(xyz, idx, mid, hi, maxb, out);
+  const int64_t Lc = std::max<int64_t>(1, L / 2);
+  bisect(xyz, idx, lo, mid, Lc, maxb, out);
+  bisect(xyz, idx, mid, hi, Lc, maxb, out);
 }
 
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
@@ -370,18 +392,21 @@ size_t scratch_budget_elems() {
   return (size_t)(mb * 1024.0 * 1024.0 / 16.0);
 }
 
-// Segments of the batch-ordered points of one system at a given batch size: the same median
-// splits as the set-up bisection (mid = lo + (hi - lo) / 2), stopped once a segment holds at
-// most maxb points.  Because the set-up bisection already ordered the points, every segment is
-// a contiguous range.
-void segments(int64_t lo, int64_t hi, int64_t maxb, std::vector<std::pair<int64_t, int64_t>>& out) {
-  if (hi - lo <= maxb) {
-    if (hi > lo) out.emplace_back(lo, hi);
+// Segments of the batch-ordered points of one system: the nodes of its batch tree with leaf
+// count <= Lm holding at most Lm x maxb points (Lm = 1: the batches; Lm = 2^m: the tree
+// stopped m levels earlier).  Because the set-up bisection already ordered the points, every
+// segment is a contiguous range.
+void segments(int64_t lo, int64_t hi, int64_t L, int64_t maxb, int64_t Lm,
+              std::vector<std::pair<int64_t, int64_t>>& out) {
+  if (hi <= lo) return;
+  if (L <= Lm && hi - lo <= maxb * Lm) {
+    out.emplace_back(lo, hi);
     return;
   }
-  const int64_t mid = lo + (hi - lo) / 2;
-  segments(lo, mid, maxb, out);
-  segments(mid, hi, maxb, out);
+  const int64_t mid = split_point(lo, hi);
+  const int64_t Lc = std::max<int64_t>(1, L / 2);
+  segments(lo, mid, Lc, maxb, Lm, out);
+  segments(mid, hi, Lc, maxb, Lm, out);
 }
 
 // Cost-model partition of one system for the H pass.  Every node of the set-up bisection (a
@@ -397,17 +422,21 @@ struct NodeCost {
   std::vector<std::pair<int64_t, int64_t>> segs;      // chosen H batches of the subtree
 };
 
-NodeCost cost_partition(int64_t lo, int64_t hi, int64_t maxb, int64_t cap, double ratio,
+NodeCost cost_partition(int64_t lo, int64_t hi, int64_t L, int64_t maxb, int64_t cap, double ratio,
                         const std::map<int64_t, const std::vector<int32_t>*>& leaf_atoms,
                         const std::vector<int>& nfn) {
   NodeCost r;
-  if (hi - lo <= maxb) {
+  r.cost = 0.0;
+  if (hi <= lo) return r;
+  const bool leaf = L <= 1 && hi - lo <= maxb;
+  if (leaf) {
     auto it = leaf_atoms.find(lo);
     if (it != leaf_atoms.end()) r.atoms = *it->second;
   } else {
-    const int64_t mid = lo + (hi - lo) / 2;
-    NodeCost a = cost_partition(lo, mid, maxb, cap, ratio, leaf_atoms, nfn);
-    NodeCost b = cost_partition(mid, hi, maxb, cap, ratio, leaf_atoms, nfn);
+    const int64_t mid = split_point(lo, hi);
+    const int64_t Lc = std::max<int64_t>(1, L / 2);
+    NodeCost a = cost_partition(lo, mid, Lc, maxb, cap, ratio, leaf_atoms, nfn);
+    NodeCost b = cost_partition(mid, hi, Lc, maxb, cap, ratio, leaf_atoms, nfn);
     std::set_union(a.atoms.begin(), a.atoms.end(), b.atoms.begin(), b.atoms.end(),
                    std::back_inserter(r.atoms));
     r.cost = a.cost + b.cost;
@@ -417,7 +446,7 @@ NodeCost cost_partition(int64_t lo, int64_t hi, int64_t maxb, int64_t cap, doubl
   double nb = 0;
   for (int32_t at : r.atoms) nb += nfn[at];
   const double own = 2.0 * (double)(hi - lo) * nb * nb + ratio * nb * nb;
-  if (hi - lo <= maxb || (hi - lo <= cap && own <= r.cost)) {
+  if (leaf || (hi - lo <= cap && own <= r.cost)) {
     r.cost = own;
     r.segs.assign(1, {lo, hi});
   }
@@ -448,9 +477,11 @@ void build_set(aims_grid* g, BatchSet& bs, int merge, bool density, int ratio = 
         leaf_atoms[d.pt_off] = &leaf_lists.back();
       }
       const int64_t maxb = g->sys_max_batch[k];
-      segs = cost_partition(base, end, maxb, maxb << 4, (double)ratio, leaf_atoms, g->atom_nfn[k]).segs;
+      segs = cost_partition(base, end, tree_leaves(end - base, maxb), maxb, maxb << 4, (double)ratio,
+                            leaf_atoms, g->atom_nfn[k]).segs;
     } else {
-      segments(base, end, (int64_t)g->sys_max_batch[k] << merge, segs);
+      const int64_t maxb = g->sys_max_batch[k];
+      segments(base, end, tree_leaves(end - base, maxb), maxb, (int64_t)1 << merge, segs);
     }
     const int nseg = (int)segs.size();
     const int a0 = g->systems[k].atom_off;
@@ -719,7 +750,7 @@ aims_grid* build(const aims_system* sys, int n_sys, int device, void* stream) {
     std::vector<int32_t> idx(s.n_points);
     for (int64_t i = 0; i < s.n_points; ++i) idx[i] = (int32_t)i;
     std::vector<std::pair<int64_t, int64_t>> segs;
-    bisect(s.pt_xyz, idx, 0, s.n_points, s.max_batch, segs);
+    bisect(s.pt_xyz, idx, 0, s.n_points, tree_leaves(s.n_points, s.max_batch), s.max_batch, segs);
     g->sys_pt_range.push_back((int64_t)g->pts_sorted.size());
     for (int64_t i = 0; i < s.n_points; ++i) {
       const int32_t q = idx[i];
