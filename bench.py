@@ -113,10 +113,11 @@ def _kernels(g, steps):
     return out
 
 
-def _measured_traffic(workload, form, family, tuning):
+def _measured_traffic(workload, form, family, tuning, flop_per_step=None):
     """HBM bytes per launch of the dominant kernel from the committed profiler summary (two
     rocprofv3 --pmc passes, FETCH_SIZE and WRITE_SIZE, scaled by a plain copy kernel), used only
-    when that summary was taken on the same kernel source, workload, form and tuning."""
+    when that summary was taken on the same kernel source, workload (and batching: the same
+    algorithmic flops per step), form and tuning."""
     import hashlib
     try:
         text = open(TRAFFIC_FILE).read()
@@ -127,12 +128,12 @@ def _measured_traffic(workload, form, family, tuning):
     for rec in recs:
         if (rec.get("kernels_sha256") == sha and rec.get("workload") == workload and
                 rec.get("form") == form and rec.get("family") == family and
-                rec.get("tuning") == tuning):
+                rec.get("tuning") == tuning and rec.get("flop_per_step") == flop_per_step):
             return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
     return None
 
 
-def _roofline(kern, head, steps, workload=None, tuning=None):
+def _roofline(kern, head, steps, workload=None, tuning=None, flop_per_step=None):
     dom = max(("density", "hs"), key=lambda k: kern.get(k, {}).get("ms_per_step", 0.0))
     kd = kern[dom]
     # algorithmic flops: 2 sum n_p n_b^2 over the density partition.  A merged H partition
@@ -145,7 +146,7 @@ def _roofline(kern, head, steps, workload=None, tuning=None):
     achieved = work / (kd["ms_per_step"] * steps * 1e-3) / 1e12
     return {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[head],
             "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[head],
-            "traffic": _measured_traffic(workload, head, dom, tuning),
+            "traffic": _measured_traffic(workload, head, dom, tuning, flop_per_step),
             "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
             "avg_launch_ms": kd["avg_launch_ms"], "launches_per_step": kd["launches"] / steps,
             "work_flop_per_launch": work / kd["launches"],
@@ -353,7 +354,7 @@ def bench_single(args, torch, inst, backward=False):
                                          "wall_ms_per_step", "gflops",
                                          "abs_dE_Ha_vs_fp64", "meets_1e-6_Ha", "rel_dN_vs_fp64",
                                          "tuning", "E", "N")}
-                     | {"roofline": _roofline(r["kernels"], p, args.steps, args.workload, r["tuning"])}
+                     | {"roofline": _roofline(r["kernels"], p, args.steps, args.workload, r["tuning"], F)}
                   for p, r in res.items()},
         "fastest_form": {"form": fastest, "ms_per_step": res[fastest]["ms_per_step"],
                          "gflops": res[fastest]["gflops"],
@@ -361,7 +362,7 @@ def bench_single(args, torch, inst, backward=False):
         "kernels": {p: r["kernels"] for p, r in res.items()},
         "autotuned": {p: (p not in fixed and not args.no_autotune) for p in forms},
         "outside_step": outside,
-        "roofline": _roofline(hr["kernels"], head, args.steps, args.workload, hr["tuning"]),
+        "roofline": _roofline(hr["kernels"], head, args.steps, args.workload, hr["tuning"], F),
     }
     if args.cpu_chunks > 0:
         _log("CPU baseline (oracle sample)...")

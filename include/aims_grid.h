@@ -92,8 +92,8 @@ typedef struct {
 
 /* Builds the splines (FP64 and FP32 copies), partitions the points into batches by recursive
  * bisection along the longest bounding-box axis until each holds <= max_batch points (a node of
- * 64 or more points splits at its median rounded to a multiple of 32 points, so that every batch
- * of a system but its last holds a multiple of 32 points),
+ * 128 or more points splits at its median rounded to a multiple of 64 points, so that every
+ * batch of a system but its last holds a multiple of 64 points),
  * keeps per batch the atoms closer than rc + screen_margin to at least one of its points (and
  * so every basis function that can be nonzero on it), and uploads everything to `device`.
  * `hip_stream` (a hipStream_t, NULL = default stream) is used by every later call.

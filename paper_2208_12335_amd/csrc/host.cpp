@@ -100,9 +100,11 @@ void natural_spline(const double* y, int n, double h, double* coef /* [(n-1)][4]
 // L: the root's is the smallest power of two with L x max_batch >= n (the depth of a plain
 // median bisection), each child takes max(1, L / 2), and a node is a batch once L = 1 and it
 // holds at most max_batch points.  A node splits at its median, moved to the nearest multiple
-// of kPad points from lo once it holds at least 2 kPad points (both halves stay non-empty).
-// Left children are then multiples of kPad, so every batch of a system but its last fills
-// whole kPad-point slab rows: no padded point columns to evaluate, store or multiply.
+// of kSplit points from lo once it holds at least 2 kSplit points (both halves stay non-empty).
+// Left children are then multiples of kSplit, so every batch of a system but its last fills
+// whole slab rows (kPad points) and whole 64-point FP64 density tiles: no padded point columns
+// to evaluate, store or multiply.
+constexpr int64_t kSplit = 2 * kPad;
 int64_t tree_leaves(int64_t n, int64_t maxb) {
   int64_t L = 1;
   while (L * maxb < n) L <<= 1;
@@ -112,7 +114,7 @@ int64_t tree_leaves(int64_t n, int64_t maxb) {
 int64_t split_point(int64_t lo, int64_t hi) {
   const int64_t n = hi - lo;
   int64_t h = n / 2;
-  if (n >= 2 * kPad) h = (h + kPad / 2) / kPad * kPad;
+  if (n >= 2 * kSplit) h = (h + kSplit / 2) / kSplit * kSplit;
   return lo + h;
 }
 
