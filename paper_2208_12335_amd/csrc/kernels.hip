@@ -151,10 +151,10 @@ __device__ __forceinline__ void eval_atom_point(double dx, double dy, double dz,
 }
 
 // Basis values of one batch: kPhiSlices workgroups of four waves per batch; workgroup s takes
-// the batch's relevant atoms s, s + kPhiSlices, ..., and its four waves take the points
-// 64 w + lane (+ 256 ...) of the same atom together, so that each slab row (one function, the
-// batch's padded points) is written in one burst by the workgroup (measured faster than one
-// wave sweeping a row in four separate chunks).  The atom is workgroup-uniform, so the species,
+// the batch's relevant atoms s, s + kPhiSlices, ...  Its waves take (atom, 64-point chunk)
+// pairs in turn, chunk-minor, so every wave has work whatever the batch's point count (a
+// 128-point batch keeps all four waves on two atoms) and the waves that share an atom write
+// its slab rows together, in one burst per row.  The atom is wave-uniform, so the species,
 // shell and table addressing is scalar; lanes past the batch's points write the zero padding
 // of the atom's rows.
 constexpr int kPhiSlices = 4;
@@ -177,12 +177,17 @@ phi_eval_kernel(const BatchDesc* __restrict__ batches, int b0, const double4* __
   typedef typename std::conditional<LAYOUT == kLayoutDense, T, bf16_t>::type S;
   const int64_t off = (LAYOUT == kLayoutDense ? 1 : 2) * d.slab_off;
   SlabStore<T, LAYOUT> store{(S*)slab1 + off, (S*)slab2 + off, ldp};
-  for (int k = slice; k < na; k += kPhiSlices) {
+  const int nc = (ldp + 63) / 64;                               // 64-point chunks per row
+  const int nk = (na - slice + kPhiSlices - 1) / kPhiSlices;    // this workgroup's atoms
+  for (int q = wq; q < nk * nc; q += 4) {
+    const int j = q / nc, c = q - j * nc;
+    const int k = slice + j * kPhiSlices;
     const int atom = batch_atoms[d.atom_off + k];
     const int col0 = batch_acol[d.atom_off + k];
     const SpeciesDesc sd = species[atom_species[atom]];
     const double ax = atom_xyz[3 * atom], ay = atom_xyz[3 * atom + 1], az = atom_xyz[3 * atom + 2];
-    for (int p = 64 * wq + lane; p < ldp; p += 256) {
+    const int p = 64 * c + lane;
+    if (p < ldp) {
       if (p < np) {
         const double4 P4 = pts[d.pt_off + p];
         double wv = 0.0;
