@@ -207,7 +207,7 @@ def bench_single(args, torch, inst, backward=False):
         elif not args.no_autotune:
             t0 = time.time()
             r = autotune(g, P, v, prec=prec, reps=2, cache="")   # measured here, never cached
-            _log(f"{prec}: autotuned {dict((k, r[k]) for k in ('h_merge', 'density_pblocks', 'persistent'))}"
+            _log(f"{prec}: autotuned {dict((k, r[k]) for k in ('h_merge', 'density_pblocks', 'persistent', 'h_flops_per_atomic') if k in r)}"
                  f" ({time.time() - t0:.1f} s)")
 
         if backward:

@@ -35,7 +35,7 @@
  * happens on the host before any launch, and aims_last_error() holds the message.
  *
  * Environment (read at setup): AIMS_SCRATCH_MB sets the scratch budget that bounds a group of
- * batches (default 4096, minimum 16); AIMS_H_MERGE sets the initial h_merge of every precision
+ * batches (default 8192, minimum 16); AIMS_H_MERGE sets the initial h_merge of every precision
  * (0..4); AIMS_FAIL_ALLOC=1 makes every device allocation fail with AIMS_ERR_OOM (to test the
  * error path); AIMS_FORCES_THREAD_PATH=1 makes aims_total_forces use its thread-per-point kernel
  * (otherwise taken only above 512 atoms per system) for every system size.

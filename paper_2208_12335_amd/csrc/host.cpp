@@ -387,9 +387,10 @@ void validate_system(const aims_system* s, int k) {
 }
 
 size_t scratch_budget_elems() {
-  // elements per slab (two slabs); 4 GiB total in FP64 by default: fewer, larger groups
-  // (fewer launch tails) measured faster than 1 GiB or less, and 288 GB leaves room for it
-  double mb = 4096.0;
+  // elements per slab (two slabs); 8 GiB total in FP64 by default: fewer, larger groups
+  // (fewer launch tails) measured faster, the gain levelling off once a 1.1M-point, 1445-function
+  // step fits one group (8 GiB), and 288 GB leaves room for it
+  double mb = 8192.0;
   if (const char* e = getenv("AIMS_SCRATCH_MB")) mb = std::max(16.0, atof(e));
   return (size_t)(mb * 1024.0 * 1024.0 / 16.0);
 }
