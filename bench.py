@@ -26,6 +26,7 @@ import time
 import numpy as np
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}   # MI355X dense MFMA peaks
+SINGLE_SCRATCH_MB = 512     # scratch budget of each per-molecule baseline handle (c4)
 HERE = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "tiled_kernels_c2_fp64_hbm_traffic.md")
 KERNEL_SRC = os.path.join(HERE, "paper_2208_12335_amd", "csrc", "kernels.hip")
@@ -414,12 +415,17 @@ def bench_grouped(args, torch, mols):
         E_graph = sums.cpu().numpy().copy()
     _log(f"grouped eager {ms_eager:.3f} ms, graph {ms_graph:.3f} ms")
 
-    # per-molecule baseline: one handle and one launch set per molecule on the same stream
+    # per-molecule baseline: one handle and one launch set per molecule on the same stream.
+    # Each handle sizes its own scratch to its molecule, and 256 such scratches at the default
+    # budget would not fit HBM together, so the baseline handles take a bounded budget.
     singles = []
     tg = g.get_tuning(prec)
+    scratch_env = os.environ.get("AIMS_SCRATCH_MB")
+    os.environ["AIMS_SCRATCH_MB"] = str(SINGLE_SCRATCH_MB)
     for m in mols:
         gm = AimsGrid(m, device=0, stream=stream)
-        gm.set_tuning(h_merge=tg["h_merge"], density_pblocks=tg["density_pblocks"], prec=prec)
+        gm.set_tuning(h_merge=tg["h_merge"], density_pblocks=tg["density_pblocks"], prec=prec,
+                      h_flops_per_atomic=tg["h_flops_per_atomic"])
         Pm = torch.from_numpy(m.P).to(dev).reshape(-1)
         vm = torch.from_numpy(m.v).to(dev)
         nm = torch.empty(gm.n_points, dtype=torch.float64, device=dev)
@@ -435,6 +441,10 @@ def bench_grouped(args, torch, mols):
 
     with torch.cuda.stream(stream):
         ms_single, wall_single = timer.run(per_molecule, args.steps, args.warmup)
+    if scratch_env is None:
+        del os.environ["AIMS_SCRATCH_MB"]
+    else:
+        os.environ["AIMS_SCRATCH_MB"] = scratch_env
     E_single = np.stack([s[4].cpu().numpy()[0] for s in singles])
     _log(f"per-molecule {ms_single:.3f} ms (wall {wall_single:.3f} ms)")
     dE = float(np.max(np.abs((E_graph[:, 1] + E_graph[:, 2]) - (E_single[:, 1] + E_single[:, 2]))))
@@ -452,6 +462,7 @@ def bench_grouped(args, torch, mols):
         "modes": {"graph": {"ms_per_step": ms_graph, "wall_ms_per_step": wall_graph},
                   "eager_grouped": {"ms_per_step": ms_eager, "wall_ms_per_step": wall_eager},
                   "per_molecule": {"ms_per_step": ms_single, "wall_ms_per_step": wall_single,
+                                   "scratch_mb_per_handle": SINGLE_SCRATCH_MB,
                                    "molecules_per_s": nmol / (ms_single * 1e-3)}},
         "speedup_graph_vs_per_molecule": ms_single / ms_graph,
         "max_abs_dE_Ha_grouped_vs_per_molecule": dE,

@@ -34,11 +34,14 @@
  * two threads at once.  Errors: every call returns an aims_status; all argument validation
  * happens on the host before any launch, and aims_last_error() holds the message.
  *
- * Environment (read at setup): AIMS_SCRATCH_MB sets the scratch budget that bounds a group of
- * batches (default 8192, minimum 16); AIMS_H_MERGE sets the initial h_merge of every precision
- * (0..4); AIMS_FAIL_ALLOC=1 makes every device allocation fail with AIMS_ERR_OOM (to test the
- * error path); AIMS_FORCES_THREAD_PATH=1 makes aims_total_forces use its thread-per-point kernel
- * (otherwise taken only above 512 atoms per system) for every system size.
+ * Environment: AIMS_SCRATCH_MB sets the scratch budget that bounds a group of batches (default
+ * 8192, minimum 16; read whenever a batch partition is built: at setup, and at the first call
+ * with a new H partition).  A handle's scratch grows to the largest group it has needed; a
+ * smaller scratch it outgrows is released unless a step graph has been captured on the handle.
+ * Read at setup: AIMS_H_MERGE sets the initial h_merge of every precision (0..4);
+ * AIMS_FORCES_THREAD_PATH=1 makes aims_total_forces use its thread-per-point kernel (otherwise
+ * taken only above 512 atoms per system) for every system size.  Read at every device
+ * allocation: AIMS_FAIL_ALLOC=1 makes it fail with AIMS_ERR_OOM (to test the error path).
  */
 #ifndef AIMS_GRID_H
 #define AIMS_GRID_H

@@ -238,6 +238,7 @@ struct aims_grid {
     double work;
   };
   bool profiling = false;
+  bool graph_captured = false;        // a step graph may reference the current scratch
   std::vector<ProfRec> prof_pending;
   int64_t prof_count[5] = {0, 0, 0, 0, 0};
   double prof_ms[5] = {0, 0, 0, 0, 0};
@@ -583,8 +584,17 @@ void build_set(aims_grid* g, BatchSet& bs, int merge, bool density, int ratio = 
   bs.dv.batch_cols = g->upload(bs.batch_cols);
   bs.dv.sys_batch_range = g->upload(bs.sys_batch_range);
   if (bs.slab_elems > g->slab_cap) {
-    // the smaller scratch stays allocated until the handle is destroyed: a step graph captured
-    // earlier may still reference it
+    // A step graph captured earlier may still reference the smaller scratch, so it then stays
+    // allocated until the handle is destroyed (as it does while the stream is being captured).
+    // Otherwise it is released, once the stream has drained, before the larger one is taken.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (g->stream) hipchk(hipStreamIsCapturing(g->stream, &cap), "capture status");
+    if (!g->graph_captured && cap == hipStreamCaptureStatusNone && g->d_slab1) {
+      hipchk(hipStreamSynchronize(g->stream), "synchronize before releasing scratch");
+      g->release(g->d_slab1);
+      g->release(g->d_slab2);
+      g->d_slab1 = g->d_slab2 = nullptr;
+    }
     g->slab_cap = 0;
     g->d_slab1 = g->alloc(bs.slab_elems * sizeof(double));
     g->d_slab2 = g->alloc(bs.slab_elems * sizeof(double));
@@ -1748,6 +1758,7 @@ aims_status aims_step_graph_create(aims_grid* g, aims_precision prec, const doub
     if (g->profiling) fail(AIMS_ERR_ARG, "disable profiling before capturing a step graph");
     std::unique_ptr<aims_step_graph> sg(new aims_step_graph());
     sg->stream = g->stream;
+    g->graph_captured = true;
     hipchk(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal), "begin capture");
     try {
       density_call(g, prec, P, v, n_out, sums_out);
