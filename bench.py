@@ -30,6 +30,7 @@ SINGLE_SCRATCH_MB = 512     # scratch budget of each per-molecule baseline handl
 HERE = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "tiled_kernels_c2_fp64_hbm_traffic.md")
 KERNEL_SRC = os.path.join(HERE, "paper_2208_12335_amd", "csrc", "kernels.hip")
+HOST_SRC = os.path.join(HERE, "paper_2208_12335_amd", "csrc", "host.cpp")     # batch partitions
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}
 FAMILIES = ("phi_eval", "density", "hs", "backward", "finish")
 
@@ -117,17 +118,18 @@ def _kernels(g, steps):
 def _measured_traffic(workload, form, family, tuning, flop_per_step=None):
     """HBM bytes per launch of the dominant kernel from the committed profiler summary (two
     rocprofv3 --pmc passes, FETCH_SIZE and WRITE_SIZE, scaled by a plain copy kernel), used only
-    when that summary was taken on the same kernel source, workload (and batching: the same
-    algorithmic flops per step), form and tuning."""
+    when that summary was taken on the same kernel and partitioning sources (kernels.hip and
+    host.cpp), workload (and batching: the same algorithmic flops per step), form and
+    tuning."""
     import hashlib
     try:
         text = open(TRAFFIC_FILE).read()
         recs = [json.loads(l) for l in text.splitlines() if l.startswith("{")]
-        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read() + open(HOST_SRC, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return None
     for rec in recs:
-        if (rec.get("kernels_sha256") == sha and rec.get("workload") == workload and
+        if (rec.get("sources_sha256") == sha and rec.get("workload") == workload and
                 rec.get("form") == form and rec.get("family") == family and
                 rec.get("tuning") == tuning and rec.get("flop_per_step") == flop_per_step):
             return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]

@@ -289,7 +289,7 @@ void aims_step_graph_destroy(aims_step_graph *graph);
  *                    ceil(n_p / (32 density_pblocks)) equal tiles.
  *   h_flops_per_atomic  0: the H/S batches are the fixed merge level above; R > 0: a cost
  *                    model chooses them (h_merge is then ignored): each node of the set-up
- *                    bisection, up to 16 x max_batch points, becomes one H batch when
+ *                    bisection, up to 4 x max_batch points, becomes one H batch when
  *                    2 n_p n_b^2 + R n_b^2 (flops plus R flop-equivalents per FP64 scatter-add)
  *                    is below the best cost of its two halves.  0..2^20.
  *   persistent       0: one workgroup per work tile (hardware dispatch order, XCD-interleaved);

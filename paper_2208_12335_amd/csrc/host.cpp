@@ -414,7 +414,7 @@ void segments(int64_t lo, int64_t hi, int64_t L, int64_t maxb, int64_t Lm,
 }
 
 // Cost-model partition of one system for the H pass.  Every node of the set-up bisection (a
-// contiguous point range) may become one H batch of up to 16 x max_batch points; its relevant
+// contiguous point range) may become one H batch of up to 4 x max_batch points; its relevant
 // atoms are the union of its children's (an atom is relevant to a range iff it is relevant to
 // one of its points), so the density batches' exact screening gives every node's basis size
 // n_b.  A node of n points costs 2 n n_b^2 flops plus `ratio` flop-equivalents for each of its
@@ -481,7 +481,7 @@ void build_set(aims_grid* g, BatchSet& bs, int merge, bool density, int ratio = 
         leaf_atoms[d.pt_off] = &leaf_lists.back();
       }
       const int64_t maxb = g->sys_max_batch[k];
-      segs = cost_partition(base, end, tree_leaves(end - base, maxb), maxb, maxb << 4, (double)ratio,
+      segs = cost_partition(base, end, tree_leaves(end - base, maxb), maxb, maxb << 2, (double)ratio,
                             leaf_atoms, g->atom_nfn[k]).segs;
     } else {
       const int64_t maxb = g->sys_max_batch[k];

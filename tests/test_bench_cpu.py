@@ -1,7 +1,7 @@
 """Host-side logic of bench.py, on the CPU: the roofline of the dominant kernel credits
 algorithmic flops only (a merged H partition's surplus is stated, not credited), every form
-carries its own roofline, and a stored traffic record is used only for the exact kernel source,
-workload, batching, form, family and tuning it was measured on."""
+carries its own roofline, and a stored traffic record is used only for the exact kernel and
+partitioning sources, workload, batching, form, family and tuning it was measured on."""
 import json
 import os
 import subprocess
@@ -45,16 +45,19 @@ def test_bf16x3_states_the_mfma_fraction():
 def test_traffic_record_matching(tmp_path, monkeypatch):
     src = tmp_path / "k.hip"
     src.write_text("kernel source")
+    host = tmp_path / "h.cpp"
+    host.write_text("partition source")
     import hashlib
-    sha = hashlib.sha256(src.read_bytes()).hexdigest()
+    sha = hashlib.sha256(src.read_bytes() + host.read_bytes()).hexdigest()
     rec = {"workload": "c2", "form": "fp64", "family": "hs", "tuning": TUNING,
-           "fetch_bytes_per_launch": 5, "write_bytes_per_launch": 2, "kernels_sha256": sha,
+           "fetch_bytes_per_launch": 5, "write_bytes_per_launch": 2, "sources_sha256": sha,
            "flop_per_step": 7.3e11}
     other = dict(rec, family="density", fetch_bytes_per_launch=100)
     f = tmp_path / "t.md"
     f.write_text("# summary\n\n" + json.dumps(other) + "\n" + json.dumps(rec) + "\n")
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
     monkeypatch.setattr(bench, "KERNEL_SRC", str(src))
+    monkeypatch.setattr(bench, "HOST_SRC", str(host))
     assert bench._measured_traffic("c2", "fp64", "hs", TUNING, 7.3e11) == 7
     assert bench._measured_traffic("c2", "fp64", "density", TUNING, 7.3e11) == 102
     # any mismatch: no traffic
@@ -62,8 +65,11 @@ def test_traffic_record_matching(tmp_path, monkeypatch):
     assert bench._measured_traffic("c3", "fp64", "hs", TUNING, 7.3e11) is None      # workload
     assert bench._measured_traffic("c2", "fp32", "hs", TUNING, 7.3e11) is None      # form
     assert bench._measured_traffic("c2", "fp64", "hs", dict(TUNING, h_merge=2), 7.3e11) is None
+    host.write_text("changed partition source")
+    assert bench._measured_traffic("c2", "fp64", "hs", TUNING, 7.3e11) is None      # partitions
+    host.write_text("partition source")
     src.write_text("changed kernel source")
-    assert bench._measured_traffic("c2", "fp64", "hs", TUNING, 7.3e11) is None      # source
+    assert bench._measured_traffic("c2", "fp64", "hs", TUNING, 7.3e11) is None      # kernels
 
 
 def test_more_than_one_gpu_is_refused():
