@@ -114,20 +114,29 @@ def vector_term(oracle, u: np.ndarray, chunk: int = 4096) -> np.ndarray:
 PBE = dict(kappa=0.804, beta=0.06672455060314922)
 
 
-def _pbe_f_torch(n, sigma):
+def _pbe_H_torch(n, sigma, ec):
+    """(H, t^2): the gradient correction of the PBE correlation energy per electron, and the
+    reduced gradient t^2 = sigma / (4 k_s^2 n^2) it is a function of (with eps_c = ec)."""
     import torch
-    kappa, beta = PBE["kappa"], PBE["beta"]
-    mu = beta * math.pi ** 2 / 3.0
+    beta = PBE["beta"]
     gamma = (1.0 - math.log(2.0)) / math.pi ** 2
-    ex, ec = _eps_xc_torch(n)
     kF = (3.0 * math.pi ** 2 * n) ** (1.0 / 3.0)
-    s2 = sigma / (4.0 * kF * kF * n * n)
-    Fx = 1.0 + kappa - kappa / (1.0 + mu * s2 / kappa)
     ks2 = 4.0 * kF / math.pi
     t2 = sigma / (4.0 * ks2 * n * n)
     A = (beta / gamma) / torch.expm1(-ec / gamma)
     At2 = A * t2
     H = gamma * torch.log1p((beta / gamma) * t2 * (1.0 + At2) / (1.0 + At2 + At2 * At2))
+    return H, t2
+
+
+def _pbe_f_torch(n, sigma):
+    kappa, beta = PBE["kappa"], PBE["beta"]
+    mu = beta * math.pi ** 2 / 3.0
+    ex, ec = _eps_xc_torch(n)
+    kF = (3.0 * math.pi ** 2 * n) ** (1.0 / 3.0)
+    s2 = sigma / (4.0 * kF * kF * n * n)
+    Fx = 1.0 + kappa - kappa / (1.0 + mu * s2 / kappa)
+    H, _ = _pbe_H_torch(n, sigma, ec)
     return n * ex * Fx + n * (ec + H)
 
 

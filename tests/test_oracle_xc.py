@@ -32,6 +32,73 @@ def test_pw92_high_density_limit():
     assert abs(const + 0.0466) < 3e-4
 
 
+def _ec_at_rs(rs):
+    """PW92 eps_c straight from the oracle's energy-density routine (no density cutoff), so that
+    its limits can be taken at any rs."""
+    import torch
+    from oracle.xc import _eps_xc_torch
+    rs = torch.as_tensor(np.asarray(rs, dtype=np.float64))
+    return _eps_xc_torch(3.0 / (4.0 * math.pi * rs ** 3))[1].numpy()
+
+
+def _high_density_fit():
+    """Least-squares fit of eps_c(rs) - c0 ln rs = -c1 + a x + c2' x^2 ln x^2 + c3' x^2, x = rs^(1/2),
+    on x in [1e-7, 3.2e-6], where the terms left out are below 1e-18."""
+    x = 1e-7 * 2.0 ** np.arange(6)
+    g = _ec_at_rs(x * x) - 0.031091 * np.log(x * x)
+    X = np.stack([np.ones_like(x), x, x * x * np.log(x * x), x * x], 1)
+    sol, *_ = np.linalg.lstsq(X, g, rcond=None)
+    return sol
+
+
+def test_pw92_second_order_constant_pins_b1():
+    """The constant term of the high-density expansion eps_c = c0 ln rs - c1 + ... is fixed by
+    b1 alone (c1 = -2 A ln(2 A b1)); Perdew and Wang's table gives c1 = 0.046644.  The bar of
+    1e-6 holds b1 to +-1.2e-4: a slip in any of its first four digits fails, and the fifth is
+    the published value's last (rounded) digit."""
+    c1 = -_high_density_fit()[0]
+    assert abs(c1 - 0.046644) < 1e-6, c1
+
+
+def test_pw92_no_half_order_term_pins_b2():
+    """The exact high-density expansion has no rs^(1/2) term.  In the PW92 form its coefficient is
+    2 A (b2 - 2 A b1^2) / b1, so b2 is tied to b1; the published (rounded) constants leave
+    2.5e-7, and a change of one unit in b2's last digit moves it to 1.07e-6 or -5.7e-7."""
+    a = _high_density_fit()[1]
+    assert abs(a) < 4e-7, a
+
+
+def test_pw92_low_density_coefficients():
+    """eps_c = -d0 / rs + d1 / rs^(3/2) + O(1/rs^2) for rs -> infinity, with d0 = a1 / b4 and
+    d1 = a1 b3 / b4^2 in the PW92 form; the published values are d0 = 0.4335, d1 = 1.4408.
+    Fitted on rs in [1e10, 1.6e11], where the O(rs^-2) term is below 1e-20 of eps_c."""
+    rs = np.array([1e10, 4e10, 16e10])
+    f = _ec_at_rs(rs) * rs
+    X = np.stack([np.ones_like(rs), rs ** -0.5, 1.0 / rs], 1)
+    d0, d1, _ = np.linalg.solve(X, f)
+    assert abs(-d0 - 0.4335) < 5e-5, d0
+    assert abs(d1 - 1.4408) < 1e-4, d1
+
+
+def test_pbe_beta_is_the_high_density_gradient_coefficient():
+    """PBE's H(rs, t) -> beta t^2 for t -> 0, and beta is defined as nu C_c(0): the gradient
+    coefficient of the correlation energy in the high-density limit, C_c(0) = 0.004235 (Ma and
+    Brueckner, as used by Perdew, Burke and Ernzerhof), times nu = (16/pi)(3 pi^2)^(1/3).  The bar
+    of 8e-6 is nu times the half unit of C_c(0)'s last digit.  The t^2 coefficient is read at
+    t^2 = 1e-10 (the next term is of order t^4)."""
+    import torch
+    from oracle.xc import _eps_xc_torch, _pbe_H_torch
+    nu = 16.0 / math.pi * (3.0 * math.pi ** 2) ** (1.0 / 3.0)
+    for n0 in (1e2, 1e6):
+        n = torch.tensor([n0], dtype=torch.float64)
+        kF = (3.0 * math.pi ** 2 * n0) ** (1.0 / 3.0)
+        ks2 = 4.0 * kF / math.pi
+        sigma = torch.tensor([1e-10 * 4.0 * ks2 * n0 * n0], dtype=torch.float64)
+        H, t2 = _pbe_H_torch(n, sigma, _eps_xc_torch(n)[1])
+        beta = (H / t2).item()
+        assert abs(beta - nu * 0.004235) < nu * 5e-7, beta
+
+
 def test_pw92_low_density_limit():
     # Wigner: eps_c ~ -0.44 / rs for rs -> infinity (rs = 2e4 keeps n above the cutoff; the
     # next term of the parametrisation is still ~2% there)
