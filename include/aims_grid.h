@@ -124,6 +124,21 @@ aims_status aims_update_density(aims_grid *g, aims_precision prec, const double 
                                 const double *P, const double *v_or_null, double *n_out,
                                 double *sums_out);
 
+/* Allocation-free density update, for callers that cannot allocate device memory during the
+ * call (code under stream capture, tight serving loops, hosts that forbid allocation): the
+ * same result as aims_update_density with atom_xyz = NULL, computed by the same kernels, and no
+ * hipMalloc, hipFree or allocating library routine inside the call.  The basis slabs of the
+ * batches live in one static device array of 64 MiB (32 MiB per slab), held by every GPU the
+ * library runs on until the process ends; the batches are processed in as many groups as that
+ * takes.  AIMS_ERR_UNSUPPORTED if a single batch needs more than 32 MiB per slab (more than
+ * 4M FP64 values: n_b rounded up to 32 times the batch's padded point count).  Every call on
+ * one GPU shares that array, so calls that overlap on one GPU (other streams, other handles,
+ * other host threads) race: the caller serialises them.  Positions are those of setup: a
+ * handle moved by an earlier call is first restored, as with atom_xyz = NULL.  Arguments as
+ * for aims_update_density. */
+aims_status aims_update_density_noalloc(aims_grid *g, aims_precision prec, const double *P,
+                                        const double *v_or_null, double *n_out, double *sums_out);
+
 /* Hamiltonian (and optionally overlap) integration: H_ij = sum_p w_p phi_i (v_p phi_j + tphi_j)
  * (raw: not symmetrised), S_ij = sum_p w_p phi_i phi_j.  v: DEVICE [n_points].  H, S_or_null:
  * DEVICE FP64 [nb][nb] row-major, overwritten. */

@@ -58,6 +58,7 @@ SIGNATURES = {
     "aims_grid_setup": (c_int, [POINTER(AimsSystem), c_int, c_void_p, POINTER(c_void_p)]),
     "aims_grid_setup_many": (c_int, [POINTER(AimsSystem), c_int32, c_int, c_void_p, POINTER(c_void_p)]),
     "aims_update_density": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "aims_update_density_noalloc": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
     "aims_integrate_h": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
     "aims_integrate_h_backward": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
                                           c_void_p, c_void_p, c_void_p]),

@@ -13,6 +13,7 @@
 #include <cstring>
 #include <functional>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -29,6 +30,14 @@ using namespace aims;
 namespace {
 
 thread_local std::string g_setup_error = "no error";
+
+// Scratch of the allocation-free density update (aims_update_density_noalloc): the two basis
+// slabs of one group of batches, in a static device array that every GPU the library runs on
+// holds until the process ends.  Host code never passes the array's name to a kernel (in host
+// code it names a host-side stand-in); it uses the device address that hipGetSymbolAddress
+// returns, taken once per device at set-up with that device current.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
 // ---------------------------------------------------------------------------------------------
 // small utilities
@@ -222,6 +231,9 @@ struct aims_grid {
   std::vector<double4> pts_sorted;            // host copy of the batch-ordered points
 
   BatchSet dens;                              // density partition (merge 0)
+  BatchSet dens_na;                           // the same batches grouped for the static scratch
+  void* na_scratch = nullptr;                 // device address of `scratch` on this handle's device
+  std::string na_error;                       // non-empty: the static scratch cannot hold a batch
   std::vector<std::unique_ptr<BatchSet>> hsets;  // H partitions by merge level (built on demand)
   int h_merge[3] = {1, 2, 2};                 // per precision
   int h_ratio[3] = {0, 0, 0};                 // per precision: > 0 selects the cost-model H partition
@@ -457,6 +469,9 @@ NodeCost cost_partition(int64_t lo, int64_t hi, int64_t L, int64_t maxb, int64_t
   return r;
 }
 
+size_t form_groups(BatchSet& bs, size_t budget);
+void upload_set(aims_grid* g, BatchSet& bs);
+
 void build_set(aims_grid* g, BatchSet& bs, int merge, bool density, int ratio = 0) {
   bs.merge = merge;
   bs.ratio = ratio;
@@ -547,8 +562,24 @@ void build_set(aims_grid* g, BatchSet& bs, int merge, bool density, int ratio = 
   }
   if ((int64_t)bs.batch_cols.size() > (int64_t)INT32_MAX) fail(AIMS_ERR_UNSUPPORTED, "too many batch columns");
 
-  // groups of batches sharing the scratch
-  const size_t budget = scratch_budget_elems();
+  form_groups(bs, scratch_budget_elems());
+  // batch range of each system (batches are in system order)
+  bs.sys_batch_range.assign(2 * (size_t)g->n_sys, 0);
+  const int nB = (int)bs.batches.size();
+  for (int s = 0, b = 0; s < g->n_sys; ++s) {
+    bs.sys_batch_range[2 * s] = b;
+    while (b < nB && bs.batches[b].sys == s) ++b;
+    bs.sys_batch_range[2 * s + 1] = b;
+  }
+  upload_set(g, bs);
+}
+
+// Groups of consecutive batches whose slabs fit `budget` elements per slab, and the slab offset
+// of each batch within its group.  Returns the largest single-batch need (elements).
+size_t form_groups(BatchSet& bs, size_t budget) {
+  bs.groups.clear();
+  bs.slab_elems = 0;
+  size_t largest = 0;
   BatchSet::Group cur{0, 0, 0.0};
   size_t used = 0;
   const int nB = (int)bs.batches.size();
@@ -564,19 +595,16 @@ void build_set(aims_grid* g, BatchSet& bs, int merge, bool density, int ratio = 
     cur.flops += 2.0 * d.n_p * (double)d.n_b * d.n_b;
     d.slab_off = (int64_t)used;
     used += need;
+    largest = std::max(largest, need);
     bs.slab_elems = std::max(bs.slab_elems, used);
   }
   cur.b1 = nB;
   if (cur.b1 > cur.b0) bs.groups.push_back(cur);
-  // batch range of each system (batches are in system order)
-  bs.sys_batch_range.assign(2 * (size_t)g->n_sys, 0);
-  for (int s = 0, b = 0; s < g->n_sys; ++s) {
-    bs.sys_batch_range[2 * s] = b;
-    while (b < nB && bs.batches[b].sys == s) ++b;
-    bs.sys_batch_range[2 * s + 1] = b;
-  }
+  return largest;
+}
 
-  // upload
+// Device copies of a batch set's tables; the handle's slabs grow to the set's largest group.
+void upload_set(aims_grid* g, BatchSet& bs) {
   bs.dv = g->common;
   bs.dv.batches = g->upload(bs.batches);
   bs.dv.batch_atoms = g->upload(bs.batch_atoms);
@@ -612,7 +640,7 @@ int density_nbn(int n_p, int cap) {
 
 // Tile work list of a batch set: square 64 x 64 tiles for the H kernel, (64 rows x 32 nbn
 // points) tiles for the density kernel, grouped per kernel variant within each batch group.
-ItemList& items_for(aims_grid* g, BatchSet& bs, int pblocks) {
+ItemList& items_for(aims_grid* g, BatchSet& bs, int pblocks, bool counters = true) {
   if (!bs.density) pblocks = 0;
   for (auto& l : bs.lists)
     if (l->pblocks == pblocks) return *l;
@@ -645,7 +673,7 @@ ItemList& items_for(aims_grid* g, BatchSet& bs, int pblocks) {
   L->d_items = g->upload(L->items);
   size_t launches = 0;
   for (const auto& r : L->runs) launches += r.size();
-  if (8 * launches > g->queue_cap) {
+  if (counters && 8 * launches > g->queue_cap) {
     g->d_queue = (int*)g->alloc(8 * launches * sizeof(int));
     g->queue_cap = 8 * launches;
   }
@@ -662,6 +690,54 @@ BatchSet& hset(aims_grid* g, int merge, int ratio = 0) {
   items_for(g, *bs, 0);
   g->hsets.push_back(std::move(bs));
   return *g->hsets.back();
+}
+
+// Point-tile cap of the allocation-free density update's work list (fixed: that call never
+// builds a list).
+constexpr int kNoAllocPblocks = 2;
+
+// Device address of the static scratch on the current device, looked up once per device.
+void* noalloc_scratch_address(int device) {
+  static std::mutex mu;
+  static std::map<int, void*> addr;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = addr.find(device);
+  if (it != addr.end()) return it->second;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    fail(AIMS_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(e));
+  }
+  addr[device] = p;
+  return p;
+}
+
+// The density batches grouped so that one group's two slabs fit the static scratch (half each,
+// sized for FP64 values, so the narrower forms fit too), with their own slab offsets and tile
+// list.  Only the batch descriptors differ from the density set on the device.
+void build_noalloc_set(aims_grid* g) {
+  BatchSet& src = g->dens;
+  BatchSet& bs = g->dens_na;
+  bs.merge = 0;
+  bs.density = true;
+  bs.batches = src.batches;
+  bs.sys_batch_range = src.sys_batch_range;
+  bs.sum_np_nb2 = src.sum_np_nb2;
+  bs.sum_nb2 = src.sum_nb2;
+  const size_t budget = kNoAllocScratchBytes / 2 / sizeof(double);
+  const size_t largest = form_groups(bs, budget);
+  g->na_scratch = noalloc_scratch_address(g->device);
+  if (largest > budget) {
+    char buf[256];
+    snprintf(buf, sizeof(buf), "a batch needs %zu bytes per basis slab, above the %zu of the "
+             "static scratch of aims_update_density_noalloc", largest * sizeof(double), budget * sizeof(double));
+    g->na_error = buf;
+    return;
+  }
+  bs.dv = src.dv;
+  bs.dv.batches = g->upload(bs.batches);
+  items_for(g, bs, kNoAllocPblocks, false);
 }
 
 aims_grid* build(const aims_system* sys, int n_sys, int device, void* stream) {
@@ -799,6 +875,7 @@ aims_grid* build(const aims_system* sys, int n_sys, int device, void* stream) {
   g->d_part = (double*)g->alloc((size_t)n_sys * g->nblk_finish * 2 * sizeof(double));
   g->d_et_batch = (double*)g->alloc(std::max<size_t>(1, g->dens.batches.size()) * sizeof(double));
   for (int p = 0; p < 3; ++p) items_for(g.get(), g->dens, g->d_pblocks[p]);
+  build_noalloc_set(g.get());
   g->d_P32 = (float*)g->alloc(std::max<int64_t>(1, g->mat_total) * sizeof(float));
   // the H partitions of the default merge levels
   for (int p = 0; p < 3; ++p) hset(g.get(), g->h_merge[p], g->h_ratio[p]);
@@ -894,8 +971,8 @@ void prof_collect(aims_grid* g) {
 struct QueueSeq {
   int* base = nullptr;
   size_t k = 0, cap = 0;
-  QueueSeq(aims_grid* g, const ItemList& L, aims_precision prec) {
-    if (!g->persistent[prec]) return;
+  QueueSeq(aims_grid* g, const ItemList& L, aims_precision prec, bool grid_only = false) {
+    if (grid_only || !g->persistent[prec]) return;
     size_t launches = 0;
     for (const auto& r : L.runs) launches += r.size();
     if (8 * launches > g->queue_cap) fail(AIMS_ERR_ARG, "work counters not allocated");
@@ -915,26 +992,44 @@ struct QueueSeq {
 
 // Density update with basis values of precision T (double / float) on the MFMA type of T,
 // or, with bf16x3, FP32 basis values split into bf16 hi/lo pairs.
+//
+// The allocation-free form (noalloc) runs the same kernels on the batch set grouped for the
+// static scratch, with its slabs in that scratch, grid launches (no work counters) and no
+// profiling events.
 template <typename T>
 void run_density(aims_grid* g, aims_precision prec, const T* P, const double* v, double* n_out,
-                 double* sums_out) {
+                 double* sums_out, bool noalloc = false) {
   hipStream_t st = g->stream;
-  BatchSet& bs = g->dens;
-  const ItemList& L = items_for(g, bs, g->d_pblocks[prec]);
+  BatchSet& bs = noalloc ? g->dens_na : g->dens;
+  const int pblocks = noalloc ? kNoAllocPblocks : g->d_pblocks[prec];
+  const ItemList* Lp = nullptr;
+  if (noalloc) {
+    for (auto& l : bs.lists)
+      if (l->pblocks == pblocks) Lp = l.get();
+    if (!Lp) fail(AIMS_ERR_ARG, "allocation-free work list missing");
+  } else {
+    Lp = &items_for(g, bs, pblocks);
+  }
+  const ItemList& L = *Lp;
+  void* slab1 = noalloc ? g->na_scratch : g->d_slab1;
+  void* slab2 = noalloc ? (void*)((unsigned char*)g->na_scratch + kNoAllocScratchBytes / 2) : g->d_slab2;
+  auto timed = [&](int kind, double work, const char* what, auto&& launch) {
+    if (noalloc) hipchk(launch(), what);
+    else ::timed(g, kind, work, what, launch);
+  };
   hipchk(launch_fill(g->d_n_sorted, (size_t)g->n_points, 0.0, st), "fill n");
   hipchk(launch_fill(g->d_et_batch, bs.batches.size(), 0.0, st), "fill E_T");
-  QueueSeq qs(g, L, prec);
+  QueueSeq qs(g, L, noalloc ? AIMS_FP64 : prec, noalloc);
   for (size_t gi = 0; gi < bs.groups.size(); ++gi) {
     const auto& gr = bs.groups[gi];
     const int nbt = gr.b1 - gr.b0;
     if (prec == AIMS_BF16X3) {
-      timed(g, kProfPhi, 0.0, "phi_eval", [&] {
-        return launch_phi_eval_bf16(bs.dv, gr.b0, nbt, kModeDensity, nullptr, g->d_slab1, g->d_slab2, st);
+      timed(kProfPhi, 0.0, "phi_eval", [&] {
+        return launch_phi_eval_bf16(bs.dv, gr.b0, nbt, kModeDensity, nullptr, slab1, slab2, st);
       });
     } else {
-      timed(g, kProfPhi, 0.0, "phi_eval", [&] {
-        return launch_phi_eval<T>(bs.dv, gr.b0, nbt, kModeDensity, nullptr, (T*)g->d_slab1,
-                                  (T*)g->d_slab2, st);
+      timed(kProfPhi, 0.0, "phi_eval", [&] {
+        return launch_phi_eval<T>(bs.dv, gr.b0, nbt, kModeDensity, nullptr, (T*)slab1, (T*)slab2, st);
       });
     }
     for (size_t r = 0; r < L.runs[gi].size(); ++r) {
@@ -942,21 +1037,21 @@ void run_density(aims_grid* g, aims_precision prec, const T* P, const double* v,
       const double work = r + 1 == L.runs[gi].size() ? gr.flops : 0.0;   // credited once per group
       const int nit = (int)(run.i1 - run.i0);
       if (prec == AIMS_BF16X3) {
-        timed(g, kProfDensity, work, "density", [&] {
+        timed(kProfDensity, work, "density", [&] {
           return launch_density_bf16(bs.dv, run.nbn, L.d_items + run.i0, nit, (const float*)P,
-                                     g->d_slab1, g->d_slab2, g->d_n_sorted, g->d_et_batch, st,
+                                     slab1, slab2, g->d_n_sorted, g->d_et_batch, st,
                                      nullptr, qs.next());
         });
       } else {
-        timed(g, kProfDensity, work, "density", [&] {
-          return launch_density<T>(bs.dv, run.nbn, L.d_items + run.i0, nit, P, (const T*)g->d_slab1,
-                                   (const T*)g->d_slab2, g->d_n_sorted, g->d_et_batch, st, nullptr,
+        timed(kProfDensity, work, "density", [&] {
+          return launch_density<T>(bs.dv, run.nbn, L.d_items + run.i0, nit, P, (const T*)slab1,
+                                   (const T*)slab2, g->d_n_sorted, g->d_et_batch, st, nullptr,
                                    qs.next());
         });
       }
     }
   }
-  timed(g, kProfFinish, 0.0, "density_finish", [&] {
+  timed(kProfFinish, 0.0, "density_finish", [&] {
     return launch_density_finish(bs.dv, g->d_n_sorted, v, n_out, g->d_part, g->nblk_finish,
                                  g->d_et_batch, sums_out, st);
   });
@@ -1002,12 +1097,12 @@ void run_hs(aims_grid* g, aims_precision prec, int mode, const double* v, double
 
 // One precision-dispatched density update (P converted to FP32 for the mixed forms).
 void density_call(aims_grid* g, aims_precision prec, const double* P, const double* v, double* n_out,
-                  double* sums_out) {
+                  double* sums_out, bool noalloc = false) {
   if (prec == AIMS_FP64) {
-    run_density<double>(g, prec, P, v, n_out, sums_out);
+    run_density<double>(g, prec, P, v, n_out, sums_out, noalloc);
   } else {
     hipchk(launch_convert_f32(P, g->d_P32, (size_t)g->mat_total, g->stream), "convert P");
-    run_density<float>(g, prec, g->d_P32, v, n_out, sums_out);
+    run_density<float>(g, prec, g->d_P32, v, n_out, sums_out, noalloc);
   }
 }
 
@@ -1255,6 +1350,20 @@ aims_status aims_update_density(aims_grid* g, aims_precision prec, const double*
     if (v_or_null) require_device(v_or_null, "v", g->n_points > 0);
     set_positions(g, atom_xyz);
     density_call(g, prec, P, v_or_null, n_out, sums_out);
+  });
+}
+
+aims_status aims_update_density_noalloc(aims_grid* g, aims_precision prec, const double* P,
+                                        const double* v_or_null, double* n_out, double* sums_out) {
+  return guarded(g, [&] {
+    check_prec(prec);
+    require_device(P, "P");
+    require_device(n_out, "n_out", g->n_points > 0);
+    require_device(sums_out, "sums_out");
+    if (v_or_null) require_device(v_or_null, "v", g->n_points > 0);
+    if (!g->na_error.empty()) fail(AIMS_ERR_UNSUPPORTED, "%s", g->na_error.c_str());
+    set_positions(g, nullptr);
+    density_call(g, prec, P, v_or_null, n_out, sums_out, true);
   });
 }
 

@@ -112,6 +112,16 @@ class AimsGrid:
                                                     _ptr(P), _ptr(v), _ptr(n), _ptr(sums)))
         return n, sums
 
+    def update_density_noalloc(self, P: torch.Tensor, v: Optional[torch.Tensor] = None,
+                               prec: str = "fp64", n_out=None, sums_out=None):
+        """``update_density`` through the allocation-free entry point (setup positions)."""
+        n = self._new(self.n_points) if n_out is None else n_out
+        sums = self._new(self.n_sys, 3) if sums_out is None else sums_out
+        with torch.cuda.device(self.device):
+            self._check(self._L.aims_update_density_noalloc(self._h, PRECISION[prec], _ptr(P),
+                                                            _ptr(v), _ptr(n), _ptr(sums)))
+        return n, sums
+
     def integrate_h(self, v: torch.Tensor, prec: str = "fp64", want_S: bool = False,
                     atom_xyz=None, H_out=None, S_out=None):
         """Flat H (and S) buffers of mat_elems entries; use ``blocks`` to view per system."""
