@@ -25,14 +25,15 @@ import time
 
 import numpy as np
 
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}   # MI355X dense MFMA peaks
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "int8x7": 5000.0}   # MI355X dense MFMA peaks (int8: TOP/s)
+MFMA_PER_FLOP_INT8 = {"density": 34, "hs": 28}   # int8 digit products per product
 SINGLE_SCRATCH_MB = 512     # scratch budget of each per-molecule baseline handle (c4)
 HERE = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "tiled_kernels_c2_fp64_hbm_traffic.md")
 KERNEL_SRC = os.path.join(HERE, "paper_2208_12335_amd", "csrc", "kernels.hip")
 HOST_SRC = os.path.join(HERE, "paper_2208_12335_amd", "csrc", "host.cpp")     # batch partitions
-DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}
-FAMILIES = ("phi_eval", "density", "hs", "backward", "finish")
+DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "int8x7": "int8x7"}
+FAMILIES = ("phi_eval", "density", "hs", "backward", "finish", "operands")
 
 WORKLOADS = {
     "c2": "64-atom random cluster (Z in {1,6,8}, box 20 bohr), l<=3 NAO basis, 75x302 grid, "
@@ -155,7 +156,11 @@ def _roofline(kern, head, steps, workload=None, tuning=None, flop_per_step=None)
             "work_flop_per_launch": work / kd["launches"],
             "executed_flop_per_launch": executed / kd["launches"],
             **({"mfma_flop_per_flop": 3, "mfma_frac": 3.0 * achieved / PEAK_TFLOPS[head]}
-               if head == "bf16x3" else {})}
+               if head == "bf16x3" else {}),
+            # int8 digit products per algorithmic multiply-add pair: 34 (density), 28 (H)
+            **({"mfma_flop_per_flop": MFMA_PER_FLOP_INT8[dom],
+                "mfma_frac": MFMA_PER_FLOP_INT8[dom] * achieved / PEAK_TFLOPS[head]}
+               if head == "int8x7" else {})}
 
 
 def _forms_summary(res):
@@ -295,7 +300,7 @@ def bench_single(args, torch, inst, backward=False):
             # n >= 0) next to the random-sign P of the workload
             occ = {}
             e64 = None
-            for prec in ("fp64", "fp32", "bf16x3"):
+            for prec in ("fp64", "fp32", "bf16x3", "int8x7"):
                 g.update_density(P_new, v, prec=prec, n_out=nn, sums_out=sums)
                 s_ = sums.cpu().numpy()[0]
                 e = float(s_[1] + s_[2])
@@ -480,7 +485,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
-    ap.add_argument("--forms", default="fp64,fp32,bf16x3",
+    ap.add_argument("--forms", default="fp64,fp32,bf16x3,int8x7",
                     help="precision forms to time (fp64 is always included)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the library's default tuning instead of the autotuner's choice")

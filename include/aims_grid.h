@@ -67,9 +67,18 @@ typedef enum {
   AIMS_FP64 = 0,    /* everything in FP64                                                    */
   AIMS_FP32 = 1,    /* per-batch contractions on FP32 MFMA, FP32 basis values and tables;
                        FP64 cross-batch reduction of H/S/n and of the N/E sums               */
-  AIMS_BF16X3 = 2   /* per-batch contractions as three BF16 MFMA products of hi/lo splits
+  AIMS_BF16X3 = 2,  /* per-batch contractions as three BF16 MFMA products of hi/lo splits
                        (x = hi + lo, hi = bf16(x), lo = bf16(x - hi); hi*hi + hi*lo + lo*hi)
                        with FP32 accumulation; FP64 cross-batch reduction as for AIMS_FP32   */
+  AIMS_INT8X7 = 3   /* per-batch contractions on the int8 matrix cores: every operand row is
+                       scaled by a power of two and written as seven balanced base-128 digits
+                       (x = 2^e sum_s q_s 128^-s, q_s in [-64, 64]); the digit products with
+                       s + t <= 8 (28 per product) accumulate exactly in int32 and combine in
+                       FP64.  Basis values are evaluated in FP64.  Density, H and S passes only
+                       (the backward, forces and the gradient term return
+                       AIMS_ERR_UNSUPPORTED); at most 4096 functions per batch.  The products
+                       follow the error-free slicing of Ozaki, Ogita, Oishi and Rump (2012),
+                       the "Development Priorities" note on exploiting new GPU hardware.  */
 } aims_precision;
 
 /* One molecular system.  All pointers are HOST pointers; the library copies what it needs

@@ -12,7 +12,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libaimsgrid
 AIMS_OK, AIMS_ERR_ARG, AIMS_ERR_OOM, AIMS_ERR_HIP, AIMS_ERR_STALE, AIMS_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "AIMS_OK", -1: "AIMS_ERR_ARG", -2: "AIMS_ERR_OOM", -3: "AIMS_ERR_HIP",
                 -4: "AIMS_ERR_STALE", -5: "AIMS_ERR_UNSUPPORTED"}
-PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2, "int8x7": 3}
 DM_METHOD = {"eigen": 0, "purify": 1}
 XC_FUNCTIONAL = {"lda": 0, "pbe": 1}
 

@@ -148,6 +148,8 @@ def autotune(grid, P, v, prec: str = "fp64", *, reps: int = 3, cache: Optional[s
         e1.synchronize()
         return e0.elapsed_time(e1) / reps
 
+    if prec == "int8x7":            # its density tiles always span 64 points
+        density_pblocks = (2,)
     best, log = search(cost, density_pblocks, h_merge, persistent, h_ratio)
     grid.set_tuning(prec=prec, **best)
     entry = dict(best, ms=log)

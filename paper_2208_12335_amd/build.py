@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libaimsgrid.so")
-SOURCES = ["kernels.hip", "forces.hip", "scf.hip", "xc.hip", "hartree.hip", "scf.cpp", "host.cpp"]
+SOURCES = ["kernels.hip", "int8.hip", "forces.hip", "scf.hip", "xc.hip", "hartree.hip", "scf.cpp", "host.cpp"]
 ARCH = os.environ.get("AIMS_OFFLOAD_ARCH", "gfx950")
 
 

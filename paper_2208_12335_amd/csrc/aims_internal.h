@@ -48,6 +48,7 @@ struct SystemDesc {
   int64_t mat_off;       // element offset of this system's nb x nb matrices
   int32_t nb;            // basis size (leading dimension)
   int32_t atom_off;      // first global atom of the system
+  int64_t row_off;       // first global basis row of the system (sum of the earlier nb)
 };
 
 struct RadialGrid {      // shared by all systems of a handle

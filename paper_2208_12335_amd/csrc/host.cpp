@@ -206,6 +206,8 @@ struct BatchSet {
   std::vector<std::unique_ptr<ItemList>> lists;
   // device copies
   DeviceView dv{};
+  int32_t* d_colexp = nullptr;     // int8 form: per batch column, exponents of the two H operands
+  int max_nb = 0;                  // largest batch basis count
 };
 
 struct aims_grid {
@@ -235,10 +237,10 @@ struct aims_grid {
   void* na_scratch = nullptr;                 // device address of `scratch` on this handle's device
   std::string na_error;                       // non-empty: the static scratch cannot hold a batch
   std::vector<std::unique_ptr<BatchSet>> hsets;  // H partitions by merge level (built on demand)
-  int h_merge[3] = {1, 2, 2};                 // per precision
-  int h_ratio[3] = {0, 0, 0};                 // per precision: > 0 selects the cost-model H partition
-  int d_pblocks[3] = {2, 5, 5};               // per precision: density point-tile cap
-  int persistent[3] = {0, 0, 0};              // per precision: persistent tile launches
+  int h_merge[4] = {1, 2, 2, 1};              // per precision
+  int h_ratio[4] = {0, 0, 0, 0};              // per precision: > 0 selects the cost-model H partition
+  int d_pblocks[4] = {2, 5, 5, 2};            // per precision: density point-tile cap (int8: 64)
+  int persistent[4] = {0, 0, 0, 0};           // per precision: persistent tile launches
   int* d_queue = nullptr;                     // 8 work counters per tiled launch of one call
   size_t queue_cap = 0;                       // counters allocated
   int nblk_finish = 64;
@@ -252,9 +254,9 @@ struct aims_grid {
   bool profiling = false;
   bool graph_captured = false;        // a step graph may reference the current scratch
   std::vector<ProfRec> prof_pending;
-  int64_t prof_count[5] = {0, 0, 0, 0, 0};
-  double prof_ms[5] = {0, 0, 0, 0, 0};
-  double prof_work[5] = {0, 0, 0, 0, 0};
+  int64_t prof_count[6] = {0, 0, 0, 0, 0, 0};
+  double prof_ms[6] = {0, 0, 0, 0, 0, 0};
+  double prof_work[6] = {0, 0, 0, 0, 0, 0};
 
   std::vector<void*> owned;           // device allocations
   DeviceView common{};                // device pointers shared by every batch set
@@ -263,6 +265,9 @@ struct aims_grid {
   double* d_part = nullptr;
   double* d_et_batch = nullptr;
   float* d_P32 = nullptr;
+  uint64_t* d_P8 = nullptr;           // int8 form: digit words of P
+  int32_t* d_eP = nullptr;            // int8 form: exponent of each row of P
+  int32_t* d_pexp = nullptr;          // int8 form: per point (batch order), exponents of Phi, t Phi
   void* d_slab1 = nullptr;
   void* d_slab2 = nullptr;
   void* d_slab3 = nullptr;            // backward: X = Phi P_b
@@ -593,6 +598,7 @@ size_t form_groups(BatchSet& bs, size_t budget) {
       used = 0;
     }
     cur.flops += 2.0 * d.n_p * (double)d.n_b * d.n_b;
+    bs.max_nb = std::max(bs.max_nb, d.n_b);
     d.slab_off = (int64_t)used;
     used += need;
     largest = std::max(largest, need);
@@ -769,6 +775,8 @@ aims_grid* build(const aims_system* sys, int n_sys, int device, void* stream) {
   // ---- species, splines, atoms ----------------------------------------------------------
   std::vector<SpeciesDesc> species;
   std::vector<int32_t> shell_l;
+  std::vector<int32_t> shell_fexp;   // per shell: balancing exponent of the int8 form
+  std::vector<int32_t> fn_fexp;      // per global basis function: the same, per function
   std::vector<double> spline64;
   std::vector<int32_t> atom_species, atom_sys;
   g->atom_nfn.resize(n_sys);
@@ -786,6 +794,15 @@ aims_grid* build(const aims_system* sys, int n_sys, int device, void* stream) {
       for (int j = 0; j < sd.nshell; ++j) {
         const int l = s.shell_l[sh_off + j];
         shell_l.push_back(l);
+        // power of two near the shell's largest |R Y_lm| (largest tabulated |R| times
+        // sqrt((2l + 1) / (4 pi))): the int8 form divides the density pass's basis values by it
+        // and multiplies the matching columns of P by it, an exact rescaling that evens out the
+        // digit scales of a point's functions
+        double rmax = 0.0;
+        for (int kk = 0; kk < n_log; ++kk) rmax = std::max(rmax, std::fabs(s.shell_R[(size_t)(sh_off + j) * n_log + kk]));
+        int ex = 0;
+        if (rmax > 0.0) (void)std::frexp(rmax * std::sqrt((2.0 * l + 1.0) / (4.0 * M_PI)), &ex);
+        shell_fexp.push_back(ex);
         nfn += 2 * l + 1;
         lmax = std::max(lmax, l);
       }
@@ -809,6 +826,7 @@ aims_grid* build(const aims_system* sys, int n_sys, int device, void* stream) {
     }
     SystemDesc sdsc{};
     sdsc.mat_off = g->mat_total;
+    sdsc.row_off = g->nb_total;
     sdsc.atom_off = g->n_atoms;
     int nb = 0;
     for (int a = 0; a < s.n_atoms; ++a) {
@@ -818,6 +836,9 @@ aims_grid* build(const aims_system* sys, int n_sys, int device, void* stream) {
       g->atom_col0[k].push_back(nb);
       g->atom_nfn[k].push_back(species[gs].nfn);
       nb += species[gs].nfn;
+      for (int j = 0; j < species[gs].nshell; ++j)
+        for (int m = 0; m < 2 * shell_l[species[gs].shell_l_off + j] + 1; ++m)
+          fn_fexp.push_back(shell_fexp[species[gs].shell_l_off + j]);
       for (int c = 0; c < 3; ++c) g->atom_xyz0.push_back(s.atom_xyz[3 * a + c]);
     }
     sdsc.nb = nb;
@@ -855,6 +876,7 @@ aims_grid* build(const aims_system* sys, int n_sys, int device, void* stream) {
   // ---- upload of the shared state, then the density partition ---------------------------
   hipchk(hipSetDevice(device), "hipSetDevice");
   hipchk(prepare_launch_configs(), "occupancy query");
+  hipchk(prepare_launch_configs_i8(), "occupancy query");
   DeviceView& dv = g->common;
   dv.systems = g->upload(g->systems);
   dv.pts = g->upload(g->pts_sorted);
@@ -865,6 +887,8 @@ aims_grid* build(const aims_system* sys, int n_sys, int device, void* stream) {
   dv.atom_sys = g->upload(atom_sys);
   dv.species = g->upload(species);
   dv.shell_l = g->upload(shell_l);
+  dv.shell_fexp = g->upload(shell_fexp);
+  dv.fn_fexp = g->upload(fn_fexp);
   dv.spline64 = g->upload(spline64);
   dv.spline32 = g->upload(spline32);
   dv.sys_pt_range = g->upload(g->sys_pt_range);
@@ -885,15 +909,33 @@ aims_grid* build(const aims_system* sys, int n_sys, int device, void* stream) {
 // ---------------------------------------------------------------------------------------------
 // per-call helpers
 // ---------------------------------------------------------------------------------------------
-void require_device(const void* p, const char* name, bool nonempty = true) {
-  if (!nonempty) return;  // zero-length arrays are never touched
+// A caller array the call reads or writes: `bytes` of device memory from p, all inside one
+// allocation (hipMemGetAddressRange), so that a short buffer is refused on the host instead of
+// being overrun on the device.  Zero-length arrays are never touched and not checked.
+void require_device(const void* p, const char* name, size_t bytes) {
+  if (bytes == 0) return;
   if (!p) fail(AIMS_ERR_ARG, "%s is NULL", name);
   if (!is_device_ptr(p)) fail(AIMS_ERR_ARG, "%s must be device memory", name);
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p) != hipSuccess || !base) {
+    (void)hipGetLastError();
+    fail(AIMS_ERR_ARG, "%s: no device allocation found", name);
+  }
+  const size_t off = (size_t)((const char*)p - (const char*)base);
+  if (off > size || size - off < bytes)
+    fail(AIMS_ERR_ARG, "%s: %zu bytes needed, the allocation holds %zu from this pointer", name,
+         bytes, off > size ? (size_t)0 : size - off);
 }
 
 void check_prec(aims_precision p) {
-  if (p != AIMS_FP64 && p != AIMS_FP32 && p != AIMS_BF16X3)
+  if (p != AIMS_FP64 && p != AIMS_FP32 && p != AIMS_BF16X3 && p != AIMS_INT8X7)
     fail(AIMS_ERR_ARG, "unknown precision %d", (int)p);
+}
+
+// The forward passes only (density, H, S) have the sliced integer form.
+void forward_only(aims_precision p, const char* what) {
+  if (p == AIMS_INT8X7) fail(AIMS_ERR_UNSUPPORTED, "%s: AIMS_INT8X7 serves the density, H and S passes only", what);
 }
 
 // Positions for this call: NULL = setup positions.  A given array (host or device) is read
@@ -911,6 +953,7 @@ void set_positions(aims_grid* g, const double* xyz) {
   }
   std::vector<double> h(n);
   if (is_device_ptr(xyz)) {
+    require_device(xyz, "atom_xyz", n * sizeof(double));
     hipchk(hipMemcpyAsync(h.data(), xyz, n * sizeof(double), hipMemcpyDeviceToHost, g->stream), "read positions");
     hipchk(hipStreamSynchronize(g->stream), "read positions");
   } else {
@@ -931,8 +974,8 @@ void set_positions(aims_grid* g, const double* xyz) {
   g->moved = true;
 }
 
-enum { kProfPhi = 0, kProfDensity = 1, kProfHS = 2, kProfBackward = 3, kProfFinish = 4 };
-const char* kProfNames[5] = {"phi_eval", "density", "hs", "backward", "finish"};
+enum { kProfPhi = 0, kProfDensity = 1, kProfHS = 2, kProfBackward = 3, kProfFinish = 4, kProfOperands = 5 };
+const char* kProfNames[6] = {"phi_eval", "density", "hs", "backward", "finish", "operands"};
 
 // Runs one launch, bracketed by events when profiling is on.
 template <typename F>
@@ -1095,10 +1138,98 @@ void run_hs(aims_grid* g, aims_precision prec, int mode, const double* v, double
   }
 }
 
+// ---- sliced integer form ------------------------------------------------------------------
+// Buffers of the int8 form, taken on first use (and before a step graph is captured).
+void prepare_i8(aims_grid* g, BatchSet* hbs) {
+  if (!g->d_P8) {
+    g->d_P8 = (uint64_t*)g->alloc(std::max<int64_t>(1, g->mat_total) * sizeof(uint64_t));
+    g->d_eP = (int32_t*)g->alloc(std::max<int64_t>(1, g->nb_total) * sizeof(int32_t));
+    g->d_pexp = (int32_t*)g->alloc(2 * std::max<int64_t>(1, g->n_points) * sizeof(int32_t));
+  }
+  if (hbs && !hbs->d_colexp)
+    hbs->d_colexp = (int32_t*)g->alloc(2 * std::max<size_t>(1, hbs->batch_cols.size()) * sizeof(int32_t));
+}
+
+// Largest basis slab row length (density: ldp) or basis count (H / S) of a group's batches: the
+// basis evaluation keeps one LDS slot pair per point or per function (64 KiB at most).
+int group_slots(const BatchSet& bs, const BatchSet::Group& gr, bool per_point) {
+  int m = 0;
+  for (int b = gr.b0; b < gr.b1; ++b) m = std::max(m, per_point ? bs.batches[b].ldp : bs.batches[b].n_b);
+  if (m > 4096) fail(AIMS_ERR_UNSUPPORTED, "AIMS_INT8X7: a batch of %d functions (at most 4096)", m);
+  return m;
+}
+
+void run_density_i8(aims_grid* g, const double* P, const double* v, double* n_out, double* sums_out) {
+  hipStream_t st = g->stream;
+  BatchSet& bs = g->dens;
+  prepare_i8(g, nullptr);
+  const ItemList& L = items_for(g, bs, g->d_pblocks[AIMS_INT8X7]);
+  int32_t* ex1 = g->d_pexp;
+  int32_t* ex2 = g->d_pexp + g->n_points;
+  uint64_t* s1 = (uint64_t*)g->d_slab1;
+  uint64_t* s2 = (uint64_t*)g->d_slab2;
+  timed(g, kProfOperands, 0.0, "slice P", [&] {
+    return launch_slice_p(bs.dv, P, g->d_P8, g->d_eP, g->nb_total, st);
+  });
+  hipchk(launch_fill(g->d_n_sorted, (size_t)g->n_points, 0.0, st), "fill n");
+  hipchk(launch_fill(g->d_et_batch, bs.batches.size(), 0.0, st), "fill E_T");
+  QueueSeq qs(g, L, AIMS_INT8X7);
+  for (size_t gi = 0; gi < bs.groups.size(); ++gi) {
+    const auto& gr = bs.groups[gi];
+    const int slots = group_slots(bs, gr, true);
+    timed(g, kProfPhi, 0.0, "phi_eval", [&] {
+      return launch_phi_eval_i8(bs.dv, gr.b0, gr.b1 - gr.b0, kModeDensity, nullptr, s1, s2, ex1, ex2,
+                                slots, st);
+    });
+    for (size_t r = 0; r < L.runs[gi].size(); ++r) {
+      const auto& run = L.runs[gi][r];
+      if (run.nbn != 2) fail(AIMS_ERR_ARG, "AIMS_INT8X7 density tiles span 64 points");
+      const double work = r + 1 == L.runs[gi].size() ? gr.flops : 0.0;
+      timed(g, kProfDensity, work, "density", [&] {
+        return launch_density_i8(bs.dv, L.d_items + run.i0, (int)(run.i1 - run.i0), g->d_P8, g->d_eP,
+                                 s1, s2, ex1, ex2, g->d_n_sorted, g->d_et_batch, st, qs.next());
+      });
+    }
+  }
+  timed(g, kProfFinish, 0.0, "density_finish", [&] {
+    return launch_density_finish(bs.dv, g->d_n_sorted, v, n_out, g->d_part, g->nblk_finish,
+                                 g->d_et_batch, sums_out, st);
+  });
+}
+
+void run_hs_i8(aims_grid* g, int mode, const double* v, double* out) {
+  hipStream_t st = g->stream;
+  BatchSet& bs = hset(g, g->h_merge[AIMS_INT8X7], g->h_ratio[AIMS_INT8X7]);
+  prepare_i8(g, &bs);
+  const ItemList& L = items_for(g, bs, 0);
+  int32_t* ex1 = bs.d_colexp;
+  int32_t* ex2 = bs.d_colexp + bs.batch_cols.size();
+  uint64_t* s1 = (uint64_t*)g->d_slab1;
+  uint64_t* s2 = (uint64_t*)g->d_slab2;
+  hipchk(launch_fill(out, (size_t)g->mat_total, 0.0, st), "fill H");
+  QueueSeq qs(g, L, AIMS_INT8X7);
+  for (size_t gi = 0; gi < bs.groups.size(); ++gi) {
+    const auto& gr = bs.groups[gi];
+    const int slots = group_slots(bs, gr, false);
+    for (const auto& run : L.runs[gi]) {
+      timed(g, kProfPhi, 0.0, "phi_eval", [&] {
+        return launch_phi_eval_i8(bs.dv, gr.b0, gr.b1 - gr.b0, mode, v, s1, s2, ex1, ex2, slots, st);
+      });
+      timed(g, kProfHS, gr.flops, "hs", [&] {
+        return launch_hs_i8(bs.dv, L.d_items + run.i0, (int)(run.i1 - run.i0), s1, s2, ex1, ex2, out,
+                            st, qs.next());
+      });
+    }
+  }
+}
+
 // One precision-dispatched density update (P converted to FP32 for the mixed forms).
 void density_call(aims_grid* g, aims_precision prec, const double* P, const double* v, double* n_out,
                   double* sums_out, bool noalloc = false) {
-  if (prec == AIMS_FP64) {
+  if (prec == AIMS_INT8X7) {
+    if (noalloc) fail(AIMS_ERR_UNSUPPORTED, "the allocation-free update takes AIMS_FP64, AIMS_FP32 or AIMS_BF16X3");
+    run_density_i8(g, P, v, n_out, sums_out);
+  } else if (prec == AIMS_FP64) {
     run_density<double>(g, prec, P, v, n_out, sums_out, noalloc);
   } else {
     hipchk(launch_convert_f32(P, g->d_P32, (size_t)g->mat_total, g->stream), "convert P");
@@ -1108,8 +1239,14 @@ void density_call(aims_grid* g, aims_precision prec, const double* P, const doub
 
 void hs_call(aims_grid* g, aims_precision prec, int mode, const double* v, double* out,
              const double* u = nullptr) {
-  if (prec == AIMS_FP64) run_hs<double>(g, prec, mode, v, out, u);
-  else run_hs<float>(g, prec, mode, v, out, u);
+  if (prec == AIMS_INT8X7) {
+    if (u) fail(AIMS_ERR_UNSUPPORTED, "AIMS_INT8X7 has no gradient term of H");
+    run_hs_i8(g, mode, v, out);
+  } else if (prec == AIMS_FP64) {
+    run_hs<double>(g, prec, mode, v, out, u);
+  } else {
+    run_hs<float>(g, prec, mode, v, out, u);
+  }
 }
 
 template <typename F>
@@ -1344,10 +1481,10 @@ aims_status aims_update_density(aims_grid* g, aims_precision prec, const double*
                                 double* sums_out) {
   return guarded(g, [&] {
     check_prec(prec);
-    require_device(P, "P");
-    require_device(n_out, "n_out", g->n_points > 0);
-    require_device(sums_out, "sums_out");
-    if (v_or_null) require_device(v_or_null, "v", g->n_points > 0);
+    require_device(P, "P", (size_t)g->mat_total * sizeof(double));
+    require_device(n_out, "n_out", (size_t)g->n_points * sizeof(double));
+    require_device(sums_out, "sums_out", 3 * (size_t)g->n_sys * sizeof(double));
+    if (v_or_null) require_device(v_or_null, "v", (size_t)g->n_points * sizeof(double));
     set_positions(g, atom_xyz);
     density_call(g, prec, P, v_or_null, n_out, sums_out);
   });
@@ -1357,10 +1494,10 @@ aims_status aims_update_density_noalloc(aims_grid* g, aims_precision prec, const
                                         const double* v_or_null, double* n_out, double* sums_out) {
   return guarded(g, [&] {
     check_prec(prec);
-    require_device(P, "P");
-    require_device(n_out, "n_out", g->n_points > 0);
-    require_device(sums_out, "sums_out");
-    if (v_or_null) require_device(v_or_null, "v", g->n_points > 0);
+    require_device(P, "P", (size_t)g->mat_total * sizeof(double));
+    require_device(n_out, "n_out", (size_t)g->n_points * sizeof(double));
+    require_device(sums_out, "sums_out", 3 * (size_t)g->n_sys * sizeof(double));
+    if (v_or_null) require_device(v_or_null, "v", (size_t)g->n_points * sizeof(double));
     if (!g->na_error.empty()) fail(AIMS_ERR_UNSUPPORTED, "%s", g->na_error.c_str());
     set_positions(g, nullptr);
     density_call(g, prec, P, v_or_null, n_out, sums_out, true);
@@ -1371,9 +1508,9 @@ aims_status aims_integrate_h(aims_grid* g, aims_precision prec, const double* at
                              double* H, double* S_or_null) {
   return guarded(g, [&] {
     check_prec(prec);
-    require_device(v, "v", g->n_points > 0);
-    require_device(H, "H");
-    if (S_or_null) require_device(S_or_null, "S");
+    require_device(v, "v", (size_t)g->n_points * sizeof(double));
+    require_device(H, "H", (size_t)g->mat_total * sizeof(double));
+    if (S_or_null) require_device(S_or_null, "S", (size_t)g->mat_total * sizeof(double));
     set_positions(g, atom_xyz);
     hs_call(g, prec, kModeH, v, H);
     if (S_or_null) hs_call(g, prec, kModeS, v, S_or_null);
@@ -1384,10 +1521,11 @@ aims_status aims_integrate_h_gga(aims_grid* g, aims_precision prec, const double
                                  const double* u, double* H) {
   return guarded(g, [&] {
     check_prec(prec);
-    if (prec == AIMS_BF16X3) fail(AIMS_ERR_UNSUPPORTED, "the gradient term supports AIMS_FP64 and AIMS_FP32");
-    require_device(v, "v", g->n_points > 0);
-    require_device(u, "u", g->n_points > 0);
-    require_device(H, "H");
+    if (prec == AIMS_BF16X3 || prec == AIMS_INT8X7)
+      fail(AIMS_ERR_UNSUPPORTED, "the gradient term supports AIMS_FP64 and AIMS_FP32");
+    require_device(v, "v", (size_t)g->n_points * sizeof(double));
+    require_device(u, "u", 3 * (size_t)g->n_points * sizeof(double));
+    require_device(H, "H", (size_t)g->mat_total * sizeof(double));
     set_positions(g, nullptr);
     if (g->moved) fail(AIMS_ERR_ARG, "the gradient term is integrated at the setup positions");
     hs_call(g, prec, kModeH, v, H, u);
@@ -1400,12 +1538,13 @@ aims_status aims_integrate_h_backward(aims_grid* g, aims_precision prec, const d
                                       double* dE_dR_or_null) {
   return guarded(g, [&] {
     check_prec(prec);
-    require_device(P, "P");
-    require_device(v, "v", g->n_points > 0);
-    require_device(gE, "gE");
-    if (dE_dP_or_null) require_device(dE_dP_or_null, "dE_dP");
-    if (dE_dv_or_null) require_device(dE_dv_or_null, "dE_dv", g->n_points > 0);
-    if (dE_dR_or_null) require_device(dE_dR_or_null, "dE_dR");
+    forward_only(prec, "the backward");
+    require_device(P, "P", (size_t)g->mat_total * sizeof(double));
+    require_device(v, "v", (size_t)g->n_points * sizeof(double));
+    require_device(gE, "gE", sizeof(double));
+    if (dE_dP_or_null) require_device(dE_dP_or_null, "dE_dP", (size_t)g->mat_total * sizeof(double));
+    if (dE_dv_or_null) require_device(dE_dv_or_null, "dE_dv", (size_t)g->n_points * sizeof(double));
+    if (dE_dR_or_null) require_device(dE_dR_or_null, "dE_dR", 3 * (size_t)g->n_atoms * sizeof(double));
     set_positions(g, atom_xyz);
     hipStream_t st = g->stream;
     if (!g->d_ntmp) {
@@ -1563,14 +1702,15 @@ aims_status aims_total_forces(aims_grid* g, aims_precision prec, const double* P
                               double* sums_out_or_null, double* dE_dR) {
   return guarded(g, [&] {
     check_prec(prec);
-    if (prec == AIMS_BF16X3) fail(AIMS_ERR_UNSUPPORTED, "total forces support AIMS_FP64 and AIMS_FP32");
+    if (prec == AIMS_BF16X3 || prec == AIMS_INT8X7)
+      fail(AIMS_ERR_UNSUPPORTED, "total forces support AIMS_FP64 and AIMS_FP32");
     if (g->moving.empty()) fail(AIMS_ERR_ARG, "no moving-grid model set (aims_grid_set_moving)");
     for (int k = 0; k < g->n_sys; ++k)
       if (!g->moving[k]) fail(AIMS_ERR_ARG, "system %d has no moving-grid model", k);
-    require_device(P, "P");
-    require_device(gE, "gE");
-    require_device(dE_dR, "dE_dR");
-    if (sums_out_or_null) require_device(sums_out_or_null, "sums_out");
+    require_device(P, "P", (size_t)g->mat_total * sizeof(double));
+    require_device(gE, "gE", sizeof(double));
+    require_device(dE_dR, "dE_dR", 3 * (size_t)g->n_atoms * sizeof(double));
+    if (sums_out_or_null) require_device(sums_out_or_null, "sums_out", 3 * (size_t)g->n_sys * sizeof(double));
     set_positions(g, nullptr);
     if (g->moved) fail(AIMS_ERR_ARG, "total forces are taken at the setup positions");
     int max_na = 1;
@@ -1680,12 +1820,12 @@ aims_status aims_density_matrix(aims_grid* g, int32_t method, const double* H, c
     if (method != AIMS_DM_EIGEN && method != AIMS_DM_PURIFY) fail(AIMS_ERR_ARG, "unknown method %d", method);
     if (!n_electrons) fail(AIMS_ERR_ARG, "null n_electrons");
     if (!(kT >= 0.0) || !std::isfinite(kT)) fail(AIMS_ERR_ARG, "kT must be finite and >= 0");
-    require_device(H, "H");
-    require_device(S, "S");
-    require_device(P_out, "P_out");
+    require_device(H, "H", (size_t)g->mat_total * sizeof(double));
+    require_device(S, "S", (size_t)g->mat_total * sizeof(double));
+    require_device(P_out, "P_out", (size_t)g->mat_total * sizeof(double));
     if (eps_out_or_null) {
       if (method == AIMS_DM_PURIFY) fail(AIMS_ERR_UNSUPPORTED, "purification computes no eigenvalues (eps_out must be NULL)");
-      require_device(eps_out_or_null, "eps_out");
+      require_device(eps_out_or_null, "eps_out", (size_t)g->nb_total * sizeof(double));
     }
     for (int k = 0; k < g->n_sys; ++k) {
       const double ne = n_electrons[k];
@@ -1758,9 +1898,9 @@ aims_status aims_hartree(aims_grid* g, const double* n, double* v_out, double* E
     if (g->h_K.empty()) fail(AIMS_ERR_ARG, "no Hartree grid set (aims_grid_set_hartree)");
     for (int k = 0; k < g->n_sys; ++k)
       if (!g->h_K[k]) fail(AIMS_ERR_ARG, "system %d has no Hartree grid", k);
-    require_device(n, "n", g->n_points > 0);
-    require_device(v_out, "v_out", g->n_points > 0);
-    if (E_out_or_null) require_device(E_out_or_null, "E_out");
+    require_device(n, "n", (size_t)g->n_points * sizeof(double));
+    require_device(v_out, "v_out", (size_t)g->n_points * sizeof(double));
+    if (E_out_or_null) require_device(E_out_or_null, "E_out", (size_t)g->n_sys * sizeof(double));
     set_positions(g, nullptr);
     if (g->moved) fail(AIMS_ERR_ARG, "the Hartree potential is taken at the setup positions");
     if (!g->h_ready) build_hartree(g);
@@ -1772,11 +1912,11 @@ aims_status aims_xc_gga(aims_grid* g, int32_t functional, const double* n, const
                         double* v_out, double* u_out, double* sums_out_or_null) {
   return guarded(g, [&] {
     if (functional != AIMS_XC_PBE) fail(AIMS_ERR_UNSUPPORTED, "aims_xc_gga takes AIMS_XC_PBE");
-    require_device(n, "n", g->n_points > 0);
-    require_device(grad_n, "grad_n", g->n_points > 0);
-    require_device(v_out, "v_out", g->n_points > 0);
-    require_device(u_out, "u_out", g->n_points > 0);
-    if (sums_out_or_null) require_device(sums_out_or_null, "sums_out");
+    require_device(n, "n", (size_t)g->n_points * sizeof(double));
+    require_device(grad_n, "grad_n", 3 * (size_t)g->n_points * sizeof(double));
+    require_device(v_out, "v_out", (size_t)g->n_points * sizeof(double));
+    require_device(u_out, "u_out", 3 * (size_t)g->n_points * sizeof(double));
+    if (sums_out_or_null) require_device(sums_out_or_null, "sums_out", 2 * (size_t)g->n_sys * sizeof(double));
     if (!g->d_xc_part) g->d_xc_part = (double*)g->alloc(2 * (size_t)kXcBlocks * g->n_sys * sizeof(double));
     hipchk(launch_pbe(g->dens.dv, n, grad_n, v_out, u_out, g->d_xc_part, sums_out_or_null, g->stream),
            "xc");
@@ -1786,9 +1926,9 @@ aims_status aims_xc_gga(aims_grid* g, int32_t functional, const double* n, const
 aims_status aims_density_gradient(aims_grid* g, const double* P, double* n_out_or_null,
                                   double* grad_out) {
   return guarded(g, [&] {
-    require_device(P, "P");
-    require_device(grad_out, "grad_out", g->n_points > 0);
-    if (n_out_or_null) require_device(n_out_or_null, "n_out", g->n_points > 0);
+    require_device(P, "P", (size_t)g->mat_total * sizeof(double));
+    require_device(grad_out, "grad_out", 3 * (size_t)g->n_points * sizeof(double));
+    if (n_out_or_null) require_device(n_out_or_null, "n_out", (size_t)g->n_points * sizeof(double));
     set_positions(g, nullptr);
     if (g->moved) fail(AIMS_ERR_ARG, "the density gradient is taken at the setup positions");
     hipStream_t st = g->stream;
@@ -1837,9 +1977,9 @@ aims_status aims_xc(aims_grid* g, int32_t functional, const double* n, double* v
   return guarded(g, [&] {
     if (functional == AIMS_XC_PBE) fail(AIMS_ERR_UNSUPPORTED, "PBE needs the density gradient (aims_xc_gga)");
     if (functional != AIMS_XC_LDA_PW92) fail(AIMS_ERR_UNSUPPORTED, "unknown functional %d", functional);
-    require_device(n, "n", g->n_points > 0);
-    require_device(v_xc_out, "v_xc_out", g->n_points > 0);
-    if (sums_out_or_null) require_device(sums_out_or_null, "sums_out");
+    require_device(n, "n", (size_t)g->n_points * sizeof(double));
+    require_device(v_xc_out, "v_xc_out", (size_t)g->n_points * sizeof(double));
+    if (sums_out_or_null) require_device(sums_out_or_null, "sums_out", 2 * (size_t)g->n_sys * sizeof(double));
     if (!g->d_xc_part) g->d_xc_part = (double*)g->alloc(2 * (size_t)kXcBlocks * g->n_sys * sizeof(double));
     hipchk(launch_lda(g->dens.dv, n, v_xc_out, g->d_xc_part, sums_out_or_null, g->stream), "xc");
   });
@@ -1857,14 +1997,16 @@ aims_status aims_step_graph_create(aims_grid* g, aims_precision prec, const doub
     if (!out) fail(AIMS_ERR_ARG, "out is NULL");
     *out = nullptr;
     check_prec(prec);
-    require_device(P, "P");
-    require_device(v, "v", g->n_points > 0);
-    require_device(n_out, "n_out", g->n_points > 0);
-    require_device(sums_out, "sums_out");
-    require_device(H, "H");
+    require_device(P, "P", (size_t)g->mat_total * sizeof(double));
+    require_device(v, "v", (size_t)g->n_points * sizeof(double));
+    require_device(n_out, "n_out", (size_t)g->n_points * sizeof(double));
+    require_device(sums_out, "sums_out", 3 * (size_t)g->n_sys * sizeof(double));
+    require_device(H, "H", (size_t)g->mat_total * sizeof(double));
     set_positions(g, nullptr);
     if (!g->stream) fail(AIMS_ERR_ARG, "step graphs need a non-default stream at setup");
     if (g->profiling) fail(AIMS_ERR_ARG, "disable profiling before capturing a step graph");
+    if (prec == AIMS_INT8X7)   // buffers taken before the capture begins
+      prepare_i8(g, &hset(g, g->h_merge[AIMS_INT8X7], g->h_ratio[AIMS_INT8X7]));
     std::unique_ptr<aims_step_graph> sg(new aims_step_graph());
     sg->stream = g->stream;
     g->graph_captured = true;
@@ -1900,7 +2042,7 @@ aims_status aims_profile_enable(aims_grid* g, int on) {
   return guarded(g, [&] {
     prof_collect(g);
     g->profiling = on != 0;
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < 6; ++k) {
       g->prof_count[k] = 0;
       g->prof_ms[k] = 0.0;
       g->prof_work[k] = 0.0;
@@ -1913,7 +2055,7 @@ aims_status aims_profile_read(aims_grid* g, const char* kernel, int64_t* launche
   return guarded(g, [&] {
     if (!kernel) fail(AIMS_ERR_ARG, "kernel name is NULL");
     int k = -1;
-    for (int i = 0; i < 5; ++i)
+    for (int i = 0; i < 6; ++i)
       if (strcmp(kernel, kProfNames[i]) == 0) k = i;
     if (k < 0) fail(AIMS_ERR_ARG, "unknown kernel family '%s'", kernel);
     prof_collect(g);
@@ -1924,7 +2066,7 @@ aims_status aims_profile_read(aims_grid* g, const char* kernel, int64_t* launche
 }
 
 aims_status aims_get_tuning(const aims_grid* g, aims_precision prec, aims_tuning* out) {
-  if (!g || !out || prec < AIMS_FP64 || prec > AIMS_BF16X3) return AIMS_ERR_ARG;
+  if (!g || !out || prec < AIMS_FP64 || prec > AIMS_INT8X7) return AIMS_ERR_ARG;
   memset(out, 0, sizeof(*out));
   out->h_merge = g->h_merge[prec];
   out->h_flops_per_atomic = g->h_ratio[prec];
@@ -1935,7 +2077,7 @@ aims_status aims_get_tuning(const aims_grid* g, aims_precision prec, aims_tuning
 
 aims_status aims_set_tuning(aims_grid* g, aims_precision prec, const aims_tuning* t) {
   return guarded(g, [&] {
-    if (!t || prec < AIMS_FP64 || prec > AIMS_BF16X3) fail(AIMS_ERR_ARG, "bad tuning arguments");
+    if (!t || prec < AIMS_FP64 || prec > AIMS_INT8X7) fail(AIMS_ERR_ARG, "bad tuning arguments");
     if (t->h_merge < 0 || t->h_merge > 4) fail(AIMS_ERR_ARG, "h_merge must be in 0..4");
     if (t->density_pblocks < 2 || t->density_pblocks > 5) fail(AIMS_ERR_ARG, "density_pblocks must be in 2..5");
     if (t->persistent != 0 && t->persistent != 1) fail(AIMS_ERR_ARG, "persistent must be 0 or 1");

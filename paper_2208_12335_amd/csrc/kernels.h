@@ -30,6 +30,8 @@ struct DeviceView {
   const int32_t* atom_sys;
   const SpeciesDesc* species;
   const int32_t* shell_l;
+  const int32_t* shell_fexp;       // int8 form: per shell, exponent of the density-pass balancing
+  const int32_t* fn_fexp;          // int8 form: the same per global basis function
   const double* spline64;
   const float* spline32;
   const int64_t* sys_pt_range;     // [n_sys][2] batch-order point range of each system
@@ -37,6 +39,12 @@ struct DeviceView {
   RadialGrid rg;
   int n_sys;
 };
+
+// Workgroups of a 256-thread kernel resident on the current device at once (cached per kernel),
+// and the grid of a tiled launch: one workgroup per item, or (persistent) the resident count
+// rounded down to a multiple of the 8 XCDs.
+int resident_workgroups(const void* fn);
+int tile_grid(int n_items, const Queue& q, const void* fn);
 
 hipError_t launch_fill(double* x, size_t n, double val, hipStream_t st);
 hipError_t launch_convert_f32(const double* x, float* y, size_t n, hipStream_t st);
@@ -101,6 +109,21 @@ hipError_t launch_hs(const DeviceView& dv, const TileItem* items, int n_items, c
 hipError_t launch_hs_bf16(const DeviceView& dv, const TileItem* items, int n_items, const void* slab1,
                           const void* slab2, double* out, hipStream_t st, Queue q = Queue());
 hipError_t launch_zero_int(int* x, int n, hipStream_t st);
+// Sliced integer form (int8.hip): P as digit words with one exponent per row; basis slabs of
+// digit words with per-point (density) or per-column (H, S) exponents; the tiled int8 kernels.
+hipError_t launch_slice_p(const DeviceView& dv, const double* P, uint64_t* P8, int32_t* eP,
+                          int64_t n_rows, hipStream_t st);
+hipError_t launch_phi_eval_i8(const DeviceView& dv, int b0, int nbatch, int mode, const double* v,
+                              uint64_t* slab1, uint64_t* slab2, int32_t* ex1, int32_t* ex2,
+                              int max_slots, hipStream_t st);
+hipError_t launch_density_i8(const DeviceView& dv, const TileItem* items, int n_items,
+                             const uint64_t* P8, const int32_t* eP, const uint64_t* slab1,
+                             const uint64_t* slab2, const int32_t* ex1, const int32_t* ex2,
+                             double* n_sorted, double* et_batch, hipStream_t st, Queue q = Queue());
+hipError_t launch_hs_i8(const DeviceView& dv, const TileItem* items, int n_items, const uint64_t* slab1,
+                        const uint64_t* slab2, const int32_t* ex1, const int32_t* ex2, double* out,
+                        hipStream_t st, Queue q = Queue());
+hipError_t prepare_launch_configs_i8();
 hipError_t prepare_launch_configs();
 hipError_t launch_density_finish(const DeviceView& dv, const double* n_sorted, const double* v,
                                  double* n_out, double* part, int nblk, const double* et_batch,

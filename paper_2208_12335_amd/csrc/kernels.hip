@@ -27,6 +27,7 @@
 #include "aims_internal.h"
 #include "basis.h"
 #include "kernels.h"
+#include "tiles.h"
 
 namespace aims {
 
@@ -218,45 +219,6 @@ constexpr int kKC = 16;            // K chunk of the FP64/FP32 kernels
 constexpr int kLdK = kKC + 1;      // K-contiguous LDS rows
 constexpr int kKB = 32;            // K chunk of the BF16 kernels
 constexpr int kLdB = kKB + 8;      // their LDS rows (bf16)
-
-// XCD-aware work order: the dispatcher places workgroup g on XCD g % 8, so consecutive work
-// items (tiles of the same batch, which share its slab) are given workgroup ids that differ by
-// multiples of 8 and stay in one XCD's L2.
-__device__ __forceinline__ int xcd_item(int g, int n) {
-  const int per = (n + 7) / 8;
-  return (g & 7) * per + (g >> 3);
-}
-
-
-// Work distribution.  Grid mode (queue == NULL): one workgroup per item, XCD-aware order.
-// Persistent mode: a fixed grid of workgroups drains eight per-XCD queues of contiguous
-// (spatially ordered) items; workgroup g starts on queue g % 8 -- the queue of its own XCD -- and
-// steals from the other queues once that is empty.  queue[8] must be zero at launch.
-template <typename F>
-__device__ __forceinline__ void run_items(int n_items, int* __restrict__ queue, F&& tile) {
-  if (!queue) {
-    const int item = xcd_item(blockIdx.x, n_items);
-    if (item < n_items) tile(item);
-    return;
-  }
-  __shared__ int s_next;
-  const int per = (n_items + 7) / 8;
-  const int x0 = blockIdx.x & 7;
-  for (int q = 0; q < 8;) {
-    const int x = (x0 + q) & 7;
-    if (threadIdx.x == 0) s_next = atomicAdd(queue + x, 1);
-    __syncthreads();
-    const int k = s_next;
-    __syncthreads();
-    const int item = x * per + k;
-    if (k >= per || item >= n_items) {
-      ++q;
-      continue;
-    }
-    tile(item);
-    __syncthreads();
-  }
-}
 
 template <typename T>
 __device__ __forceinline__ void load4(const T* __restrict__ p, T (&v)[4]);
@@ -1230,7 +1192,7 @@ static inline int item_grid(int n_items) { return ((n_items + 7) / 8) * 8; }
 
 // Workgroups of a 256-thread kernel that are resident on the current device at once
 // (occupancy x compute units), cached per kernel.
-static int resident_workgroups(const void* fn) {
+int resident_workgroups(const void* fn) {
   static std::mutex mu;
   static std::unordered_map<const void*, int> cache;
   std::lock_guard<std::mutex> lk(mu);
@@ -1248,7 +1210,7 @@ static int resident_workgroups(const void* fn) {
 
 // Grid of a tiled launch: one workgroup per item, or (persistent) the resident workgroup
 // count rounded down to a multiple of the 8 XCDs.
-static inline int tile_grid(int n_items, const Queue& q, const void* fn) {
+int tile_grid(int n_items, const Queue& q, const void* fn) {
   const int g = item_grid(n_items);
   if (!q.counters) return g;
   const int res = q.workgroups > 0 ? q.workgroups : resident_workgroups(fn);

@@ -102,14 +102,30 @@ class AimsGrid:
     def _new(self, *shape):
         return torch.empty(*shape, dtype=torch.float64, device=self.device)
 
+    def _arg(self, t: Optional[torch.Tensor], n: int, name: str, at_least: bool = False):
+        """Pointer of a caller tensor after checking it holds exactly ``n`` float64 values
+        (``at_least``: n or more), contiguous, on this handle's device (None passes through)."""
+        if t is None:
+            return None
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name}: expected a torch tensor")
+        if t.device != self.device:
+            raise ValueError(f"{name}: on {t.device}, the handle is on {self.device}")
+        k = t.numel()
+        if k < n or (k != n and not at_least):
+            raise ValueError(f"{name}: {k} elements, {'at least ' if at_least else ''}{n} expected")
+        return _ptr(t)
+
     def update_density(self, P: torch.Tensor, v: Optional[torch.Tensor] = None,
                        prec: str = "fp64", atom_xyz=None, n_out=None, sums_out=None):
         """n [n_points] (caller order) and sums [n_sys, 3] = (N, E_V, E_T)."""
         n = self._new(self.n_points) if n_out is None else n_out
         sums = self._new(self.n_sys, 3) if sums_out is None else sums_out
         with torch.cuda.device(self.device):
-            self._check(self._L.aims_update_density(self._h, PRECISION[prec], self._xyz(atom_xyz),
-                                                    _ptr(P), _ptr(v), _ptr(n), _ptr(sums)))
+            self._check(self._L.aims_update_density(
+                self._h, PRECISION[prec], self._xyz(atom_xyz), self._arg(P, self.mat_elems, "P"),
+                self._arg(v, self.n_points, "v"), self._arg(n, self.n_points, "n_out"),
+                self._arg(sums, 3 * self.n_sys, "sums_out")))
         return n, sums
 
     def update_density_noalloc(self, P: torch.Tensor, v: Optional[torch.Tensor] = None,
@@ -118,8 +134,10 @@ class AimsGrid:
         n = self._new(self.n_points) if n_out is None else n_out
         sums = self._new(self.n_sys, 3) if sums_out is None else sums_out
         with torch.cuda.device(self.device):
-            self._check(self._L.aims_update_density_noalloc(self._h, PRECISION[prec], _ptr(P),
-                                                            _ptr(v), _ptr(n), _ptr(sums)))
+            self._check(self._L.aims_update_density_noalloc(
+                self._h, PRECISION[prec], self._arg(P, self.mat_elems, "P"),
+                self._arg(v, self.n_points, "v"), self._arg(n, self.n_points, "n_out"),
+                self._arg(sums, 3 * self.n_sys, "sums_out")))
         return n, sums
 
     def integrate_h(self, v: torch.Tensor, prec: str = "fp64", want_S: bool = False,
@@ -128,8 +146,9 @@ class AimsGrid:
         H = self._new(self.mat_elems) if H_out is None else H_out
         S = (self._new(self.mat_elems) if S_out is None else S_out) if want_S else None
         with torch.cuda.device(self.device):
-            self._check(self._L.aims_integrate_h(self._h, PRECISION[prec], self._xyz(atom_xyz),
-                                                 _ptr(v), _ptr(H), _ptr(S)))
+            self._check(self._L.aims_integrate_h(
+                self._h, PRECISION[prec], self._xyz(atom_xyz), self._arg(v, self.n_points, "v"),
+                self._arg(H, self.mat_elems, "H_out"), self._arg(S, self.mat_elems, "S_out")))
         return H, S
 
     def backward(self, P, v, gE, prec: str = "fp64", atom_xyz=None, want=("P", "v", "R")):
@@ -138,8 +157,10 @@ class AimsGrid:
         dR = self._new(self.n_atoms, 3) if "R" in want else None
         with torch.cuda.device(self.device):
             self._check(self._L.aims_integrate_h_backward(
-                self._h, PRECISION[prec], self._xyz(atom_xyz), _ptr(P), _ptr(v), _ptr(gE),
-                _ptr(dP), _ptr(dv), _ptr(dR)))
+                self._h, PRECISION[prec], self._xyz(atom_xyz), self._arg(P, self.mat_elems, "P"),
+                self._arg(v, self.n_points, "v"), self._arg(gE, 1, "gE", at_least=True),
+                self._arg(dP, self.mat_elems, "dE_dP"), self._arg(dv, self.n_points, "dE_dv"),
+                self._arg(dR, 3 * self.n_atoms, "dE_dR")))
         return dP, dv, dR
 
     def set_moving_grid(self, systems=None, sigma: float = 0.3, partition_a: float = 0.64):
@@ -151,6 +172,9 @@ class AimsGrid:
             owner = np.ascontiguousarray(s.pt_atom, dtype=np.int32)
             wgrid = np.ascontiguousarray(s.pt_wgrid, dtype=np.float64)
             Z = np.ascontiguousarray(s.atom_Z, dtype=np.float64)
+            npt, nat = len(self._systems[k].pt_xyz), len(self._systems[k].atom_xyz)
+            if owner.size != npt or wgrid.size != npt or Z.size != nat:
+                raise ValueError(f"system {k}: moving-grid arrays need {npt} points and {nat} atoms")
             m = AimsMovingGrid()
             m.pt_owner = _np_ptr(owner, c_int32)
             m.pt_wgrid = _np_ptr(wgrid, c_double)
@@ -167,16 +191,19 @@ class AimsGrid:
         dR = self._new(self.n_atoms, 3)
         sums = self._new(self.n_sys, 3) if sums_out is None else sums_out
         with torch.cuda.device(self.device):
-            self._check(self._L.aims_total_forces(self._h, PRECISION[prec], _ptr(P), _ptr(gE),
-                                                  _ptr(sums), _ptr(dR)))
+            self._check(self._L.aims_total_forces(
+                self._h, PRECISION[prec], self._arg(P, self.mat_elems, "P"),
+                self._arg(gE, 1, "gE", at_least=True), self._arg(sums, 3 * self.n_sys, "sums_out"),
+                self._arg(dR, 3 * self.n_atoms, "dE_dR")))
         return dR, sums
 
     def integrate_h_gga(self, v: torch.Tensor, u: torch.Tensor, prec: str = "fp64", H_out=None):
         """H_ij = sum_p w phi_i (v phi_j + t phi_j + u . grad phi_j), u [n_points, 3]."""
         H = self._new(self.mat_elems) if H_out is None else H_out
         with torch.cuda.device(self.device):
-            self._check(self._L.aims_integrate_h_gga(self._h, PRECISION[prec], _ptr(v), _ptr(u),
-                                                     _ptr(H)))
+            self._check(self._L.aims_integrate_h_gga(
+                self._h, PRECISION[prec], self._arg(v, self.n_points, "v"),
+                self._arg(u, 3 * self.n_points, "u"), self._arg(H, self.mat_elems, "H_out")))
         return H
 
     def xc_gga(self, n: torch.Tensor, grad_n: torch.Tensor, functional: str = "pbe"):
@@ -187,8 +214,10 @@ class AimsGrid:
         u = self._new(self.n_points, 3)
         sums = self._new(self.n_sys, 2)
         with torch.cuda.device(self.device):
-            self._check(self._L.aims_xc_gga(self._h, XC_FUNCTIONAL[functional], _ptr(n),
-                                            _ptr(grad_n), _ptr(v), _ptr(u), _ptr(sums)))
+            self._check(self._L.aims_xc_gga(
+                self._h, XC_FUNCTIONAL[functional], self._arg(n, self.n_points, "n"),
+                self._arg(grad_n, 3 * self.n_points, "grad_n"), self._arg(v, self.n_points, "v_out"),
+                self._arg(u, 3 * self.n_points, "u_out"), self._arg(sums, 2 * self.n_sys, "sums_out")))
         return v, u, sums
 
     def density_gradient(self, P: torch.Tensor, n_out=None, grad_out=None, want_n: bool = True):
@@ -196,7 +225,9 @@ class AimsGrid:
         n = (self._new(self.n_points) if n_out is None else n_out) if want_n else None
         grad = self._new(self.n_points, 3) if grad_out is None else grad_out
         with torch.cuda.device(self.device):
-            self._check(self._L.aims_density_gradient(self._h, _ptr(P), _ptr(n), _ptr(grad)))
+            self._check(self._L.aims_density_gradient(
+                self._h, self._arg(P, self.mat_elems, "P"), self._arg(n, self.n_points, "n_out"),
+                self._arg(grad, 3 * self.n_points, "grad_out")))
         return n, grad
 
     def set_hartree_grid(self, radial, l_max: int = 6, systems=None):
@@ -208,6 +239,9 @@ class AimsGrid:
             node, n_radial, r_map = radial[k]
             owner = np.ascontiguousarray(s.pt_atom, dtype=np.int32)
             node = np.ascontiguousarray(node, dtype=np.int32)
+            npt = len(self._systems[k].pt_xyz)
+            if owner.size != npt or node.size != npt:
+                raise ValueError(f"system {k}: Hartree grid arrays need {npt} points")
             h = AimsHartreeGrid()
             h.pt_owner = _np_ptr(owner, c_int32)
             h.pt_node = _np_ptr(node, c_int32)
@@ -221,7 +255,9 @@ class AimsGrid:
         v = self._new(self.n_points) if v_out is None else v_out
         E = self._new(self.n_sys) if E_out is None else E_out
         with torch.cuda.device(self.device):
-            self._check(self._L.aims_hartree(self._h, _ptr(n), _ptr(v), _ptr(E)))
+            self._check(self._L.aims_hartree(self._h, self._arg(n, self.n_points, "n"),
+                                             self._arg(v, self.n_points, "v_out"),
+                                             self._arg(E, self.n_sys, "E_out")))
         return v, E
 
     def xc(self, n: torch.Tensor, functional: str = "lda", v_out=None, sums_out=None):
@@ -230,8 +266,10 @@ class AimsGrid:
         v = self._new(self.n_points) if v_out is None else v_out
         sums = self._new(self.n_sys, 2) if sums_out is None else sums_out
         with torch.cuda.device(self.device):
-            self._check(self._L.aims_xc(self._h, XC_FUNCTIONAL[functional], _ptr(n), _ptr(v),
-                                        _ptr(sums)))
+            self._check(self._L.aims_xc(self._h, XC_FUNCTIONAL[functional],
+                                        self._arg(n, self.n_points, "n"),
+                                        self._arg(v, self.n_points, "v_out"),
+                                        self._arg(sums, 2 * self.n_sys, "sums_out")))
         return v, sums
 
     def density_matrix(self, H: torch.Tensor, S: torch.Tensor, n_electrons, kT: float = 0.0,
@@ -246,9 +284,11 @@ class AimsGrid:
         eps = self._new(int(sum(self.nb_sys))) if (want_eps and method == "eigen") else None
         mu = np.zeros(self.n_sys)
         with torch.cuda.device(self.device):
-            self._check(self._L.aims_density_matrix(self._h, DM_METHOD[method], _ptr(H), _ptr(S),
-                                                    _np_ptr(ne, c_double), float(kT), _ptr(P),
-                                                    _ptr(eps), _np_ptr(mu, c_double)))
+            self._check(self._L.aims_density_matrix(
+                self._h, DM_METHOD[method], self._arg(H, self.mat_elems, "H"),
+                self._arg(S, self.mat_elems, "S"), _np_ptr(ne, c_double), float(kT),
+                self._arg(P, self.mat_elems, "P_out"), self._arg(eps, int(sum(self.nb_sys)), "eps_out"),
+                _np_ptr(mu, c_double)))
         return P, eps, mu
 
     def last_purify_products(self) -> int:
@@ -307,9 +347,11 @@ class AimsGrid:
             return None
         if isinstance(atom_xyz, torch.Tensor):
             if atom_xyz.is_cuda:
-                return _ptr(atom_xyz.contiguous())
+                return self._arg(atom_xyz.contiguous(), 3 * self.n_atoms, "atom_xyz")
             atom_xyz = atom_xyz.numpy()
         self._xyz_keep = np.ascontiguousarray(atom_xyz, dtype=np.float64)
+        if self._xyz_keep.size != 3 * self.n_atoms:
+            raise ValueError(f"atom_xyz: {self._xyz_keep.size} values, {3 * self.n_atoms} expected")
         return c_void_p(self._xyz_keep.ctypes.data)
 
     def close(self):
@@ -332,9 +374,11 @@ class StepGraph:
         self._keep = (P, v, n_out, sums_out, H_out)
         h = c_void_p()
         with torch.cuda.device(grid.device):
-            grid._check(grid._L.aims_step_graph_create(grid._h, PRECISION[prec], _ptr(P), _ptr(v),
-                                                       _ptr(n_out), _ptr(sums_out), _ptr(H_out),
-                                                       byref(h)))
+            grid._check(grid._L.aims_step_graph_create(
+                grid._h, PRECISION[prec], grid._arg(P, grid.mat_elems, "P"),
+                grid._arg(v, grid.n_points, "v"), grid._arg(n_out, grid.n_points, "n_out"),
+                grid._arg(sums_out, 3 * grid.n_sys, "sums_out"),
+                grid._arg(H_out, grid.mat_elems, "H_out"), byref(h)))
         self._g = h
 
     def launch(self):
@@ -360,6 +404,13 @@ class AimsEnergy(torch.autograd.Function):
     def forward(ctx, grid: AimsGrid, P, v, R, prec="fp64"):
         if grid.n_sys != 1:
             raise ValueError("AimsEnergy handles one system per handle")
+        # The backward's dE/dR takes X = Phi P and Y = (T Phi) P, which is the gradient only for
+        # a symmetric P (a general P needs Phi (P + P^T)/2 and (T Phi) P^T), so another P is refused.
+        nb = grid.nb_sys[0]
+        Pm = P.detach().reshape(nb, nb)
+        scale = float(Pm.abs().max()) if Pm.numel() else 0.0
+        if Pm.numel() and float((Pm - Pm.T).abs().max()) > 1e-12 * max(scale, 1e-300):
+            raise ValueError("AimsEnergy needs a symmetric P (max|P - P^T| above 1e-12 max|P|)")
         _, sums = grid.update_density(P.detach().contiguous(), v.detach().contiguous(), prec=prec,
                                       atom_xyz=R.detach())
         ctx.grid, ctx.prec = grid, prec

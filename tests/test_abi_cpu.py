@@ -127,3 +127,27 @@ def test_basis_count_limit(lib):
     assert lib.aims_grid_setup(ctypes.byref(s), 0, None, ctypes.byref(h)) == -5
     assert h.value is None
     assert "basis functions" in lib.aims_last_error(None).decode()
+
+
+def test_binding_refuses_wrong_sizes_on_host():
+    """The binding checks every caller tensor (element count, dtype, contiguity, device) before
+    it reaches the C ABI, so a short buffer never becomes an out-of-bounds device access."""
+    import torch
+    from paper_2208_12335_amd.grid import AimsGrid
+    g = object.__new__(AimsGrid)
+    g.device = torch.device("cpu")
+    ok = torch.zeros(12, dtype=torch.float64)
+    assert g._arg(ok, 12, "x") is not None
+    assert g._arg(None, 12, "x") is None
+    assert g._arg(torch.zeros(13, dtype=torch.float64), 12, "gE", at_least=True) is not None
+    with pytest.raises(ValueError, match="11 elements"):
+        g._arg(torch.zeros(11, dtype=torch.float64), 12, "P")
+    with pytest.raises(ValueError, match="13 elements"):
+        g._arg(torch.zeros(13, dtype=torch.float64), 12, "H_out")
+    with pytest.raises(TypeError):
+        g._arg(torch.zeros(12, dtype=torch.float32), 12, "v")
+    with pytest.raises(ValueError, match="contiguous"):
+        g._arg(torch.zeros(12, 2, dtype=torch.float64)[:, 0], 12, "v")
+    g.device = torch.device("cuda", 0)
+    with pytest.raises(ValueError, match="handle is on"):
+        g._arg(ok, 12, "P")

@@ -113,3 +113,39 @@ def test_autograd_function(gpu):
     E2 = AimsEnergy.apply(g, P.detach(), v.detach(), R2, "fp64")
     ref2 = GridOracle(inst.moved(R2.detach().cpu().numpy())).energy(inst.P, inst.v)
     assert abs(E2.item() - ref2) < 1e-10 * abs(ref2)
+
+
+def test_short_buffers_and_asymmetric_P_refused(gpu):
+    """Caller buffers shorter than the call needs are refused on the host, by the binding and by
+    the C ABI itself (allocation range of the device pointer), before any launch; AimsEnergy
+    refuses a density matrix that is not symmetric (its backward assumes P = P^T)."""
+    import ctypes
+    from paper_2208_12335_amd import _lib
+    inst = synth.make_instance("c1")
+    g = AimsGrid(inst, device=gpu.index)
+    P = torch.from_numpy(inst.P).to(gpu).reshape(-1)
+    v = torch.from_numpy(inst.v).to(gpu)
+    with pytest.raises(ValueError):
+        g.update_density(P[:-1].contiguous(), v)
+    L = _lib.load()
+    # a buffer of its own allocation, half of n_points, straight through the C ABI
+    hip = ctypes.CDLL("libamdhip64.so")
+    raw = ctypes.c_void_p()
+    assert hip.hipMalloc(ctypes.byref(raw), ctypes.c_size_t(8 * (inst.n_points // 2))) == 0
+    try:
+        sums = torch.empty(3, dtype=torch.float64, device=gpu)
+        st = L.aims_update_density(g._h, 0, None, ctypes.c_void_p(P.data_ptr()),
+                                   ctypes.c_void_p(v.data_ptr()), raw, ctypes.c_void_p(sums.data_ptr()))
+        msg = L.aims_last_error(g._h).decode()
+        print(f"[abi] short n_out: status {st}, {msg}", flush=True)
+        assert st == _lib.AIMS_ERR_ARG and "n_out" in msg
+    finally:
+        torch.cuda.synchronize()
+        hip.hipFree(raw)
+    nb = inst.n_basis
+    Pa = inst.P.copy()
+    Pa[0, 1] += 1e-3
+    with pytest.raises(ValueError, match="symmetric"):
+        AimsEnergy.apply(g, torch.from_numpy(Pa).to(gpu).reshape(-1), v,
+                         torch.from_numpy(inst.atom_xyz).to(gpu).reshape(-1, 3))
+    assert nb > 0

@@ -106,9 +106,15 @@ def test_positions_and_errors(gpu, c1):
     with pytest.raises(AimsError) as e:
         g.update_density(P, v, atom_xyz=c1.atom_xyz + np.array([0.5, 0, 0]))
     assert "STALE" in str(e.value)
-    with pytest.raises(AimsError) as e:
-        g.update_density(P.cpu(), v)                       # host pointer
-    assert "ARG" in str(e.value)
+    with pytest.raises(ValueError):
+        g.update_density(P.cpu(), v)                       # host tensor: refused by the binding
+    import ctypes
+    from paper_2208_12335_amd import _lib
+    Ph = P.cpu()                                           # and by the C ABI itself
+    st = g._L.aims_update_density(g._h, 0, None, ctypes.c_void_p(Ph.data_ptr()),
+                                  ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(v.data_ptr()),
+                                  ctypes.c_void_p(P.data_ptr()))
+    assert st == _lib.AIMS_ERR_ARG and "device memory" in g._L.aims_last_error(g._h).decode()
     # moved positions (within the margin) agree with the oracle at those positions
     X = c1.atom_xyz.copy()
     X[1, 0] += 0.004
