@@ -544,6 +544,8 @@ void build_set(aims_grid* g, BatchSet& bs, int merge, bool density, int ratio = 
       }
     });
     for (int b = 0; b < nseg; ++b) {
+      // each batch's column list starts on a multiple of 4 entries (16-byte index loads)
+      while (bs.batch_cols.size() % 4) bs.batch_cols.push_back(0);
       BatchDesc d{};
       d.pt_off = (int32_t)segs[b].first;
       d.n_p = (int32_t)(segs[b].second - segs[b].first);
@@ -565,6 +567,8 @@ void build_set(aims_grid* g, BatchSet& bs, int merge, bool density, int ratio = 
       bs.sum_nb2 += (double)d.n_b * d.n_b;
     }
   }
+  // tail padding: index loads of a K chunk may read up to 31 entries past a batch's list
+  bs.batch_cols.insert(bs.batch_cols.end(), 32, 0);
   if ((int64_t)bs.batch_cols.size() > (int64_t)INT32_MAX) fail(AIMS_ERR_UNSUPPORTED, "too many batch columns");
 
   form_groups(bs, scratch_budget_elems());

@@ -377,7 +377,7 @@ density_i8_tile(int item, const TileItem* __restrict__ items, const BatchDesc* _
                 const uint64_t* __restrict__ slab2, const int32_t* __restrict__ ex1,
                 const int32_t* __restrict__ ex2, const int32_t* __restrict__ fexp,
                 double* __restrict__ n_sorted, double* __restrict__ et_batch,
-                uint64_t* __restrict__ lds) {
+                uint64_t* __restrict__ lds, int* __restrict__ rowc) {
   const TileItem it = items[item];
   const BatchDesc d = batches[it.batch];
   const SystemDesc sys = systems[d.sys];
@@ -396,7 +396,17 @@ density_i8_tile(int item, const TileItem* __restrict__ items, const BatchDesc* _
 #pragma unroll
   for (int L = 0; L < kLevelsD; ++L) acc[L] = v16i{};
 
-  // A staging: row ra = tid / 4, k octet ka = tid % 4 (gathered P words)
+  // the epilogue's row constants, read once per tile: exponent of the row of P, and that plus
+  // the row's balancing exponent (ordered before the epilogue by the K loop's barriers)
+  if (tid < 64) {
+    const int j = j0 + tid;
+    const int gj = (int)sys.row_off + cols[j < nb ? j : 0];
+    rowc[tid] = eP[gj];
+    rowc[64 + tid] = eP[gj] + fexp[gj];
+  }
+
+  // A staging: row ra = tid / 4, k octet ka = tid % 4 (gathered P words; the batch's column
+  // list starts 16-byte aligned and is padded, so its indices come in two 16-byte loads)
   const int ra = tid >> 2, ka = tid & 3;
   const bool rok = j0 + ra < nb;
   const uint32_t prow = (uint32_t)cols[rok ? j0 + ra : 0] * (uint32_t)sys.nb;
@@ -405,11 +415,14 @@ density_i8_tile(int item, const TileItem* __restrict__ items, const BatchDesc* _
   const bool pok = p0 + pb < ldp;
   uint64_t av[8], bv[8];
   auto fetch = [&](int kc) {
+    const int4 c0 = *reinterpret_cast<const int4*>(cols + kc + 8 * ka);
+    const int4 c1 = *reinterpret_cast<const int4*>(cols + kc + 8 * ka + 4);
+    const int ci[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
       const int k = kc + 8 * ka + m;
       const bool ok = rok && k < nb;
-      const uint64_t x = Pm[prow + (uint32_t)cols[k < nb ? k : nb - 1]];
+      const uint64_t x = Pm[prow + (uint32_t)(k < nb ? ci[m] : cols[0])];
       av[m] = ok ? x : 0ull;
     }
 #pragma unroll
@@ -453,14 +466,22 @@ density_i8_tile(int item, const TileItem* __restrict__ items, const BatchDesc* _
   double sn = 0.0, se = 0.0;
   if (live && p < d.n_p) {
     const int e1 = ex1[d.pt_off + p], e2 = ex2[d.pt_off + p];
+    uint64_t f1[16], f2[16];             // the epilogue's basis digits, loaded together
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int j = j0 + 32 * wm + acc_row32(lane, r);
-      if (j < nb) {
-        const int gj = (int)sys.row_off + cols[j];
-        const double x = ldexp(level_sum<kLevelsD>(acc, r), eP[gj] + e1);
-        sn += x * from_digits(S1[(size_t)j * ldp + p], e1 + fexp[gj]);
-        se += x * from_digits(S2[(size_t)j * ldp + p], e2);
+      const size_t o = (size_t)(j < nb ? j : 0) * ldp + p;
+      f1[r] = S1[o];
+      f2[r] = S2[o];
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int jl = 32 * wm + acc_row32(lane, r);
+      if (j0 + jl < nb) {
+        const double x = level_sum<kLevelsD>(acc, r);
+        // X phi = 2^(eP + e1) x * 2^(e1 + f) digits(phi);  X t phi = 2^(eP + e1) x * 2^e2 digits
+        sn += ldexp(x * from_digits(f1[r], 0), rowc[64 + jl] + 2 * e1);
+        se += ldexp(x * from_digits(f2[r], 0), rowc[jl] + e1 + e2);
       }
     }
     se *= pts[d.pt_off + p].w;
@@ -485,9 +506,10 @@ density_i8_kernel(const TileItem* __restrict__ items, int n_items, const BatchDe
                   double* __restrict__ n_sorted, double* __restrict__ et_batch,
                   int* __restrict__ queue) {
   __shared__ __attribute__((aligned(16))) uint64_t lds[4 * kOpWords];
+  __shared__ int rowc[128];
   run_items(n_items, queue, [&](int item) {
     density_i8_tile(item, items, batches, systems, pts, batch_cols, P8, eP, slab1, slab2, ex1, ex2,
-                    fexp, n_sorted, et_batch, lds);
+                    fexp, n_sorted, et_batch, lds, rowc);
   });
 }
 
@@ -497,7 +519,7 @@ hs_i8_tile(int item, const TileItem* __restrict__ items, const BatchDesc* __rest
            const SystemDesc* __restrict__ systems, const int32_t* __restrict__ batch_cols,
            const uint64_t* __restrict__ slab1, const uint64_t* __restrict__ slab2,
            const int32_t* __restrict__ ex1, const int32_t* __restrict__ ex2,
-           double* __restrict__ out, uint64_t* __restrict__ lds) {
+           double* __restrict__ out, uint64_t* __restrict__ lds, int* __restrict__ rowc) {
   const TileItem it = items[item];
   const BatchDesc d = batches[it.batch];
   const SystemDesc sys = systems[d.sys];
@@ -512,6 +534,11 @@ hs_i8_tile(int item, const TileItem* __restrict__ items, const BatchDesc* __rest
   v16i acc[kLevelsH];
 #pragma unroll
   for (int L = 0; L < kLevelsH; ++L) acc[L] = v16i{};
+  if (tid < 64) {                       // row constants of the epilogue: H row, exponent
+    const int i = i0 + tid < nb ? i0 + tid : 0;
+    rowc[tid] = cols[i];
+    rowc[64 + tid] = ex1[d.col_off + i];
+  }
 
   // staging: row r = tid / 4 of both operands, point octet q = tid % 4 (64 contiguous bytes)
   const int r = tid >> 2, q = tid & 3;
@@ -564,10 +591,10 @@ hs_i8_tile(int item, const TileItem* __restrict__ items, const BatchDesc* __rest
   const int ej = ex2[d.col_off + j];
 #pragma unroll
   for (int rr = 0; rr < 16; ++rr) {
-    const int i = i0 + 32 * wm + acc_row32(lane, rr);
-    if (i < nb)
-      unsafeAtomicAdd(O + (size_t)cols[i] * sys.nb + gj,
-                      ldexp(level_sum<kLevelsH>(acc, rr), ex1[d.col_off + i] + ej));
+    const int il = 32 * wm + acc_row32(lane, rr);
+    if (i0 + il < nb)
+      unsafeAtomicAdd(O + (size_t)rowc[il] * sys.nb + gj,
+                      ldexp(level_sum<kLevelsH>(acc, rr), rowc[64 + il] + ej));
   }
 }
 
@@ -578,8 +605,9 @@ hs_i8_kernel(const TileItem* __restrict__ items, int n_items, const BatchDesc* _
              const int32_t* __restrict__ ex1, const int32_t* __restrict__ ex2,
              double* __restrict__ out, int* __restrict__ queue) {
   __shared__ __attribute__((aligned(16))) uint64_t lds[4 * kOpWords];
+  __shared__ int rowc[128];
   run_items(n_items, queue, [&](int item) {
-    hs_i8_tile(item, items, batches, systems, batch_cols, slab1, slab2, ex1, ex2, out, lds);
+    hs_i8_tile(item, items, batches, systems, batch_cols, slab1, slab2, ex1, ex2, out, lds, rowc);
   });
 }
 
