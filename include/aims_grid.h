@@ -330,9 +330,22 @@ typedef struct {
   int32_t density_pblocks;
   int32_t persistent;
   int32_t h_flops_per_atomic;
+  /* Tile shapes by (points, basis count) bucket.  A density batch of n_b functions falls in
+   * bucket min(7, (n_b - 1) / 64); density_bucket_pblocks[b] (0, or 2..5) replaces
+   * density_pblocks for the batches of bucket b.  An H / S batch falls in bucket
+   * 2 min(7, (n_b - 1) / 64) + (1 if n_b mod 64 is in 1..32); bit b of h_tile32_mask runs that
+   * bucket on 32 x 32 tiles instead of 64 x 64 (AIMS_FP64 and AIMS_FP32 only). */
+  int32_t h_tile32_mask;
+  int32_t density_bucket_pblocks[8];
 } aims_tuning;
 aims_status aims_get_tuning(const aims_grid *g, aims_precision prec, aims_tuning *out);
 aims_status aims_set_tuning(aims_grid *g, aims_precision prec, const aims_tuning *t);
+
+/* Batches and algorithmic flops (sum of 2 n_p n_b^2) per tile-shape bucket, for an autotuner:
+ * which = 0, the density partition (8 buckets); which = 1, the precision's current H partition
+ * (16 buckets).  batches_out and flops_out are HOST arrays of that many entries. */
+aims_status aims_bucket_stats(aims_grid *g, aims_precision prec, int32_t which, int64_t *batches_out,
+                              double *flops_out);
 
 /* Work statistics: number of batches, sum_b n_p n_b^2 (flops = 4x this per s.c.f. step), and
  * sum_b n_b^2 (entries scattered into H per call); any pointer may be NULL. */

@@ -40,7 +40,8 @@ class AimsSystem(ctypes.Structure):
 
 class AimsTuning(ctypes.Structure):
     _fields_ = [("h_merge", c_int32), ("density_pblocks", c_int32), ("persistent", c_int32),
-                ("h_flops_per_atomic", c_int32)]
+                ("h_flops_per_atomic", c_int32), ("h_tile32_mask", c_int32),
+                ("density_bucket_pblocks", c_int32 * 8)]
 
 
 class AimsHartreeGrid(ctypes.Structure):
@@ -80,6 +81,7 @@ SIGNATURES = {
     "aims_get_tuning": (c_int, [c_void_p, c_int, POINTER(AimsTuning)]),
     "aims_set_tuning": (c_int, [c_void_p, c_int, POINTER(AimsTuning)]),
     "aims_work_stats": (c_int, [c_void_p, POINTER(c_int64), POINTER(c_double), POINTER(c_double)]),
+    "aims_bucket_stats": (c_int, [c_void_p, c_int, c_int32, POINTER(c_int64), POINTER(c_double)]),
     "aims_n_basis": (c_int64, [c_void_p]),
     "aims_n_points": (c_int64, [c_void_p]),
     "aims_n_atoms": (c_int32, [c_void_p]),

@@ -13,9 +13,17 @@ integration scheme itself is fixed by the grid partition):
 
 The density pass depends only on (pblocks, persistent) and the H pass only on its partition
 (h_merge or h_flops_per_atomic) and persistent, so the tuner times the two passes separately and picks, per ``persistent`` value,
-the best of each, then the better ``persistent``.  Results are cached in a JSON file keyed by
-(device architecture, precision, workload bucket) so later handles of a similar workload skip
-the measurement.
+the best of each, then the better ``persistent``.
+
+Then the tile shapes are refined per (points, basis count) bucket (``refine_buckets``): the
+density batches of each basis-size bucket get their own point-tile cap
+(``density_bucket_pblocks``), and each H bucket (basis-size class x whether the last 64-wide
+tile row is at most half full) runs 64 x 64 or 32 x 32 tiles (``h_tile32_mask``, FP64 and
+FP32).  Buckets are visited in decreasing order of their flops, one at a time, keeping a change
+only when the pass gets faster by more than ``min_gain``.
+
+Results are cached in a JSON file keyed by (device architecture, precision, workload bucket) so
+later handles of a similar workload skip the measurement.
 """
 from __future__ import annotations
 
@@ -23,13 +31,15 @@ import json
 import math
 import os
 import tempfile
-from typing import Callable, Dict, Iterable, Optional, Tuple
+from typing import Callable, Dict, Iterable, Optional, Sequence, Tuple
 
 DENSITY_PBLOCKS = (2, 3, 4, 5)
 H_MERGE = (0, 1, 2, 3)
 H_RATIO = (64, 256, 1024, 4096)
 PERSISTENT = (0, 1)
-KNOBS = ("h_merge", "density_pblocks", "persistent", "h_flops_per_atomic")
+KNOBS = ("h_merge", "density_pblocks", "persistent", "h_flops_per_atomic", "h_tile32_mask",
+         "density_bucket_pblocks")
+BASE_KNOBS = KNOBS[:4]
 
 
 def default_cache_path() -> str:
@@ -81,6 +91,45 @@ def search(cost: Callable[[str, dict], float],
     return best, log
 
 
+def refine_buckets(cost: Callable[[str, dict], float], base: dict, density_flops: Sequence[float],
+                   h_flops: Sequence[float], pblocks: Iterable[int] = DENSITY_PBLOCKS,
+                   allow_h32: bool = True, min_gain: float = 0.005) -> Tuple[dict, Dict[str, float]]:
+    """Per-bucket tile shapes on top of ``base`` by coordinate descent over the buckets that
+    hold work.  ``cost(kind, cfg)`` times pass ``kind`` under the full tuning ``cfg``."""
+    cfg = dict(base)
+    cfg.setdefault("h_tile32_mask", 0)
+    cfg["density_bucket_pblocks"] = list(cfg.get("density_bucket_pblocks") or [0] * len(density_flops))
+    log: Dict[str, float] = {}
+    pbl = list(pblocks)
+    if len(pbl) > 1:
+        t_best = float(cost("density", cfg))
+        log["density base"] = t_best
+        for b in sorted(range(len(density_flops)), key=lambda k: -density_flops[k]):
+            if density_flops[b] <= 0:
+                continue
+            for pb in pbl:
+                if pb == (cfg["density_bucket_pblocks"][b] or cfg["density_pblocks"]):
+                    continue
+                trial = dict(cfg, density_bucket_pblocks=list(cfg["density_bucket_pblocks"]))
+                trial["density_bucket_pblocks"][b] = pb
+                t = float(cost("density", trial))
+                log[f"density bucket {b} pblocks={pb}"] = t
+                if t < t_best * (1.0 - min_gain):
+                    cfg, t_best = trial, t
+    if allow_h32:
+        t_best = float(cost("h", cfg))
+        log["h base"] = t_best
+        for b in sorted(range(len(h_flops)), key=lambda k: -h_flops[k]):
+            if h_flops[b] <= 0:
+                continue
+            trial = dict(cfg, h_tile32_mask=cfg["h_tile32_mask"] ^ (1 << b))
+            t = float(cost("h", trial))
+            log[f"h bucket {b} tile32={(trial['h_tile32_mask'] >> b) & 1}"] = t
+            if t < t_best * (1.0 - min_gain):
+                cfg, t_best = trial, t
+    return cfg, log
+
+
 def load_cache(path: str) -> dict:
     try:
         with open(path) as f:
@@ -104,7 +153,7 @@ def store_cache(path: str, key: str, entry: dict) -> None:
 def autotune(grid, P, v, prec: str = "fp64", *, reps: int = 3, cache: Optional[str] = None,
              force: bool = False, density_pblocks: Iterable[int] = DENSITY_PBLOCKS,
              h_merge: Iterable[int] = H_MERGE, persistent: Iterable[int] = PERSISTENT,
-             h_ratio: Iterable[int] = H_RATIO) -> dict:
+             h_ratio: Iterable[int] = H_RATIO, buckets: bool = True) -> dict:
     """Time the candidates on ``grid``'s device with inputs P, v (device tensors), apply the
     best tuning for ``prec`` and return {tuning..., "source": "cache"|"measured", "key": ...,
     "ms": {...}}.  ``cache=""`` disables the cache file."""
@@ -137,7 +186,9 @@ def autotune(grid, P, v, prec: str = "fp64", *, reps: int = 3, cache: Optional[s
         grid.set_tuning(h_merge=cfg.get("h_merge", cur["h_merge"]),
                         h_flops_per_atomic=cfg.get("h_flops_per_atomic", cur["h_flops_per_atomic"]),
                         density_pblocks=cfg.get("density_pblocks", cur["density_pblocks"]),
-                        persistent=cfg["persistent"], prec=prec)
+                        persistent=cfg["persistent"], prec=prec,
+                        h_tile32_mask=cfg.get("h_tile32_mask", 0),
+                        density_bucket_pblocks=cfg.get("density_bucket_pblocks", [0] * 8))
         run(kind)                                   # warm (first use builds the work lists)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -151,7 +202,15 @@ def autotune(grid, P, v, prec: str = "fp64", *, reps: int = 3, cache: Optional[s
     if prec == "int8x7":            # its density tiles always span 64 points
         density_pblocks = (2,)
     best, log = search(cost, density_pblocks, h_merge, persistent, h_ratio)
+    best = dict(best, h_tile32_mask=0, density_bucket_pblocks=[0] * 8)
     grid.set_tuning(prec=prec, **best)
+    if buckets:
+        _, dfl = grid.bucket_stats(prec, "density")
+        _, hfl = grid.bucket_stats(prec, "h")
+        best, blog = refine_buckets(cost, best, dfl, hfl, density_pblocks,
+                                    allow_h32=prec in ("fp64", "fp32"))
+        log.update(blog)
+        grid.set_tuning(prec=prec, **best)
     entry = dict(best, ms=log)
     if path:
         store_cache(path, key, entry)

@@ -37,6 +37,7 @@ thread_local std::string g_setup_error = "no error";
 // code it names a host-side stand-in); it uses the device address that hipGetSymbolAddress
 // returns, taken once per device at set-up with that device current.
 constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+constexpr int kDensityBuckets = 8;   // basis-size classes of 64 functions (the tile-shape buckets)
 static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
 // ---------------------------------------------------------------------------------------------
@@ -179,7 +180,7 @@ bool is_device_ptr(const void* p) {
 // bisection stopped `merge` levels earlier), which trades a few more flops for fewer FP64
 // scatter-adds into H.
 struct ItemList {
-  int pblocks = 0;                 // density: a tile spans up to 32 * pblocks points; 0 = H tiles
+  uint64_t key = 0;                // tile shapes of the list (tile_key)
   std::vector<TileItem> items;
   struct Run {
     int nbn;                       // point blocks of the kernel variant (density), 0 for H
@@ -241,6 +242,8 @@ struct aims_grid {
   int h_ratio[4] = {0, 0, 0, 0};              // per precision: > 0 selects the cost-model H partition
   int d_pblocks[4] = {2, 5, 5, 2};            // per precision: density point-tile cap (int8: 64)
   int persistent[4] = {0, 0, 0, 0};           // per precision: persistent tile launches
+  int32_t d_bucket_pblocks[4][kDensityBuckets] = {};   // per precision and basis-size bucket (0 = d_pblocks)
+  uint32_t h_tile32[4] = {0, 0, 0, 0};        // per precision: H buckets on 32 x 32 tiles (FP64, FP32)
   int* d_queue = nullptr;                     // 8 work counters per tiled launch of one call
   size_t queue_cap = 0;                       // counters allocated
   int nblk_finish = 64;
@@ -650,22 +653,46 @@ int density_nbn(int n_p, int cap) {
 
 // Tile work list of a batch set: square 64 x 64 tiles for the H kernel, (64 rows x 32 nbn
 // points) tiles for the density kernel, grouped per kernel variant within each batch group.
-ItemList& items_for(aims_grid* g, BatchSet& bs, int pblocks, bool counters = true) {
-  if (!bs.density) pblocks = 0;
+// Tile shapes by (points, basis count) bucket.  The density pass buckets its batches by basis
+// count, kDensityBuckets classes of 64 functions (the last open-ended); each class has its own
+// point-tile cap.  The H / S pass buckets by basis count class and by whether the last 64-wide
+// tile row is at most half full (n_b mod 64 in 1..32); each bucket runs 64 x 64 or 32 x 32
+// tiles.  The batches of one bucket run as one launch per group of batches.
+int density_bucket(int n_b) { return std::min(kDensityBuckets - 1, std::max(0, (n_b - 1) / 64)); }
+int h_bucket(int n_b) {
+  const int r = n_b % 64;
+  return 2 * std::min(kDensityBuckets - 1, std::max(0, (n_b - 1) / 64)) + (r != 0 && r <= 32 ? 1 : 0);
+}
+
+// Key of a work list: density -- the default cap (4 bits) and the per-bucket caps (4 bits each,
+// 0 = default); H -- the mask of 32 x 32 buckets, tagged by bit 63.
+uint64_t density_key(int pblocks, const int32_t* bucket_pblocks) {
+  uint64_t k = (uint64_t)pblocks;
+  for (int b = 0; b < kDensityBuckets; ++b) k |= (uint64_t)(bucket_pblocks ? bucket_pblocks[b] : 0) << (4 + 4 * b);
+  return k;
+}
+uint64_t h_key(uint32_t mask) { return (1ull << 63) | mask; }
+
+ItemList& tile_list(aims_grid* g, BatchSet& bs, uint64_t key, bool counters = true) {
   for (auto& l : bs.lists)
-    if (l->pblocks == pblocks) return *l;
+    if (l->key == key) return *l;
   std::unique_ptr<ItemList> L(new ItemList());
-  L->pblocks = pblocks;
+  L->key = key;
+  const bool hlist = (key >> 63) != 0;
   for (const auto& gr : bs.groups) {
     std::vector<std::vector<TileItem>> per(6);
     for (int b = gr.b0; b < gr.b1; ++b) {
       const BatchDesc& d = bs.batches[b];
-      const int tb = (d.n_b + kTile - 1) / kTile;
-      if (!bs.density) {
+      if (hlist) {
+        const bool t32 = (key >> h_bucket(d.n_b)) & 1u;
+        const int te = t32 ? 32 : 64;
+        const int tb = (d.n_b + te - 1) / te;
         for (int ti = 0; ti < tb; ++ti)
-          for (int tj = 0; tj < tb; ++tj) per[0].push_back(TileItem{b, (int16_t)ti, (int16_t)tj});
+          for (int tj = 0; tj < tb; ++tj) per[t32 ? 1 : 0].push_back(TileItem{b, (int16_t)ti, (int16_t)tj});
       } else {
-        const int nbn = density_nbn(d.n_p, pblocks);
+        const int tb = (d.n_b + kTile - 1) / kTile;
+        const int cap_b = (int)((key >> (4 + 4 * density_bucket(d.n_b))) & 15u);
+        const int nbn = density_nbn(d.n_p, cap_b ? cap_b : (int)(key & 15u));
         const int tp = (d.n_p + 32 * nbn - 1) / (32 * nbn);
         for (int ti = 0; ti < tb; ++ti)
           for (int tj = 0; tj < tp; ++tj) per[nbn].push_back(TileItem{b, (int16_t)ti, (int16_t)tj});
@@ -691,13 +718,26 @@ ItemList& items_for(aims_grid* g, BatchSet& bs, int pblocks, bool counters = tru
   return *bs.lists.back();
 }
 
+// The density list with one cap for every bucket (the allocation-free path, set-up) and the
+// lists a precision's tuning selects.
+ItemList& items_for(aims_grid* g, BatchSet& bs, int pblocks, bool counters = true) {
+  return tile_list(g, bs, density_key(pblocks, nullptr), counters);
+}
+uint64_t dens_key_of(const aims_grid* g, int prec) {
+  if (prec == AIMS_INT8X7) return density_key(2, nullptr);     // 64-point tiles only
+  return density_key(g->d_pblocks[prec], g->d_bucket_pblocks[prec]);
+}
+uint64_t h_key_of(const aims_grid* g, int prec) {
+  return h_key(prec == AIMS_FP64 || prec == AIMS_FP32 ? g->h_tile32[prec] : 0u);
+}
+
 BatchSet& hset(aims_grid* g, int merge, int ratio = 0) {
   if (ratio > 0) merge = 0;
   for (auto& p : g->hsets)
     if (p->merge == merge && p->ratio == ratio) return *p;
   std::unique_ptr<BatchSet> bs(new BatchSet());
   build_set(g, *bs, merge, false, ratio);
-  items_for(g, *bs, 0);
+  tile_list(g, *bs, h_key(0));
   g->hsets.push_back(std::move(bs));
   return *g->hsets.back();
 }
@@ -1052,10 +1092,10 @@ void run_density(aims_grid* g, aims_precision prec, const T* P, const double* v,
   const ItemList* Lp = nullptr;
   if (noalloc) {
     for (auto& l : bs.lists)
-      if (l->pblocks == pblocks) Lp = l.get();
+      if (l->key == density_key(pblocks, nullptr)) Lp = l.get();
     if (!Lp) fail(AIMS_ERR_ARG, "allocation-free work list missing");
   } else {
-    Lp = &items_for(g, bs, pblocks);
+    Lp = &tile_list(g, bs, dens_key_of(g, prec));
   }
   const ItemList& L = *Lp;
   void* slab1 = noalloc ? g->na_scratch : g->d_slab1;
@@ -1109,7 +1149,7 @@ void run_hs(aims_grid* g, aims_precision prec, int mode, const double* v, double
             const double* u = nullptr) {
   hipStream_t st = g->stream;
   BatchSet& bs = hset(g, g->h_merge[prec], g->h_ratio[prec]);
-  const ItemList& L = items_for(g, bs, 0);
+  const ItemList& L = tile_list(g, bs, h_key_of(g, prec));
   hipchk(launch_fill(out, (size_t)g->mat_total, 0.0, st), "fill H");
   QueueSeq qs(g, L, prec);
   for (size_t gi = 0; gi < bs.groups.size(); ++gi) {
@@ -1135,7 +1175,8 @@ void run_hs(aims_grid* g, aims_precision prec, int mode, const double* v, double
             return launch_vector_term<T>(bs.dv, gr.b0, nbt, u, s2, st);
           });
         timed(g, kProfHS, gr.flops, "hs", [&] {
-          return launch_hs<T>(bs.dv, L.d_items + run.i0, nit, s1, s2, out, st, qs.next());
+          return launch_hs<T>(bs.dv, L.d_items + run.i0, nit, s1, s2, out, st, qs.next(),
+                              run.nbn ? 32 : 64);
         });
       }
     }
@@ -1167,7 +1208,7 @@ void run_density_i8(aims_grid* g, const double* P, const double* v, double* n_ou
   hipStream_t st = g->stream;
   BatchSet& bs = g->dens;
   prepare_i8(g, nullptr);
-  const ItemList& L = items_for(g, bs, g->d_pblocks[AIMS_INT8X7]);
+  const ItemList& L = tile_list(g, bs, dens_key_of(g, AIMS_INT8X7));
   int32_t* ex1 = g->d_pexp;
   int32_t* ex2 = g->d_pexp + g->n_points;
   uint64_t* s1 = (uint64_t*)g->d_slab1;
@@ -1205,7 +1246,7 @@ void run_hs_i8(aims_grid* g, int mode, const double* v, double* out) {
   hipStream_t st = g->stream;
   BatchSet& bs = hset(g, g->h_merge[AIMS_INT8X7], g->h_ratio[AIMS_INT8X7]);
   prepare_i8(g, &bs);
-  const ItemList& L = items_for(g, bs, 0);
+  const ItemList& L = tile_list(g, bs, h_key(0));
   int32_t* ex1 = bs.d_colexp;
   int32_t* ex2 = bs.d_colexp + bs.batch_cols.size();
   uint64_t* s1 = (uint64_t*)g->d_slab1;
@@ -1584,7 +1625,7 @@ aims_status aims_integrate_h_backward(aims_grid* g, aims_precision prec, const d
     hipchk(launch_fill(g->d_n_sorted, (size_t)g->n_points, 0.0, st), "fill n");
     hipchk(launch_fill(g->d_et_batch, bs.batches.size(), 0.0, st), "fill E_T");
     hipchk(launch_fill(dE_dR_or_null, 3 * (size_t)g->n_atoms, 0.0, st), "fill dE/dR");
-    const ItemList& L = items_for(g, bs, g->d_pblocks[prec]);
+    const ItemList& L = tile_list(g, bs, dens_key_of(g, prec));
     for (size_t gi = 0; gi < bs.groups.size(); ++gi) {
       const auto& gr = bs.groups[gi];
       const int nbt = gr.b1 - gr.b0;
@@ -1749,7 +1790,7 @@ aims_status aims_total_forces(aims_grid* g, aims_precision prec, const double* P
     hipchk(launch_fill(g->d_et_batch, bs.batches.size(), 0.0, st), "fill E_T");
     hipchk(launch_fill(dE_dR, 3 * (size_t)g->n_atoms, 0.0, st), "fill dE/dR");
     const double* v = g->d_vmodel;
-    const ItemList& L = items_for(g, bs, g->d_pblocks[prec]);
+    const ItemList& L = tile_list(g, bs, dens_key_of(g, prec));
     for (size_t gi = 0; gi < bs.groups.size(); ++gi) {
       const auto& gr = bs.groups[gi];
       const int nbt = gr.b1 - gr.b0;
@@ -1952,7 +1993,7 @@ aims_status aims_density_gradient(aims_grid* g, const double* P, double* n_out_o
     }
     hipchk(launch_fill(g->d_n_sorted, (size_t)g->n_points, 0.0, st), "fill n");
     hipchk(launch_fill(g->d_et_batch, bs.batches.size(), 0.0, st), "fill E_T");
-    const ItemList& L = items_for(g, bs, g->d_pblocks[AIMS_FP64]);
+    const ItemList& L = tile_list(g, bs, dens_key_of(g, AIMS_FP64));
     double *s1 = (double*)g->d_slab1, *s2 = (double*)g->d_slab2, *s3 = (double*)g->d_slab3;
     for (size_t gi = 0; gi < bs.groups.size(); ++gi) {
       const auto& gr = bs.groups[gi];
@@ -2076,6 +2117,8 @@ aims_status aims_get_tuning(const aims_grid* g, aims_precision prec, aims_tuning
   out->h_flops_per_atomic = g->h_ratio[prec];
   out->density_pblocks = g->d_pblocks[prec];
   out->persistent = g->persistent[prec];
+  out->h_tile32_mask = (int32_t)g->h_tile32[prec];
+  for (int b = 0; b < kDensityBuckets; ++b) out->density_bucket_pblocks[b] = g->d_bucket_pblocks[prec][b];
   return AIMS_OK;
 }
 
@@ -2087,12 +2130,45 @@ aims_status aims_set_tuning(aims_grid* g, aims_precision prec, const aims_tuning
     if (t->persistent != 0 && t->persistent != 1) fail(AIMS_ERR_ARG, "persistent must be 0 or 1");
     if (t->h_flops_per_atomic < 0 || t->h_flops_per_atomic > (1 << 20))
       fail(AIMS_ERR_ARG, "h_flops_per_atomic must be in 0..2^20");
-    hset(g, t->h_merge, t->h_flops_per_atomic);
-    items_for(g, g->dens, t->density_pblocks);
+    for (int b = 0; b < kDensityBuckets; ++b)
+      if (t->density_bucket_pblocks[b] != 0 && (t->density_bucket_pblocks[b] < 2 || t->density_bucket_pblocks[b] > 5))
+        fail(AIMS_ERR_ARG, "density_bucket_pblocks[%d] must be 0 or in 2..5", b);
+    if (t->h_tile32_mask < 0 || t->h_tile32_mask >= (1 << (2 * kDensityBuckets)))
+      fail(AIMS_ERR_ARG, "h_tile32_mask must be in 0..2^%d - 1", 2 * kDensityBuckets);
+    if (t->h_tile32_mask && prec != AIMS_FP64 && prec != AIMS_FP32)
+      fail(AIMS_ERR_UNSUPPORTED, "32 x 32 H tiles exist for AIMS_FP64 and AIMS_FP32");
+    BatchSet& hb = hset(g, t->h_merge, t->h_flops_per_atomic);
+    tile_list(g, hb, h_key((uint32_t)t->h_tile32_mask));
+    if (prec != AIMS_INT8X7) tile_list(g, g->dens, density_key(t->density_pblocks, t->density_bucket_pblocks));
     g->h_merge[prec] = t->h_merge;
     g->h_ratio[prec] = t->h_flops_per_atomic;
     g->persistent[prec] = t->persistent;
     g->d_pblocks[prec] = t->density_pblocks;
+    g->h_tile32[prec] = (uint32_t)t->h_tile32_mask;
+    for (int b = 0; b < kDensityBuckets; ++b) g->d_bucket_pblocks[prec][b] = t->density_bucket_pblocks[b];
+  });
+}
+
+// Per tile-shape bucket: the batches and the algorithmic flops (2 n_p n_b^2) of the density
+// partition (which = 0, kDensityBuckets buckets) or of the precision's H partition (which = 1,
+// 2 kDensityBuckets buckets).
+aims_status aims_bucket_stats(aims_grid* g, aims_precision prec, int32_t which, int64_t* batches_out,
+                              double* flops_out) {
+  return guarded(g, [&] {
+    check_prec(prec);
+    if (which != 0 && which != 1) fail(AIMS_ERR_ARG, "which must be 0 (density) or 1 (H)");
+    if (!batches_out || !flops_out) fail(AIMS_ERR_ARG, "null output");
+    const int nbk = which ? 2 * kDensityBuckets : kDensityBuckets;
+    for (int b = 0; b < nbk; ++b) {
+      batches_out[b] = 0;
+      flops_out[b] = 0.0;
+    }
+    const BatchSet& bs = which ? hset(g, g->h_merge[prec], g->h_ratio[prec]) : g->dens;
+    for (const BatchDesc& d : bs.batches) {
+      const int b = which ? h_bucket(d.n_b) : density_bucket(d.n_b);
+      batches_out[b] += 1;
+      flops_out[b] += 2.0 * d.n_p * (double)d.n_b * d.n_b;
+    }
   });
 }
 

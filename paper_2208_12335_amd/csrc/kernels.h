@@ -105,7 +105,7 @@ hipError_t launch_dv(const DeviceView& dv, double* dE_dv, const double* n_sorted
                      const double* gE, hipStream_t st);
 template <typename T>
 hipError_t launch_hs(const DeviceView& dv, const TileItem* items, int n_items, const T* slab1,
-                     const T* slab2, double* out, hipStream_t st, Queue q = Queue());
+                     const T* slab2, double* out, hipStream_t st, Queue q = Queue(), int te = 64);
 hipError_t launch_hs_bf16(const DeviceView& dv, const TileItem* items, int n_items, const void* slab1,
                           const void* slab2, double* out, hipStream_t st, Queue q = Queue());
 hipError_t launch_zero_int(int* x, int n, hipStream_t st);

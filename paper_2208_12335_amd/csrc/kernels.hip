@@ -530,74 +530,80 @@ density_kernel(const TileItem* __restrict__ items, int n_items, const BatchDesc*
 
 
 // H / S, FP64 / FP32: C[i][j] = sum_p slab1[i][p] slab2[j][p] over the batch's points, then a
-// FP64 scatter-add into the dense output.
-template <typename T>
+// FP64 scatter-add into the dense output.  TE = 64: 64 x 64 tiles, each wave a 2 x 2 set of
+// 16 x 16 blocks; TE = 32: 32 x 32 tiles (less padding on ragged basis counts), each wave one
+// block, threads 0-127 staging the first operand and 128-255 the second.
+template <typename T, int TE>
 __device__ __forceinline__ void
 hs_tile(int item, const TileItem* __restrict__ items, int n_items, const BatchDesc* __restrict__ batches,
           const SystemDesc* __restrict__ systems, const int32_t* __restrict__ batch_cols,
           const T* __restrict__ slab1, const T* __restrict__ slab2, double* __restrict__ out) {
+  constexpr int NB = TE / 32;         // 16 x 16 blocks per wave and dimension
   const TileItem it = items[item];
   const BatchDesc d = batches[it.batch];
   const SystemDesc sys = systems[d.sys];
   const int nb = d.n_b, ldp = d.ldp;
-  const int i0 = it.ti * kTile, jb = it.tj * kTile;
+  const int i0 = it.ti * TE, jb = it.tj * TE;
   const int* cols = batch_cols + d.col_off;
 
-  __shared__ T As[2][kTile * kLdK];   // Phi^T[i][p], p contiguous (K)
-  __shared__ T Bs[2][kTile * kLdK];   // second operand [j][p], p contiguous (K)
+  __shared__ T As[2][TE * kLdK];      // Phi^T[i][p], p contiguous (K)
+  __shared__ T Bs[2][TE * kLdK];      // second operand [j][p], p contiguous (K)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
-  const int mrows = nb - (i0 + wm * 32), ncols = nb - (jb + wn * 32);
+  const int mrows = nb - (i0 + wm * 16 * NB), ncols = nb - (jb + wn * 16 * NB);
   typedef typename Acc<T>::type acc_t;
-  acc_t acc[2][2];
+  acc_t acc[NB][NB];
 #pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
+  for (int mi = 0; mi < NB; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = acc_t{0, 0, 0, 0};
+    for (int ni = 0; ni < NB; ++ni) acc[mi][ni] = acc_t{0, 0, 0, 0};
 
-  const int row = tid >> 2, seg = tid & 3;
-  const bool a_ok = i0 + row < nb, b_ok = jb + row < nb;
+  // TE = 64: thread t stages row t / 4 of both operands; TE = 32: threads 0-127 stage row t / 4
+  // of the first operand, threads 128-255 row (t - 128) / 4 of the second
+  const int row = TE == 64 ? tid >> 2 : (tid & 127) >> 2, seg = tid & 3;
+  const bool sa = TE == 64 || tid < 128, sb = TE == 64 || tid >= 128;
+  const bool a_ok = sa && i0 + row < nb, b_ok = sb && jb + row < nb;
   const T* Ap = slab1 + d.slab_off + (size_t)(a_ok ? i0 + row : 0) * ldp + 4 * seg;
   const T* Bp = slab2 + d.slab_off + (size_t)(b_ok ? jb + row : 0) * ldp + 4 * seg;
   T av[4], bv[4];
   auto fetch = [&](int kc) {
-    load4<T>(Ap + kc, av);     // rows beyond n_b read row 0 and are zeroed when stashed
-    load4<T>(Bp + kc, bv);
+    if (sa) load4<T>(Ap + kc, av);     // rows beyond n_b read row 0 and are zeroed when stashed
+    if (sb) load4<T>(Bp + kc, bv);
   };
   auto stash = [&](int buf) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      As[buf][row * kLdK + 4 * seg + c] = a_ok ? av[c] : T(0);
-      Bs[buf][row * kLdK + 4 * seg + c] = b_ok ? bv[c] : T(0);
+      if (sa) As[buf][row * kLdK + 4 * seg + c] = a_ok ? av[c] : T(0);
+      if (sb) Bs[buf][row * kLdK + 4 * seg + c] = b_ok ? bv[c] : T(0);
     }
   };
-  const bool full = mrows >= 32 && ncols >= 32;
+  const bool full = mrows >= 16 * NB && ncols >= 16 * NB;
   auto multiply = [&](int buf) {
-    T a[4][2], b[4][2];
+    T a[4][NB], b[4][NB];
 #pragma unroll
     for (int s4 = 0; s4 < 4; ++s4) {
       const int kr = 4 * s4 + (lane >> 4);
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        a[s4][i] = As[buf][(wm * 32 + i * 16 + (lane & 15)) * kLdK + kr];
-        b[s4][i] = Bs[buf][(wn * 32 + i * 16 + (lane & 15)) * kLdK + kr];
+      for (int i = 0; i < NB; ++i) {
+        a[s4][i] = As[buf][(wm * 16 * NB + i * 16 + (lane & 15)) * kLdK + kr];
+        b[s4][i] = Bs[buf][(wn * 16 * NB + i * 16 + (lane & 15)) * kLdK + kr];
       }
     }
     if (full) {
 #pragma unroll
       for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
-        for (int mi = 0; mi < 2; ++mi)
+        for (int mi = 0; mi < NB; ++mi)
 #pragma unroll
-          for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = mfma16(a[s4][mi], b[s4][ni], acc[mi][ni]);
+          for (int ni = 0; ni < NB; ++ni) acc[mi][ni] = mfma16(a[s4][mi], b[s4][ni], acc[mi][ni]);
     } else {
 #pragma unroll
       for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
-        for (int mi = 0; mi < 2; ++mi) {
+        for (int mi = 0; mi < NB; ++mi) {
           if (16 * mi >= mrows) continue;
 #pragma unroll
-          for (int ni = 0; ni < 2; ++ni)
+          for (int ni = 0; ni < NB; ++ni)
             if (16 * ni < ncols) acc[mi][ni] = mfma16(a[s4][mi], b[s4][ni], acc[mi][ni]);
         }
     }
@@ -616,28 +622,28 @@ hs_tile(int item, const TileItem* __restrict__ items, int n_items, const BatchDe
   if (mrows <= 0 || ncols <= 0) return;
   double* O = out + sys.mat_off;
 #pragma unroll
-  for (int ni = 0; ni < 2; ++ni) {
-    const int j = jb + wn * 32 + ni * 16 + (lane & 15);
+  for (int ni = 0; ni < NB; ++ni) {
+    const int j = jb + wn * 16 * NB + ni * 16 + (lane & 15);
     if (j >= nb) continue;
     const size_t gj = (size_t)cols[j];
 #pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
+    for (int mi = 0; mi < NB; ++mi)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = i0 + wm * 32 + mi * 16 + acc_row<T>(lane, r);
+        const int i = i0 + wm * 16 * NB + mi * 16 + acc_row<T>(lane, r);
         if (i < nb) unsafeAtomicAdd(O + (size_t)cols[i] * sys.nb + gj, (double)acc[mi][ni][r]);
       }
   }
 }
 
-template <typename T>
+template <typename T, int TE>
 __global__ void __launch_bounds__(256)
 hs_kernel(const TileItem* __restrict__ items, int n_items, const BatchDesc* __restrict__ batches,
           const SystemDesc* __restrict__ systems, const int32_t* __restrict__ batch_cols,
           const T* __restrict__ slab1, const T* __restrict__ slab2, double* __restrict__ out,
     int* __restrict__ queue) {
   run_items(n_items, queue, [&](int item) {
-    hs_tile<T>(item, items, n_items, batches, systems, batch_cols, slab1, slab2, out);
+    hs_tile<T, TE>(item, items, n_items, batches, systems, batch_cols, slab1, slab2, out);
   });
 }
 
@@ -1287,10 +1293,14 @@ hipError_t launch_density(const DeviceView& dv, int nbn, const TileItem* items, 
 
 template <typename T>
 hipError_t launch_hs(const DeviceView& dv, const TileItem* items, int n_items, const T* slab1,
-                     const T* slab2, double* out, hipStream_t st, Queue q) {
+                     const T* slab2, double* out, hipStream_t st, Queue q, int te) {
   if (n_items == 0) return hipSuccess;
-  hipLaunchKernelGGL(hs_kernel<T>, dim3(tile_grid(n_items, q, (const void*)hs_kernel<T>)), dim3(256), 0, st, items, n_items,
-                     dv.batches, dv.systems, dv.batch_cols, slab1, slab2, out, q.counters);
+  if (te == 32)
+    hipLaunchKernelGGL((hs_kernel<T, 32>), dim3(tile_grid(n_items, q, (const void*)hs_kernel<T, 32>)), dim3(256), 0, st,
+                       items, n_items, dv.batches, dv.systems, dv.batch_cols, slab1, slab2, out, q.counters);
+  else
+    hipLaunchKernelGGL((hs_kernel<T, 64>), dim3(tile_grid(n_items, q, (const void*)hs_kernel<T, 64>)), dim3(256), 0, st,
+                       items, n_items, dv.batches, dv.systems, dv.batch_cols, slab1, slab2, out, q.counters);
   return hipGetLastError();
 }
 
@@ -1379,9 +1389,9 @@ template hipError_t launch_pulay<double>(const DeviceView&, int, int, const doub
 template hipError_t launch_pulay<float>(const DeviceView&, int, int, const double*, const float*,
                                         const float*, const double*, double*, hipStream_t, double*);
 template hipError_t launch_hs<double>(const DeviceView&, const TileItem*, int, const double*,
-                                      const double*, double*, hipStream_t, Queue);
+                                      const double*, double*, hipStream_t, Queue, int);
 template hipError_t launch_hs<float>(const DeviceView&, const TileItem*, int, const float*,
-                                     const float*, double*, hipStream_t, Queue);
+                                     const float*, double*, hipStream_t, Queue, int);
 
 // Resident-workgroup counts of every tiled kernel, queried once on the current device
 // (outside any stream capture, so that later persistent launches only read the cache).
@@ -1393,7 +1403,8 @@ hipError_t prepare_launch_configs() {
       (const void*)density_kernel<float, 4>,  (const void*)density_kernel<float, 5>,
       (const void*)density_kernel_bf16<2>,    (const void*)density_kernel_bf16<3>,
       (const void*)density_kernel_bf16<4>,    (const void*)density_kernel_bf16<5>,
-      (const void*)hs_kernel<double>,         (const void*)hs_kernel<float>,
+      (const void*)hs_kernel<double, 64>,     (const void*)hs_kernel<float, 64>,
+      (const void*)hs_kernel<double, 32>,     (const void*)hs_kernel<float, 32>,
       (const void*)hs_kernel_bf16};
   for (const void* f : fns)
     if (resident_workgroups(f) <= 0) return hipErrorInvalidDeviceFunction;

@@ -314,11 +314,14 @@ class AimsGrid:
         t = AimsTuning()
         self._check(self._L.aims_get_tuning(self._h, PRECISION[prec], byref(t)))
         return {"h_merge": t.h_merge, "density_pblocks": t.density_pblocks,
-                "persistent": t.persistent, "h_flops_per_atomic": t.h_flops_per_atomic}
+                "persistent": t.persistent, "h_flops_per_atomic": t.h_flops_per_atomic,
+                "h_tile32_mask": t.h_tile32_mask,
+                "density_bucket_pblocks": list(t.density_bucket_pblocks)}
 
     def set_tuning(self, h_merge: Optional[int] = None, density_pblocks: Optional[int] = None,
                    prec="fp64", persistent: Optional[int] = None,
-                   h_flops_per_atomic: Optional[int] = None):
+                   h_flops_per_atomic: Optional[int] = None, h_tile32_mask: Optional[int] = None,
+                   density_bucket_pblocks: Optional[Sequence[int]] = None):
         cur = self.get_tuning(prec)
         t = AimsTuning()
         t.h_merge = int(cur["h_merge"] if h_merge is None else h_merge)
@@ -326,7 +329,23 @@ class AimsGrid:
         t.persistent = int(cur["persistent"] if persistent is None else persistent)
         t.h_flops_per_atomic = int(cur["h_flops_per_atomic"] if h_flops_per_atomic is None
                                    else h_flops_per_atomic)
+        t.h_tile32_mask = int(cur["h_tile32_mask"] if h_tile32_mask is None else h_tile32_mask)
+        bp = cur["density_bucket_pblocks"] if density_bucket_pblocks is None else density_bucket_pblocks
+        if len(bp) != 8:
+            raise ValueError("density_bucket_pblocks needs 8 entries")
+        for b, x in enumerate(bp):
+            t.density_bucket_pblocks[b] = int(x)
         self._check(self._L.aims_set_tuning(self._h, PRECISION[prec], byref(t)))
+
+    def bucket_stats(self, prec="fp64", which="density"):
+        """(batches, flops) per tile-shape bucket of the density partition (8) or of the
+        precision's H partition (16)."""
+        nbk = 8 if which == "density" else 16
+        nb = (c_int64 * nbk)()
+        fl = (c_double * nbk)()
+        self._check(self._L.aims_bucket_stats(self._h, PRECISION[prec], 0 if which == "density" else 1,
+                                              nb, fl))
+        return list(nb), list(fl)
 
     def profile(self, on: bool = True):
         self._check(self._L.aims_profile_enable(self._h, 1 if on else 0))

@@ -74,3 +74,37 @@ def test_cache_roundtrip(tmp_path):
     with open(p, "w") as f:
         json.dump([1, 2], f)
     assert load_cache(p) == {}
+
+
+def test_refine_buckets_per_bucket_choices():
+    """Coordinate descent over the tile-shape buckets: each bucket with work gets the shape that
+    makes its pass faster; buckets without work are never timed; small gains are ignored."""
+    from paper_2208_12335_amd.autotune import refine_buckets
+    dfl = [0.0, 5.0, 0.0, 9.0, 0.0, 0.0, 0.0, 1.0]
+    hfl = [0.0] * 16
+    hfl[2], hfl[5], hfl[9] = 4.0, 7.0, 1.0
+
+    def cost(kind, cfg):
+        if kind == "density":
+            bp = cfg["density_bucket_pblocks"]
+            pb = lambda b: bp[b] or cfg["density_pblocks"]
+            t = 10.0
+            t -= 1.0 if pb(3) == 4 else 0.0        # bucket 3 likes 4 point blocks
+            t -= 0.5 if pb(1) == 5 else 0.0        # bucket 1 likes 5
+            t -= 0.01 if pb(7) == 3 else 0.0       # below the 0.5% threshold
+            return t
+        m = cfg["h_tile32_mask"]
+        return 20.0 - (2.0 if m >> 5 & 1 else 0.0) + (1.0 if m >> 2 & 1 else 0.0)
+
+    timed = []
+    base = {"h_merge": 1, "h_flops_per_atomic": 0, "density_pblocks": 2, "persistent": 1}
+    best, log = refine_buckets(lambda k, c: (timed.append((k, c)), cost(k, c))[1], base, dfl, hfl)
+    assert best["density_bucket_pblocks"] == [0, 5, 0, 4, 0, 0, 0, 0]
+    assert best["h_tile32_mask"] == 1 << 5
+    assert all(k in best for k in base)
+    # empty buckets are never tried
+    assert not any("bucket 0 " in k or "bucket 2 p" in k for k in log)
+    assert not any("h bucket 0 " in k for k in log)
+    # FP64 / FP32 only for the 32 x 32 H tiles
+    best2, _ = refine_buckets(cost, base, dfl, hfl, allow_h32=False)
+    assert best2["h_tile32_mask"] == 0
