@@ -215,7 +215,7 @@ def bench_single(args, torch, inst, backward=False):
         elif not args.no_autotune:
             t0 = time.time()
             r = autotune(g, P, v, prec=prec, reps=2, cache="")   # measured here, never cached
-            _log(f"{prec}: autotuned {dict((k, r[k]) for k in ('h_merge', 'density_pblocks', 'persistent', 'h_flops_per_atomic') if k in r)}"
+            _log(f"{prec}: autotuned {dict((k, r[k]) for k in ('h_merge', 'density_pblocks', 'persistent', 'h_flops_per_atomic', 'h_tile32_mask', 'density_bucket_pblocks') if k in r)}"
                  f" ({time.time() - t0:.1f} s)")
 
         if backward:
@@ -405,7 +405,7 @@ def bench_grouped(args, torch, mols):
     with torch.cuda.stream(stream):
         if not args.no_autotune:
             r = autotune(g, P, v, prec=prec, reps=2, cache="")
-            _log(f"autotuned {dict((k, r[k]) for k in ('h_merge', 'density_pblocks', 'persistent'))}")
+            _log(f"autotuned {dict((k, r[k]) for k in ('h_merge', 'density_pblocks', 'persistent', 'h_flops_per_atomic', 'h_tile32_mask', 'density_bucket_pblocks'))}")
 
         def eager():
             g.update_density(P, v, prec=prec, n_out=n, sums_out=sums)
@@ -432,7 +432,8 @@ def bench_grouped(args, torch, mols):
     for m in mols:
         gm = AimsGrid(m, device=0, stream=stream)
         gm.set_tuning(h_merge=tg["h_merge"], density_pblocks=tg["density_pblocks"], prec=prec,
-                      h_flops_per_atomic=tg["h_flops_per_atomic"])
+                      h_flops_per_atomic=tg["h_flops_per_atomic"], h_tile32_mask=tg["h_tile32_mask"],
+                      density_bucket_pblocks=tg["density_bucket_pblocks"])
         Pm = torch.from_numpy(m.P).to(dev).reshape(-1)
         vm = torch.from_numpy(m.v).to(dev)
         nm = torch.empty(gm.n_points, dtype=torch.float64, device=dev)
