@@ -194,21 +194,39 @@ class GridOracle:
             cols.append(self.atom_off[a] + np.arange(sh.numel()))
         return torch.cat(blocks, 1), torch.cat(tblocks, 1), np.concatenate(cols)
 
-    def gradient_closed_form(self, P: np.ndarray, v: np.ndarray) -> np.ndarray:
+    def gradient_closed_form(self, P: np.ndarray, v: np.ndarray,
+                             atoms: Optional[np.ndarray] = None) -> np.ndarray:
         """dE/dR_a = -sum_p w_p sum_{i in a} [(2 v_p X_pi + Y_pi) grad phi_i + X_pi grad tphi_i]
         with X = Phi P and Y = (T Phi) P, using the analytic basis gradient
-        grad phi = (R' - l R/r) Y_lm u + (R/r) grad S_lm(u).  Cross-check of ``gradient``."""
+        grad phi = (R' - l R/r) Y_lm u + (R/r) grad S_lm(u).  Cross-check of ``gradient``.
+        ``atoms`` limits dE/dR to those atoms: only points within rc of one of them are visited,
+        and X, Y and the basis gradients are formed for their functions only (the other rows
+        of the result are zero)."""
         inst = self.inst
         g = np.zeros((inst.n_atoms, 3))
-        for sl in self._chunks():
-            Phi, TPhi, cols, G, GT = self.basis_values(inst.pt_xyz[sl], grad=True)
-            Pc = P[np.ix_(cols, cols)]
+        if atoms is None:
+            want = None
+            sel = np.arange(inst.n_points)
+        else:
+            want = np.asarray(atoms)
+            d = np.sqrt(((inst.pt_xyz[:, None, :] - inst.atom_xyz[None, want, :]) ** 2).sum(-1))
+            sel = np.nonzero(d.min(axis=1) < inst.rc)[0]
+        for s0 in range(0, sel.size, self.chunk):
+            idx = sel[s0:s0 + self.chunk]
+            pts = inst.pt_xyz[idx]
+            if want is None:
+                Phi, TPhi, cols, G, GT = self.basis_values(pts, grad=True)
+                gcols = cols
+            else:
+                Phi, TPhi, cols = self.basis_values(pts)
+                _, _, gcols, G, GT = self.basis_values(pts, atoms=want, grad=True)
+            Pc = P[np.ix_(cols, gcols)]
             Xm = Phi @ Pc
             Ym = TPhi @ Pc
-            w = inst.pt_w[sl][:, None]
-            coef = w * (2.0 * v[sl][:, None] * Xm + Ym)
+            w = inst.pt_w[idx][:, None]
+            coef = w * (2.0 * v[idx][:, None] * Xm + Ym)
             contrib = (coef[:, :, None] * G + (w * Xm)[:, :, None] * GT).sum(0)   # [nf, 3]
-            host = np.searchsorted(self.atom_off, cols, side="right") - 1
+            host = np.searchsorted(self.atom_off, gcols, side="right") - 1
             np.add.at(g, host, -contrib)
         return g
 

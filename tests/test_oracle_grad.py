@@ -44,6 +44,10 @@ def test_small_cluster_position_gradient_vs_fd():
     # restricting to a subset of atoms gives the same rows as the full gradient
     gfull = o.gradient(inst.P, inst.v)["dE_dR"]
     assert np.max(np.abs(gfull[atoms] - g["dE_dR"][atoms])) < 1e-11 * np.max(np.abs(gfull))
+    # and so does the closed form restricted to them (points near them, their columns only)
+    gr = o.gradient_closed_form(inst.P, inst.v, atoms=atoms)
+    assert np.max(np.abs(gr[atoms] - gfull[atoms])) < 1e-10 * np.max(np.abs(gfull))
+    assert np.all(gr[[0, 2, 4]] == 0.0)
 
 
 def test_density_matrix_and_potential_gradients_exact(c1, c1_oracle):

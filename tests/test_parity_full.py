@@ -66,3 +66,16 @@ def test_c2_whole_output_properties(c2_run):
     S = out["S"]
     assert np.max(np.abs(S - S.T)) < 1e-13 * np.max(np.abs(S))
     assert np.all(np.isfinite(out["n"])) and np.all(np.isfinite(out["H"]))
+
+
+def test_c2_whole_sums_against_oracle(c2_run):
+    """N, E_V and E_T over every point of the workload against the oracle's full density pass
+    (about a minute on the host cores)."""
+    inst, g, out = c2_run
+    d = GridOracle(inst).density(inst.P, inst.v)
+    N, EV, ET = out["sums"]
+    errs = {"N": abs(N - d["N"]) / abs(d["N"]), "E_V": abs(EV - d["E_V"]) / abs(d["E_V"]),
+            "E_T": abs(ET - d["E_T"]) / abs(d["E_T"]), "n": relerr(out["n"], d["n"])}
+    print("[full] whole-workload sums vs oracle: " + ", ".join(f"{k} {e:.2e}" for k, e in errs.items())
+          + f"; |dE| = {abs(EV + ET - d['E_V'] - d['E_T']):.2e} Ha", flush=True)
+    assert max(errs.values()) < 1e-10
