@@ -920,6 +920,7 @@ aims_grid* build(const aims_system* sys, int n_sys, int device, void* stream) {
   // ---- upload of the shared state, then the density partition ---------------------------
   hipchk(hipSetDevice(device), "hipSetDevice");
   hipchk(prepare_launch_configs(), "occupancy query");
+
   hipchk(prepare_launch_configs_i8(), "occupancy query");
   DeviceView& dv = g->common;
   dv.systems = g->upload(g->systems);
@@ -1023,18 +1024,31 @@ const char* kProfNames[6] = {"phi_eval", "density", "hs", "backward", "finish", 
 
 // Runs one launch, bracketed by events when profiling is on.
 template <typename F>
-void timed(aims_grid* g, int kind, double work, const char* what, F&& launch) {
+void timed(aims_grid* g, int kind, double work, const char* what, F&& launch,
+           hipStream_t on = nullptr) {
   if (!g->profiling) {
     hipchk(launch(), what);
     return;
   }
+  if (!on) on = g->stream;
   aims_grid::ProfRec r{kind, nullptr, nullptr, work};
   hipchk(hipEventCreate(&r.a), "event");
   hipchk(hipEventCreate(&r.b), "event");
-  hipchk(hipEventRecord(r.a, g->stream), "event");
+  hipchk(hipEventRecord(r.a, on), "event");
   hipchk(launch(), what);
-  hipchk(hipEventRecord(r.b, g->stream), "event");
+  hipchk(hipEventRecord(r.b, on), "event");
   g->prof_pending.push_back(r);
+}
+
+// The groups of one pass, in order on the handle's stream: each group's basis evaluation into
+// the slab pair, then the group's tiles (every tile-shape run of the group).
+// phi(gi, slab1, slab2, stream) and tiles(gi, slab1, slab2, stream) launch one group.
+template <typename Phi, typename Tiles>
+void run_groups(aims_grid* g, size_t ngroups, Phi&& phi, Tiles&& tiles) {
+  for (size_t gi = 0; gi < ngroups; ++gi) {
+    phi(gi, g->d_slab1, g->d_slab2, g->stream);
+    tiles(gi, g->d_slab1, g->d_slab2, g->stream);
+  }
 }
 
 void prof_collect(aims_grid* g) {
@@ -1098,27 +1112,26 @@ void run_density(aims_grid* g, aims_precision prec, const T* P, const double* v,
     Lp = &tile_list(g, bs, dens_key_of(g, prec));
   }
   const ItemList& L = *Lp;
-  void* slab1 = noalloc ? g->na_scratch : g->d_slab1;
-  void* slab2 = noalloc ? (void*)((unsigned char*)g->na_scratch + kNoAllocScratchBytes / 2) : g->d_slab2;
-  auto timed = [&](int kind, double work, const char* what, auto&& launch) {
+  void* na_slab1 = g->na_scratch;
+  void* na_slab2 = (void*)((unsigned char*)g->na_scratch + kNoAllocScratchBytes / 2);
+  auto timed = [&](int kind, double work, const char* what, auto&& launch, hipStream_t on) {
     if (noalloc) hipchk(launch(), what);
-    else ::timed(g, kind, work, what, launch);
+    else ::timed(g, kind, work, what, launch, on);
   };
   hipchk(launch_fill(g->d_n_sorted, (size_t)g->n_points, 0.0, st), "fill n");
   hipchk(launch_fill(g->d_et_batch, bs.batches.size(), 0.0, st), "fill E_T");
   QueueSeq qs(g, L, noalloc ? AIMS_FP64 : prec, noalloc);
-  for (size_t gi = 0; gi < bs.groups.size(); ++gi) {
+  auto phi = [&](size_t gi, void* slab1, void* slab2, hipStream_t on) {
     const auto& gr = bs.groups[gi];
     const int nbt = gr.b1 - gr.b0;
-    if (prec == AIMS_BF16X3) {
-      timed(kProfPhi, 0.0, "phi_eval", [&] {
-        return launch_phi_eval_bf16(bs.dv, gr.b0, nbt, kModeDensity, nullptr, slab1, slab2, st);
-      });
-    } else {
-      timed(kProfPhi, 0.0, "phi_eval", [&] {
-        return launch_phi_eval<T>(bs.dv, gr.b0, nbt, kModeDensity, nullptr, (T*)slab1, (T*)slab2, st);
-      });
-    }
+    timed(kProfPhi, 0.0, "phi_eval", [&] {
+      if (prec == AIMS_BF16X3)
+        return launch_phi_eval_bf16(bs.dv, gr.b0, nbt, kModeDensity, nullptr, slab1, slab2, on);
+      return launch_phi_eval<T>(bs.dv, gr.b0, nbt, kModeDensity, nullptr, (T*)slab1, (T*)slab2, on);
+    }, on);
+  };
+  auto tiles = [&](size_t gi, void* slab1, void* slab2, hipStream_t on) {
+    const auto& gr = bs.groups[gi];
     for (size_t r = 0; r < L.runs[gi].size(); ++r) {
       const auto& run = L.runs[gi][r];
       const double work = r + 1 == L.runs[gi].size() ? gr.flops : 0.0;   // credited once per group
@@ -1126,22 +1139,30 @@ void run_density(aims_grid* g, aims_precision prec, const T* P, const double* v,
       if (prec == AIMS_BF16X3) {
         timed(kProfDensity, work, "density", [&] {
           return launch_density_bf16(bs.dv, run.nbn, L.d_items + run.i0, nit, (const float*)P,
-                                     slab1, slab2, g->d_n_sorted, g->d_et_batch, st,
+                                     slab1, slab2, g->d_n_sorted, g->d_et_batch, on,
                                      nullptr, qs.next());
-        });
+        }, on);
       } else {
         timed(kProfDensity, work, "density", [&] {
           return launch_density<T>(bs.dv, run.nbn, L.d_items + run.i0, nit, P, (const T*)slab1,
-                                   (const T*)slab2, g->d_n_sorted, g->d_et_batch, st, nullptr,
+                                   (const T*)slab2, g->d_n_sorted, g->d_et_batch, on, nullptr,
                                    qs.next());
-        });
+        }, on);
       }
     }
+  };
+  if (noalloc) {
+    for (size_t gi = 0; gi < bs.groups.size(); ++gi) {
+      phi(gi, na_slab1, na_slab2, st);
+      tiles(gi, na_slab1, na_slab2, st);
+    }
+  } else {
+    run_groups(g, bs.groups.size(), phi, tiles);
   }
   timed(kProfFinish, 0.0, "density_finish", [&] {
     return launch_density_finish(bs.dv, g->d_n_sorted, v, n_out, g->d_part, g->nblk_finish,
                                  g->d_et_batch, sums_out, st);
-  });
+  }, st);
 }
 
 template <typename T>
@@ -1152,35 +1173,31 @@ void run_hs(aims_grid* g, aims_precision prec, int mode, const double* v, double
   const ItemList& L = tile_list(g, bs, h_key_of(g, prec));
   hipchk(launch_fill(out, (size_t)g->mat_total, 0.0, st), "fill H");
   QueueSeq qs(g, L, prec);
-  for (size_t gi = 0; gi < bs.groups.size(); ++gi) {
+  auto phi = [&](size_t gi, void* s1, void* s2, hipStream_t on) {
     const auto& gr = bs.groups[gi];
     const int nbt = gr.b1 - gr.b0;
+    timed(g, kProfPhi, 0.0, "phi_eval", [&] {
+      if (prec == AIMS_BF16X3) return launch_phi_eval_bf16(bs.dv, gr.b0, nbt, mode, v, s1, s2, on);
+      return launch_phi_eval<T>(bs.dv, gr.b0, nbt, mode, v, (T*)s1, (T*)s2, on);
+    }, on);
+    if (u)
+      timed(g, kProfPhi, 0.0, "vector term", [&] {
+        return launch_vector_term<T>(bs.dv, gr.b0, nbt, u, (T*)s2, on);
+      }, on);
+  };
+  auto tiles = [&](size_t gi, void* s1, void* s2, hipStream_t on) {
+    const auto& gr = bs.groups[gi];
     for (const auto& run : L.runs[gi]) {
       const int nit = (int)(run.i1 - run.i0);
-      if (prec == AIMS_BF16X3) {
-        timed(g, kProfPhi, 0.0, "phi_eval", [&] {
-          return launch_phi_eval_bf16(bs.dv, gr.b0, nbt, mode, v, g->d_slab1, g->d_slab2, st);
-        });
-        timed(g, kProfHS, gr.flops, "hs", [&] {
-          return launch_hs_bf16(bs.dv, L.d_items + run.i0, nit, g->d_slab1, g->d_slab2, out, st, qs.next());
-        });
-      } else {
-        T* s1 = (T*)g->d_slab1;
-        T* s2 = (T*)g->d_slab2;
-        timed(g, kProfPhi, 0.0, "phi_eval", [&] {
-          return launch_phi_eval<T>(bs.dv, gr.b0, nbt, mode, v, s1, s2, st);
-        });
-        if (u)
-          timed(g, kProfPhi, 0.0, "vector term", [&] {
-            return launch_vector_term<T>(bs.dv, gr.b0, nbt, u, s2, st);
-          });
-        timed(g, kProfHS, gr.flops, "hs", [&] {
-          return launch_hs<T>(bs.dv, L.d_items + run.i0, nit, s1, s2, out, st, qs.next(),
-                              run.nbn ? 32 : 64);
-        });
-      }
+      timed(g, kProfHS, gr.flops, "hs", [&] {
+        if (prec == AIMS_BF16X3)
+          return launch_hs_bf16(bs.dv, L.d_items + run.i0, nit, s1, s2, out, on, qs.next());
+        return launch_hs<T>(bs.dv, L.d_items + run.i0, nit, (const T*)s1, (const T*)s2, out, on,
+                            qs.next(), run.nbn ? 32 : 64);
+      }, on);
     }
-  }
+  };
+  run_groups(g, bs.groups.size(), phi, tiles);
 }
 
 // ---- sliced integer form ------------------------------------------------------------------
@@ -1211,31 +1228,34 @@ void run_density_i8(aims_grid* g, const double* P, const double* v, double* n_ou
   const ItemList& L = tile_list(g, bs, dens_key_of(g, AIMS_INT8X7));
   int32_t* ex1 = g->d_pexp;
   int32_t* ex2 = g->d_pexp + g->n_points;
-  uint64_t* s1 = (uint64_t*)g->d_slab1;
-  uint64_t* s2 = (uint64_t*)g->d_slab2;
   timed(g, kProfOperands, 0.0, "slice P", [&] {
     return launch_slice_p(bs.dv, P, g->d_P8, g->d_eP, g->nb_total, st);
   });
   hipchk(launch_fill(g->d_n_sorted, (size_t)g->n_points, 0.0, st), "fill n");
   hipchk(launch_fill(g->d_et_batch, bs.batches.size(), 0.0, st), "fill E_T");
   QueueSeq qs(g, L, AIMS_INT8X7);
-  for (size_t gi = 0; gi < bs.groups.size(); ++gi) {
+  auto phi = [&](size_t gi, void* s1, void* s2, hipStream_t on) {
     const auto& gr = bs.groups[gi];
     const int slots = group_slots(bs, gr, true);
     timed(g, kProfPhi, 0.0, "phi_eval", [&] {
-      return launch_phi_eval_i8(bs.dv, gr.b0, gr.b1 - gr.b0, kModeDensity, nullptr, s1, s2, ex1, ex2,
-                                slots, st);
-    });
+      return launch_phi_eval_i8(bs.dv, gr.b0, gr.b1 - gr.b0, kModeDensity, nullptr, (uint64_t*)s1,
+                                (uint64_t*)s2, ex1, ex2, slots, on);
+    }, on);
+  };
+  auto tiles = [&](size_t gi, void* s1, void* s2, hipStream_t on) {
+    const auto& gr = bs.groups[gi];
     for (size_t r = 0; r < L.runs[gi].size(); ++r) {
       const auto& run = L.runs[gi][r];
       if (run.nbn != 2) fail(AIMS_ERR_ARG, "AIMS_INT8X7 density tiles span 64 points");
       const double work = r + 1 == L.runs[gi].size() ? gr.flops : 0.0;
       timed(g, kProfDensity, work, "density", [&] {
         return launch_density_i8(bs.dv, L.d_items + run.i0, (int)(run.i1 - run.i0), g->d_P8, g->d_eP,
-                                 s1, s2, ex1, ex2, g->d_n_sorted, g->d_et_batch, st, qs.next());
-      });
+                                 (const uint64_t*)s1, (const uint64_t*)s2, ex1, ex2, g->d_n_sorted,
+                                 g->d_et_batch, on, qs.next());
+      }, on);
     }
-  }
+  };
+  run_groups(g, bs.groups.size(), phi, tiles);
   timed(g, kProfFinish, 0.0, "density_finish", [&] {
     return launch_density_finish(bs.dv, g->d_n_sorted, v, n_out, g->d_part, g->nblk_finish,
                                  g->d_et_batch, sums_out, st);
@@ -1249,23 +1269,25 @@ void run_hs_i8(aims_grid* g, int mode, const double* v, double* out) {
   const ItemList& L = tile_list(g, bs, h_key(0));
   int32_t* ex1 = bs.d_colexp;
   int32_t* ex2 = bs.d_colexp + bs.batch_cols.size();
-  uint64_t* s1 = (uint64_t*)g->d_slab1;
-  uint64_t* s2 = (uint64_t*)g->d_slab2;
   hipchk(launch_fill(out, (size_t)g->mat_total, 0.0, st), "fill H");
   QueueSeq qs(g, L, AIMS_INT8X7);
-  for (size_t gi = 0; gi < bs.groups.size(); ++gi) {
+  auto phi = [&](size_t gi, void* s1, void* s2, hipStream_t on) {
     const auto& gr = bs.groups[gi];
     const int slots = group_slots(bs, gr, false);
-    for (const auto& run : L.runs[gi]) {
-      timed(g, kProfPhi, 0.0, "phi_eval", [&] {
-        return launch_phi_eval_i8(bs.dv, gr.b0, gr.b1 - gr.b0, mode, v, s1, s2, ex1, ex2, slots, st);
-      });
+    timed(g, kProfPhi, 0.0, "phi_eval", [&] {
+      return launch_phi_eval_i8(bs.dv, gr.b0, gr.b1 - gr.b0, mode, v, (uint64_t*)s1, (uint64_t*)s2,
+                                ex1, ex2, slots, on);
+    }, on);
+  };
+  auto tiles = [&](size_t gi, void* s1, void* s2, hipStream_t on) {
+    const auto& gr = bs.groups[gi];
+    for (const auto& run : L.runs[gi])
       timed(g, kProfHS, gr.flops, "hs", [&] {
-        return launch_hs_i8(bs.dv, L.d_items + run.i0, (int)(run.i1 - run.i0), s1, s2, ex1, ex2, out,
-                            st, qs.next());
-      });
-    }
-  }
+        return launch_hs_i8(bs.dv, L.d_items + run.i0, (int)(run.i1 - run.i0), (const uint64_t*)s1,
+                            (const uint64_t*)s2, ex1, ex2, out, on, qs.next());
+      }, on);
+  };
+  run_groups(g, bs.groups.size(), phi, tiles);
 }
 
 // One precision-dispatched density update (P converted to FP32 for the mixed forms).
