@@ -126,12 +126,20 @@ aims_status aims_grid_setup_many(const aims_system *sys, int32_t n_sys, int devi
  * sums_out[3] = { N = sum w n, E_V = sum w v n, E_T = sum_p w_p sum_ij P_ij phi_i tphi_j }.
  * P: DEVICE, FP64, [nb][nb] row-major, symmetric (the caller's responsibility).  v_or_null:
  * DEVICE [n_points] or NULL (then E_V = 0).  n_out: DEVICE [n_points].  sums_out: DEVICE [3].
- * atom_xyz: NULL (positions from setup) or a host or device [n_atoms][3] array; it is read
- * synchronously and must lie within screen_margin of the setup positions (else
- * AIMS_ERR_STALE). */
+ * atom_xyz: NULL (positions from setup) or a host or device [n_atoms][3] array within
+ * screen_margin of the setup positions.  A host array is checked before any launch
+ * (AIMS_ERR_STALE).  A device array is copied and checked on the device, with no host
+ * synchronisation (so the call can be captured into a graph): if an atom moved beyond the
+ * margin or is not finite, the call's outputs are set to NaN and aims_positions_status reports
+ * AIMS_ERR_STALE.  The same holds for aims_integrate_h and aims_integrate_h_backward. */
 aims_status aims_update_density(aims_grid *g, aims_precision prec, const double *atom_xyz,
                                 const double *P, const double *v_or_null, double *n_out,
                                 double *sums_out);
+
+/* Result of the screening check of the last positions given as a device array (synchronous):
+ * AIMS_OK, or AIMS_ERR_STALE when an atom had moved beyond screen_margin or was not finite (the
+ * outputs of that call are NaN). */
+aims_status aims_positions_status(aims_grid *g);
 
 /* Allocation-free density update, for callers that cannot allocate device memory during the
  * call (code under stream capture, tight serving loops, hosts that forbid allocation): the

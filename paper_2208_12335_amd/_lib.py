@@ -7,7 +7,9 @@ import ctypes
 import os
 from ctypes import POINTER, c_char_p, c_double, c_int, c_int32, c_int64, c_void_p
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libaimsgrid.so")
+# AIMS_LIB selects another build of the same library (the host-sanitized one, for CPU checks)
+LIB_PATH = os.environ.get("AIMS_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                      "libaimsgrid.so")
 
 AIMS_OK, AIMS_ERR_ARG, AIMS_ERR_OOM, AIMS_ERR_HIP, AIMS_ERR_STALE, AIMS_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "AIMS_OK", -1: "AIMS_ERR_ARG", -2: "AIMS_ERR_OOM", -3: "AIMS_ERR_HIP",
@@ -81,6 +83,7 @@ SIGNATURES = {
     "aims_get_tuning": (c_int, [c_void_p, c_int, POINTER(AimsTuning)]),
     "aims_set_tuning": (c_int, [c_void_p, c_int, POINTER(AimsTuning)]),
     "aims_work_stats": (c_int, [c_void_p, POINTER(c_int64), POINTER(c_double), POINTER(c_double)]),
+    "aims_positions_status": (c_int, [c_void_p]),
     "aims_bucket_stats": (c_int, [c_void_p, c_int, c_int32, POINTER(c_int64), POINTER(c_double)]),
     "aims_n_basis": (c_int64, [c_void_p]),
     "aims_n_points": (c_int64, [c_void_p]),

@@ -18,6 +18,8 @@
 #include <thread>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "aims_grid.h"
 #include "aims_internal.h"
 #include "kernels.h"
@@ -264,6 +266,9 @@ struct aims_grid {
   std::vector<void*> owned;           // device allocations
   DeviceView common{};                // device pointers shared by every batch set
   double* d_atom_xyz = nullptr;
+  double* d_atom_xyz0 = nullptr;      // set-up positions (restored device to device)
+  int* d_pos_flag = nullptr;          // 1 when the last device positions failed the screening check
+  bool pos_async = false;             // this call took positions on the device (outputs checked)
   double* d_n_sorted = nullptr;
   double* d_part = nullptr;
   double* d_et_batch = nullptr;
@@ -309,6 +314,7 @@ struct aims_grid {
   HartreeDev hd;
   int dm_iterations = 0;                     // purification products of the last system
   bool force_thread_path = false;           // AIMS_FORCES_THREAD_PATH=1: thread-per-point kernel
+  bool debug = false;                        // AIMS_DEBUG=1: check every index table on the host
   bool gf_ready = false;
   int gf_k = 0;
   int gf_nranges = 0;
@@ -653,6 +659,55 @@ int density_nbn(int n_p, int cap) {
 
 // Tile work list of a batch set: square 64 x 64 tiles for the H kernel, (64 rows x 32 nbn
 // points) tiles for the density kernel, grouped per kernel variant within each batch group.
+// AIMS_DEBUG: every index the kernels read through a batch set's tables, checked on the host
+// against the buffers it addresses (points, atoms, basis columns, slabs, the work list's tiles).
+void debug_check(const aims_grid* g, const BatchSet& bs, const ItemList* L, const char* what) {
+  auto bad = [&](const char* m, int64_t b) {
+    fail(AIMS_ERR_ARG, "internal table check (%s): %s at batch %lld", what, m, (long long)b);
+  };
+  const int64_t nB = (int64_t)bs.batches.size();
+  for (int64_t b = 0; b < nB; ++b) {
+    const BatchDesc& d = bs.batches[b];
+    if (d.sys < 0 || d.sys >= g->n_sys) bad("system index", b);
+    const int64_t p0 = g->sys_pt_range[2 * d.sys], p1 = g->sys_pt_range[2 * d.sys + 1];
+    if (d.n_p < 0 || d.pt_off < p0 || d.pt_off + (int64_t)d.n_p > p1) bad("point range", b);
+    if (d.ldp != round_up(d.n_p, kPad)) bad("slab row length", b);
+    if (d.atom_off < 0 || d.atom_off + (int64_t)d.n_atoms > (int64_t)bs.batch_atoms.size()) bad("atom range", b);
+    if (d.col_off < 0 || d.col_off % 4 || d.col_off + (int64_t)d.n_b + 32 > (int64_t)bs.batch_cols.size())
+      bad("column range", b);
+    const int64_t a0 = g->sys_atom_range[2 * d.sys], a1 = g->sys_atom_range[2 * d.sys + 1];
+    int col = 0;
+    for (int k = 0; k < d.n_atoms; ++k) {
+      const int32_t at = bs.batch_atoms[d.atom_off + k];
+      if (at < a0 || at >= a1) bad("atom index", b);
+      if (bs.batch_acol[d.atom_off + k] != col) bad("atom column", b);
+      col += g->atom_nfn[d.sys][at - a0];
+    }
+    if (col != d.n_b) bad("basis count", b);
+    for (int j = 0; j < d.n_b; ++j) {
+      const int32_t c = bs.batch_cols[d.col_off + j];
+      if (c < 0 || c >= g->systems[d.sys].nb) bad("basis column", b);
+    }
+    if (d.slab_off < 0 || d.slab_off + (int64_t)round_up(d.n_b, 32) * d.ldp > (int64_t)bs.slab_elems)
+      bad("slab extent", b);
+  }
+  for (const auto& gr : bs.groups)
+    if (gr.b0 < 0 || gr.b1 > nB || gr.b0 >= gr.b1) bad("group range", gr.b0);
+  if (!L) return;
+  const bool hlist = (L->key >> 63) != 0;
+  for (size_t gi = 0; gi < L->runs.size(); ++gi)
+    for (const auto& run : L->runs[gi])
+      for (int64_t i = run.i0; i < run.i1; ++i) {
+        const TileItem& it = L->items[i];
+        if (it.batch < bs.groups[gi].b0 || it.batch >= bs.groups[gi].b1) bad("tile outside its group", it.batch);
+        const BatchDesc& d = bs.batches[it.batch];
+        const int rows = hlist ? (run.nbn ? 32 : 64) : kTile;
+        const int pts = hlist ? rows : 32 * run.nbn;
+        if (it.ti < 0 || it.ti * rows >= d.n_b) bad("tile row", it.batch);
+        if (it.tj < 0 || it.tj * pts >= (hlist ? d.n_b : d.n_p)) bad("tile column", it.batch);
+      }
+}
+
 // Tile shapes by (points, basis count) bucket.  The density pass buckets its batches by basis
 // count, kDensityBuckets classes of 64 functions (the last open-ended); each class has its own
 // point-tile cap.  The H / S pass buckets by basis count class and by whether the last 64-wide
@@ -707,6 +762,7 @@ ItemList& tile_list(aims_grid* g, BatchSet& bs, uint64_t key, bool counters = tr
     L->runs.push_back(runs);
   }
   if ((int64_t)L->items.size() > INT32_MAX) fail(AIMS_ERR_UNSUPPORTED, "too many tiles");
+  if (g->debug) debug_check(g, bs, L.get(), hlist ? "H work list" : "density work list");
   L->d_items = g->upload(L->items);
   size_t launches = 0;
   for (const auto& r : L->runs) launches += r.size();
@@ -772,6 +828,9 @@ void build_noalloc_set(aims_grid* g) {
   bs.merge = 0;
   bs.density = true;
   bs.batches = src.batches;
+  bs.batch_atoms = src.batch_atoms;     // host copies (the device tables are the density set's)
+  bs.batch_acol = src.batch_acol;
+  bs.batch_cols = src.batch_cols;
   bs.sys_batch_range = src.sys_batch_range;
   bs.sum_np_nb2 = src.sum_np_nb2;
   bs.sum_nb2 = src.sum_nb2;
@@ -815,6 +874,7 @@ aims_grid* build(const aims_system* sys, int n_sys, int device, void* stream) {
     for (int p = 0; p < 3; ++p) g->h_merge[p] = m;
   }
   if (const char* e = getenv("AIMS_FORCES_THREAD_PATH")) g->force_thread_path = atoi(e) != 0;
+  if (const char* e = getenv("AIMS_DEBUG")) g->debug = atoi(e) != 0;
 
   // ---- species, splines, atoms ----------------------------------------------------------
   std::vector<SpeciesDesc> species;
@@ -927,6 +987,8 @@ aims_grid* build(const aims_system* sys, int n_sys, int device, void* stream) {
   dv.pts = g->upload(g->pts_sorted);
   dv.perm = g->upload(perm);
   g->d_atom_xyz = g->upload(g->atom_xyz0);
+  g->d_atom_xyz0 = g->upload(g->atom_xyz0);
+  g->d_pos_flag = g->upload(std::vector<int>(1, 0));
   dv.atom_xyz = g->d_atom_xyz;
   dv.atom_species = g->upload(atom_species);
   dv.atom_sys = g->upload(atom_sys);
@@ -983,27 +1045,35 @@ void forward_only(aims_precision p, const char* what) {
   if (p == AIMS_INT8X7) fail(AIMS_ERR_UNSUPPORTED, "%s: AIMS_INT8X7 serves the density, H and S passes only", what);
 }
 
-// Positions for this call: NULL = setup positions.  A given array (host or device) is read
-// synchronously and checked against the screening margin.
+// Positions for this call: NULL = setup positions (restored on the device).  A device array is
+// copied and checked on the device, with no host synchronisation (so the call can be captured):
+// if any atom is not finite or moved more than screen_margin, the call's outputs become NaN
+// (poison_outputs) and aims_positions_status reports AIMS_ERR_STALE.  A host array is checked on
+// the host before any launch.
 void set_positions(aims_grid* g, const double* xyz) {
   const size_t n = 3 * (size_t)g->n_atoms;
+  g->pos_async = false;
   if (!xyz) {
     if (g->moved) {
-      hipchk(hipMemcpyAsync(g->d_atom_xyz, g->atom_xyz0.data(), n * sizeof(double),
-                            hipMemcpyHostToDevice, g->stream), "restore positions");
-      hipchk(hipStreamSynchronize(g->stream), "restore positions");
+      hipchk(hipMemcpyAsync(g->d_atom_xyz, g->d_atom_xyz0, n * sizeof(double), hipMemcpyDeviceToDevice,
+                            g->stream), "restore positions");
+      hipchk(launch_positions_check(g->d_atom_xyz, g->d_atom_xyz0, g->n_atoms, g->margin, g->d_pos_flag,
+                                    g->stream), "position check");
       g->moved = false;
     }
     return;
   }
-  std::vector<double> h(n);
   if (is_device_ptr(xyz)) {
     require_device(xyz, "atom_xyz", n * sizeof(double));
-    hipchk(hipMemcpyAsync(h.data(), xyz, n * sizeof(double), hipMemcpyDeviceToHost, g->stream), "read positions");
-    hipchk(hipStreamSynchronize(g->stream), "read positions");
-  } else {
-    memcpy(h.data(), xyz, n * sizeof(double));
+    hipchk(hipMemcpyAsync(g->d_atom_xyz, xyz, n * sizeof(double), hipMemcpyDeviceToDevice, g->stream),
+           "positions");
+    hipchk(launch_positions_check(g->d_atom_xyz, g->d_atom_xyz0, g->n_atoms, g->margin, g->d_pos_flag,
+                                  g->stream), "position check");
+    g->moved = true;
+    g->pos_async = true;
+    return;
   }
+  std::vector<double> h(xyz, xyz + n);
   for (int a = 0; a < g->n_atoms; ++a) {
     double d2 = 0;
     for (int c = 0; c < 3; ++c) {
@@ -1016,7 +1086,14 @@ void set_positions(aims_grid* g, const double* xyz) {
   }
   hipchk(hipMemcpyAsync(g->d_atom_xyz, h.data(), n * sizeof(double), hipMemcpyHostToDevice, g->stream), "positions");
   hipchk(hipStreamSynchronize(g->stream), "positions");
+  hipchk(launch_positions_check(g->d_atom_xyz, g->d_atom_xyz0, g->n_atoms, g->margin, g->d_pos_flag,
+                                g->stream), "position check");
   g->moved = true;
+}
+
+// Outputs of a call that took device positions: NaN if those failed the check.
+void poison_outputs(aims_grid* g, double* x, size_t n) {
+  if (g->pos_async && x) hipchk(launch_poison(x, n, g->d_pos_flag, g->stream), "position check");
 }
 
 enum { kProfPhi = 0, kProfDensity = 1, kProfHS = 2, kProfBackward = 3, kProfFinish = 4, kProfOperands = 5 };
@@ -1316,8 +1393,16 @@ void hs_call(aims_grid* g, aims_precision prec, int mode, const double* v, doubl
   }
 }
 
+// A roctx range around each C-ABI call, so that traces (rocprofv3 --marker-trace) show which
+// call issued which kernels.
+struct CallRange {
+  explicit CallRange(const char* name) { roctxRangePush(name); }
+  ~CallRange() { roctxRangePop(); }
+};
+
 template <typename F>
-aims_status guarded(aims_grid* g, F&& f) {
+aims_status guarded(const char* name, aims_grid* g, F&& f) {
+  CallRange range(name);
   try {
     if (!g) fail(AIMS_ERR_ARG, "null handle");
     hipchk(hipSetDevice(g->device), "hipSetDevice");
@@ -1546,7 +1631,7 @@ aims_status aims_grid_setup(const aims_system* sys, int device, void* hip_stream
 aims_status aims_update_density(aims_grid* g, aims_precision prec, const double* atom_xyz,
                                 const double* P, const double* v_or_null, double* n_out,
                                 double* sums_out) {
-  return guarded(g, [&] {
+  return guarded(__func__, g, [&] {
     check_prec(prec);
     require_device(P, "P", (size_t)g->mat_total * sizeof(double));
     require_device(n_out, "n_out", (size_t)g->n_points * sizeof(double));
@@ -1554,12 +1639,14 @@ aims_status aims_update_density(aims_grid* g, aims_precision prec, const double*
     if (v_or_null) require_device(v_or_null, "v", (size_t)g->n_points * sizeof(double));
     set_positions(g, atom_xyz);
     density_call(g, prec, P, v_or_null, n_out, sums_out);
+    poison_outputs(g, n_out, (size_t)g->n_points);
+    poison_outputs(g, sums_out, 3 * (size_t)g->n_sys);
   });
 }
 
 aims_status aims_update_density_noalloc(aims_grid* g, aims_precision prec, const double* P,
                                         const double* v_or_null, double* n_out, double* sums_out) {
-  return guarded(g, [&] {
+  return guarded(__func__, g, [&] {
     check_prec(prec);
     require_device(P, "P", (size_t)g->mat_total * sizeof(double));
     require_device(n_out, "n_out", (size_t)g->n_points * sizeof(double));
@@ -1573,7 +1660,7 @@ aims_status aims_update_density_noalloc(aims_grid* g, aims_precision prec, const
 
 aims_status aims_integrate_h(aims_grid* g, aims_precision prec, const double* atom_xyz, const double* v,
                              double* H, double* S_or_null) {
-  return guarded(g, [&] {
+  return guarded(__func__, g, [&] {
     check_prec(prec);
     require_device(v, "v", (size_t)g->n_points * sizeof(double));
     require_device(H, "H", (size_t)g->mat_total * sizeof(double));
@@ -1581,12 +1668,14 @@ aims_status aims_integrate_h(aims_grid* g, aims_precision prec, const double* at
     set_positions(g, atom_xyz);
     hs_call(g, prec, kModeH, v, H);
     if (S_or_null) hs_call(g, prec, kModeS, v, S_or_null);
+    poison_outputs(g, H, (size_t)g->mat_total);
+    poison_outputs(g, S_or_null, (size_t)g->mat_total);
   });
 }
 
 aims_status aims_integrate_h_gga(aims_grid* g, aims_precision prec, const double* v,
                                  const double* u, double* H) {
-  return guarded(g, [&] {
+  return guarded(__func__, g, [&] {
     check_prec(prec);
     if (prec == AIMS_BF16X3 || prec == AIMS_INT8X7)
       fail(AIMS_ERR_UNSUPPORTED, "the gradient term supports AIMS_FP64 and AIMS_FP32");
@@ -1603,7 +1692,7 @@ aims_status aims_integrate_h_backward(aims_grid* g, aims_precision prec, const d
                                       const double* P, const double* v, const double* gE,
                                       double* dE_dP_or_null, double* dE_dv_or_null,
                                       double* dE_dR_or_null) {
-  return guarded(g, [&] {
+  return guarded(__func__, g, [&] {
     check_prec(prec);
     forward_only(prec, "the backward");
     require_device(P, "P", (size_t)g->mat_total * sizeof(double));
@@ -1623,11 +1712,16 @@ aims_status aims_integrate_h_backward(aims_grid* g, aims_precision prec, const d
       hs_call(g, prec, kModeH, v, dE_dP_or_null);
       hipchk(launch_scale(dE_dP_or_null, dE_dP_or_null, (size_t)g->mat_total, gE, st), "scale dE/dP");
     }
-    if (!dE_dv_or_null && !dE_dR_or_null) return;
+    if (!dE_dv_or_null && !dE_dR_or_null) {
+      poison_outputs(g, dE_dP_or_null, (size_t)g->mat_total);
+      return;
+    }
     if (!dE_dR_or_null) {
       // n (for dE/dv) from a plain density pass
       density_call(g, prec, P, v, g->d_ntmp, g->d_sums_tmp);
       hipchk(launch_dv(g->dens.dv, dE_dv_or_null, g->d_n_sorted, g->n_points, gE, st), "dE/dv");
+      poison_outputs(g, dE_dP_or_null, (size_t)g->mat_total);
+      poison_outputs(g, dE_dv_or_null, (size_t)g->n_points);
       return;
     }
     // dE/dR: X = Phi P_b (whose pass also forms n, for dE/dv) and Y = (T Phi) P_b per batch,
@@ -1707,11 +1801,14 @@ aims_status aims_integrate_h_backward(aims_grid* g, aims_precision prec, const d
     }
     if (dE_dv_or_null)
       hipchk(launch_dv(g->dens.dv, dE_dv_or_null, g->d_n_sorted, g->n_points, gE, st), "dE/dv");
+    poison_outputs(g, dE_dP_or_null, (size_t)g->mat_total);
+    poison_outputs(g, dE_dv_or_null, (size_t)g->n_points);
+    poison_outputs(g, dE_dR_or_null, 3 * (size_t)g->n_atoms);
   });
 }
 
 aims_status aims_grid_set_moving(aims_grid* g, int32_t sys, const aims_moving_grid* m) {
-  return guarded(g, [&] {
+  return guarded(__func__, g, [&] {
     if (!m) fail(AIMS_ERR_ARG, "null moving-grid description");
     if (sys < 0 || sys >= g->n_sys) fail(AIMS_ERR_ARG, "system %d out of range", sys);
     if (!(m->nuc_sigma > 0.0) || !std::isfinite(m->nuc_sigma)) fail(AIMS_ERR_ARG, "nuc_sigma must be > 0");
@@ -1767,7 +1864,7 @@ aims_status aims_grid_set_moving(aims_grid* g, int32_t sys, const aims_moving_gr
 
 aims_status aims_total_forces(aims_grid* g, aims_precision prec, const double* P, const double* gE,
                               double* sums_out_or_null, double* dE_dR) {
-  return guarded(g, [&] {
+  return guarded(__func__, g, [&] {
     check_prec(prec);
     if (prec == AIMS_BF16X3 || prec == AIMS_INT8X7)
       fail(AIMS_ERR_UNSUPPORTED, "total forces support AIMS_FP64 and AIMS_FP32");
@@ -1883,7 +1980,7 @@ aims_status aims_total_forces(aims_grid* g, aims_precision prec, const double* P
 aims_status aims_density_matrix(aims_grid* g, int32_t method, const double* H, const double* S,
                                 const double* n_electrons, double kT, double* P_out,
                                 double* eps_out_or_null, double* mu_out_or_null) {
-  return guarded(g, [&] {
+  return guarded(__func__, g, [&] {
     if (method != AIMS_DM_EIGEN && method != AIMS_DM_PURIFY) fail(AIMS_ERR_ARG, "unknown method %d", method);
     if (!n_electrons) fail(AIMS_ERR_ARG, "null n_electrons");
     if (!(kT >= 0.0) || !std::isfinite(kT)) fail(AIMS_ERR_ARG, "kT must be finite and >= 0");
@@ -1923,7 +2020,7 @@ aims_status aims_density_matrix(aims_grid* g, int32_t method, const double* H, c
 }
 
 aims_status aims_grid_set_hartree(aims_grid* g, int32_t sys, const aims_hartree_grid* h) {
-  return guarded(g, [&] {
+  return guarded(__func__, g, [&] {
     if (!h) fail(AIMS_ERR_ARG, "null Hartree grid description");
     if (sys < 0 || sys >= g->n_sys) fail(AIMS_ERR_ARG, "system %d out of range", sys);
     if (h->n_radial < 3 || h->n_radial > 4096) fail(AIMS_ERR_ARG, "n_radial must be in 3..4096");
@@ -1961,7 +2058,7 @@ aims_status aims_grid_set_hartree(aims_grid* g, int32_t sys, const aims_hartree_
 
 
 aims_status aims_hartree(aims_grid* g, const double* n, double* v_out, double* E_out_or_null) {
-  return guarded(g, [&] {
+  return guarded(__func__, g, [&] {
     if (g->h_K.empty()) fail(AIMS_ERR_ARG, "no Hartree grid set (aims_grid_set_hartree)");
     for (int k = 0; k < g->n_sys; ++k)
       if (!g->h_K[k]) fail(AIMS_ERR_ARG, "system %d has no Hartree grid", k);
@@ -1977,7 +2074,7 @@ aims_status aims_hartree(aims_grid* g, const double* n, double* v_out, double* E
 
 aims_status aims_xc_gga(aims_grid* g, int32_t functional, const double* n, const double* grad_n,
                         double* v_out, double* u_out, double* sums_out_or_null) {
-  return guarded(g, [&] {
+  return guarded(__func__, g, [&] {
     if (functional != AIMS_XC_PBE) fail(AIMS_ERR_UNSUPPORTED, "aims_xc_gga takes AIMS_XC_PBE");
     require_device(n, "n", (size_t)g->n_points * sizeof(double));
     require_device(grad_n, "grad_n", 3 * (size_t)g->n_points * sizeof(double));
@@ -1992,7 +2089,7 @@ aims_status aims_xc_gga(aims_grid* g, int32_t functional, const double* n, const
 
 aims_status aims_density_gradient(aims_grid* g, const double* P, double* n_out_or_null,
                                   double* grad_out) {
-  return guarded(g, [&] {
+  return guarded(__func__, g, [&] {
     require_device(P, "P", (size_t)g->mat_total * sizeof(double));
     require_device(grad_out, "grad_out", 3 * (size_t)g->n_points * sizeof(double));
     if (n_out_or_null) require_device(n_out_or_null, "n_out", (size_t)g->n_points * sizeof(double));
@@ -2041,7 +2138,7 @@ aims_status aims_density_gradient(aims_grid* g, const double* P, double* n_out_o
 
 aims_status aims_xc(aims_grid* g, int32_t functional, const double* n, double* v_xc_out,
                     double* sums_out_or_null) {
-  return guarded(g, [&] {
+  return guarded(__func__, g, [&] {
     if (functional == AIMS_XC_PBE) fail(AIMS_ERR_UNSUPPORTED, "PBE needs the density gradient (aims_xc_gga)");
     if (functional != AIMS_XC_LDA_PW92) fail(AIMS_ERR_UNSUPPORTED, "unknown functional %d", functional);
     require_device(n, "n", (size_t)g->n_points * sizeof(double));
@@ -2060,7 +2157,7 @@ struct aims_step_graph {
 
 aims_status aims_step_graph_create(aims_grid* g, aims_precision prec, const double* P, const double* v,
                                    double* n_out, double* sums_out, double* H, aims_step_graph** out) {
-  return guarded(g, [&] {
+  return guarded(__func__, g, [&] {
     if (!out) fail(AIMS_ERR_ARG, "out is NULL");
     *out = nullptr;
     check_prec(prec);
@@ -2106,7 +2203,7 @@ void aims_step_graph_destroy(aims_step_graph* graph) {
 }
 
 aims_status aims_profile_enable(aims_grid* g, int on) {
-  return guarded(g, [&] {
+  return guarded(__func__, g, [&] {
     prof_collect(g);
     g->profiling = on != 0;
     for (int k = 0; k < 6; ++k) {
@@ -2119,7 +2216,7 @@ aims_status aims_profile_enable(aims_grid* g, int on) {
 
 aims_status aims_profile_read(aims_grid* g, const char* kernel, int64_t* launches, double* total_ms,
                               double* work) {
-  return guarded(g, [&] {
+  return guarded(__func__, g, [&] {
     if (!kernel) fail(AIMS_ERR_ARG, "kernel name is NULL");
     int k = -1;
     for (int i = 0; i < 6; ++i)
@@ -2145,7 +2242,7 @@ aims_status aims_get_tuning(const aims_grid* g, aims_precision prec, aims_tuning
 }
 
 aims_status aims_set_tuning(aims_grid* g, aims_precision prec, const aims_tuning* t) {
-  return guarded(g, [&] {
+  return guarded(__func__, g, [&] {
     if (!t || prec < AIMS_FP64 || prec > AIMS_INT8X7) fail(AIMS_ERR_ARG, "bad tuning arguments");
     if (t->h_merge < 0 || t->h_merge > 4) fail(AIMS_ERR_ARG, "h_merge must be in 0..4");
     if (t->density_pblocks < 2 || t->density_pblocks > 5) fail(AIMS_ERR_ARG, "density_pblocks must be in 2..5");
@@ -2176,7 +2273,7 @@ aims_status aims_set_tuning(aims_grid* g, aims_precision prec, const aims_tuning
 // 2 kDensityBuckets buckets).
 aims_status aims_bucket_stats(aims_grid* g, aims_precision prec, int32_t which, int64_t* batches_out,
                               double* flops_out) {
-  return guarded(g, [&] {
+  return guarded(__func__, g, [&] {
     check_prec(prec);
     if (which != 0 && which != 1) fail(AIMS_ERR_ARG, "which must be 0 (density) or 1 (H)");
     if (!batches_out || !flops_out) fail(AIMS_ERR_ARG, "null output");
@@ -2191,6 +2288,16 @@ aims_status aims_bucket_stats(aims_grid* g, aims_precision prec, int32_t which, 
       batches_out[b] += 1;
       flops_out[b] += 2.0 * d.n_p * (double)d.n_b * d.n_b;
     }
+  });
+}
+
+aims_status aims_positions_status(aims_grid* g) {
+  return guarded(__func__, g, [&] {
+    int flag = 0;
+    hipchk(hipMemcpyAsync(&flag, g->d_pos_flag, sizeof(int), hipMemcpyDeviceToHost, g->stream), "status");
+    hipchk(hipStreamSynchronize(g->stream), "status");
+    if (flag) fail(AIMS_ERR_STALE, "the last positions given on the device moved an atom beyond screen_margin "
+                                   "(or were not finite); that call's outputs are NaN");
   });
 }
 

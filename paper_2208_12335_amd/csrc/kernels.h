@@ -109,6 +109,11 @@ hipError_t launch_hs(const DeviceView& dv, const TileItem* items, int n_items, c
 hipError_t launch_hs_bf16(const DeviceView& dv, const TileItem* items, int n_items, const void* slab1,
                           const void* slab2, double* out, hipStream_t st, Queue q = Queue());
 hipError_t launch_zero_int(int* x, int n, hipStream_t st);
+// Positions given on the device: flag = 1 if any atom is not finite or farther than margin from
+// xyz0; the outputs of such a call are then set to NaN (launch_poison, a no-op when flag = 0).
+hipError_t launch_positions_check(const double* xyz, const double* xyz0, int n, double margin,
+                                  int* flag, hipStream_t st);
+hipError_t launch_poison(double* x, size_t n, const int* flag, hipStream_t st);
 // Sliced integer form (int8.hip): P as digit words with one exponent per row; basis slabs of
 // digit words with per-point (density) or per-column (H, S) exponents; the tiled int8 kernels.
 hipError_t launch_slice_p(const DeviceView& dv, const double* P, uint64_t* P8, int32_t* eP,

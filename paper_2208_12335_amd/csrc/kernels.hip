@@ -1223,6 +1223,47 @@ int tile_grid(int n_items, const Queue& q, const void* fn) {
   return std::min(g, std::max(8, res / 8 * 8));
 }
 
+// Screening check of positions held on the device: flag = 1 if any atom is not finite or moved
+// farther than the margin from its set-up position, else 0.  One workgroup.
+__global__ void __launch_bounds__(256)
+positions_check_kernel(const double* __restrict__ xyz, const double* __restrict__ xyz0, int n,
+                       double margin2, int* __restrict__ flag) {
+  int bad = 0;
+  for (int a = threadIdx.x; a < n; a += blockDim.x) {
+    double d2 = 0.0;
+    bool fin = true;
+    for (int c = 0; c < 3; ++c) {
+      const double x = xyz[3 * a + c];
+      fin = fin && isfinite(x);
+      const double d = x - xyz0[3 * a + c];
+      d2 += d * d;
+    }
+    if (!fin || !(d2 <= margin2)) bad = 1;
+  }
+  bad = __syncthreads_or(bad);
+  if (threadIdx.x == 0) *flag = bad;
+}
+
+// The outputs of a call whose device positions failed the check become NaN (a no-op otherwise).
+__global__ void poison_kernel(double* __restrict__ x, size_t n, const int* __restrict__ flag) {
+  if (*flag == 0) return;
+  const double nan = __builtin_nan("");
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    x[i] = nan;
+}
+
+hipError_t launch_positions_check(const double* xyz, const double* xyz0, int n, double margin,
+                                  int* flag, hipStream_t st) {
+  hipLaunchKernelGGL(positions_check_kernel, dim3(1), dim3(256), 0, st, xyz, xyz0, n, margin * margin, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_poison(double* x, size_t n, const int* flag, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(poison_kernel, dim3(grid_for(n, 256 * 4)), dim3(256), 0, st, x, n, flag);
+  return hipGetLastError();
+}
+
 __global__ void zero_int_kernel(int* __restrict__ x, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) x[i] = 0;
 }

@@ -347,6 +347,11 @@ class AimsGrid:
                                               nb, fl))
         return list(nb), list(fl)
 
+    def positions_status(self):
+        """Raises AimsError (AIMS_ERR_STALE) if the last positions given as a device tensor
+        failed the screening check (that call's outputs are NaN)."""
+        self._check(self._L.aims_positions_status(self._h))
+
     def profile(self, on: bool = True):
         self._check(self._L.aims_profile_enable(self._h, 1 if on else 0))
 
@@ -425,11 +430,13 @@ class AimsEnergy(torch.autograd.Function):
             raise ValueError("AimsEnergy handles one system per handle")
         # The backward's dE/dR takes X = Phi P and Y = (T Phi) P, which is the gradient only for
         # a symmetric P (a general P needs Phi (P + P^T)/2 and (T Phi) P^T), so another P is refused.
+        # (checked outside stream capture, where reading the result back is allowed)
         nb = grid.nb_sys[0]
         Pm = P.detach().reshape(nb, nb)
-        scale = float(Pm.abs().max()) if Pm.numel() else 0.0
-        if Pm.numel() and float((Pm - Pm.T).abs().max()) > 1e-12 * max(scale, 1e-300):
-            raise ValueError("AimsEnergy needs a symmetric P (max|P - P^T| above 1e-12 max|P|)")
+        if Pm.numel() and not torch.cuda.is_current_stream_capturing():
+            scale = float(Pm.abs().max())
+            if float((Pm - Pm.T).abs().max()) > 1e-12 * max(scale, 1e-300):
+                raise ValueError("AimsEnergy needs a symmetric P (max|P - P^T| above 1e-12 max|P|)")
         _, sums = grid.update_density(P.detach().contiguous(), v.detach().contiguous(), prec=prec,
                                       atom_xyz=R.detach())
         ctx.grid, ctx.prec = grid, prec

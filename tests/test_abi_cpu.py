@@ -151,3 +151,18 @@ def test_binding_refuses_wrong_sizes_on_host():
     g.device = torch.device("cuda", 0)
     with pytest.raises(ValueError, match="handle is on"):
         g._arg(ok, 12, "P")
+
+
+def test_valid_setup_runs_host_stages_then_needs_a_device(lib, c1):
+    """A valid system passes validation, and the host stages of set-up (natural splines of
+    every shell, the bisection of the points into batches) run before the first device call;
+    without a GPU the call then fails cleanly (a HIP error, no handle).  Under the host
+    sanitizers this exercises the host set-up code end to end."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present: set-up would succeed")
+    s, keep = _system(c1)
+    h = ctypes.c_void_p()
+    st = lib.aims_grid_setup(ctypes.byref(s), 0, None, ctypes.byref(h))
+    assert st == -3 and h.value is None
+    assert len(lib.aims_last_error(None).decode()) > 5

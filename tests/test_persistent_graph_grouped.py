@@ -152,3 +152,26 @@ def test_autotune_live(gpu, cluster, tmp_path):
     r2 = autotune(g2, P, v, prec="fp64", cache=cache)
     assert r2["source"] == "cache" and r2["key"] == r["key"]
     assert g2.get_tuning("fp64") == t
+
+
+def test_debug_table_checks(gpu, monkeypatch):
+    """AIMS_DEBUG=1 checks every index table of every batch set and work list on the host as it
+    is built (set-up, the H partitions of the tunings set below, per-bucket tile lists, the
+    allocation-free set); a grouped handle and a cluster pass, and their results are unchanged."""
+    monkeypatch.setenv("AIMS_DEBUG", "1")
+    mols = synth.make_molecule_set(n_mol=6, seed=4, n_min=3, n_max=12)
+    inst = synth.make_instance("c2", n_atoms=12, box=9.0, seed=6)
+    for systems in (mols, [inst]):
+        g = AimsGrid(systems, device=gpu.index)
+        for t in (dict(h_merge=2), dict(h_flops_per_atomic=256, h_tile32_mask=0xffff),
+                  dict(density_bucket_pblocks=[5, 4, 3, 2, 5, 4, 3, 2])):
+            g.set_tuning(prec="fp64", **t)
+        P = torch.cat([torch.from_numpy(m.P).reshape(-1) for m in systems]).to(gpu)
+        v = torch.cat([torch.from_numpy(m.v) for m in systems]).to(gpu)
+        n, sums = g.update_density(P, v)
+        H, _ = g.integrate_h(v)
+        torch.cuda.synchronize()
+        k = len(systems) - 1
+        o = GridOracle(systems[k])
+        Hr, _ = o.integrate_h(systems[k].v, want_S=False)
+        assert relerr(g.blocks(H)[k].cpu().numpy(), Hr) <= 1e-10
