@@ -267,7 +267,16 @@ def bench_single(args, torch, inst, backward=False):
             if meth == "purify":
                 k = g.last_purify_products()
                 r["products"] = k
-                r["gemm_tflops"] = (k + 4) * 2.0 * inst.n_basis ** 3 / (ms_dm * 1e-3) / 1e12
+                # the inverse factor of S is kept while S is unchanged (every s.c.f. iteration
+                # after the first); alternating two overlap matrices times the call that also
+                # factorises S
+                S_alt = (S * (1.0 + 2.0 ** -40)).contiguous()
+                flip = [S_alt, S]
+                def solve_factor():
+                    flip.reverse()
+                    g.density_matrix(H, flip[0], n_e, method=meth, P_out=P_new, want_eps=False)
+                r["ms_with_factorisation"], _ = timer.run(solve_factor, 4, 0)
+                r["symmetric_product_tflops"] = k * float(inst.n_basis) ** 3 / (ms_dm * 1e-3) / 1e12
             ms_it = res["fp64"]["ms_per_step"] + ms_dm
             r["scf_iteration_ms"] = ms_it
             r["density_matrix_share"] = ms_dm / ms_it

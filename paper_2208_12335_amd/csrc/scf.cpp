@@ -11,8 +11,10 @@
 //    spectral projector onto the N_e / 2 lowest states of H' by trace-correcting purification:
 //    X_0 = (e_max I - H') / (e_max - e_min) from Gershgorin bounds, then repeatedly X <- X^2 when
 //    tr X exceeds N_e / 2 and X <- 2 X - X^2 otherwise, until X^2 = X; P = 2 L^{-T} X L^{-1}.
-//    Every step is a GEMM whose coefficients a small kernel picks on the device, so the loop
-//    needs no host round trip except a convergence check every few products.  It needs an even
+//    Every step is one fused kernel (the symmetric product on the FP64 matrix cores, with the
+//    choice between the two polynomials taken on the device from the trace the previous step
+//    left), and the device also decides when to stop, so the host only reads a flag every few
+//    products.  L^{-1} is kept between calls and reused while S is unchanged.  It needs an even
 //    electron count, aufbau occupations and a gap at the Fermi level.
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
@@ -31,10 +33,10 @@ namespace {
 
 constexpr int kStatusArg = -1, kStatusOom = -2, kStatusHip = -3, kStatusUnsupported = -5;
 constexpr int kMaxPurify = 160;        // purification products before giving up
-constexpr int kCheckEvery = 4;         // products between convergence checks
+constexpr int kBatch = 8;              // products launched between reads of the device state
 
 // layout of DmSolver::small
-constexpr int kBounds = 0, kCoef = 2, kHist = 8, kPart = 768;
+constexpr int kBounds = 0, kState = 4, kHist = 8;
 
 int fail_msg(std::string& err, int code, const char* fmt, ...) {
   char buf[512];
@@ -60,10 +62,11 @@ int fail_msg(std::string& err, int code, const char* fmt, ...) {
   } while (0)
 
 void free_matrices(DmSolver& s) {
-  for (double** p : {&s.A, &s.B, &s.X, &s.Y, &s.T, &s.vec, &s.vec2}) {
+  for (double** p : {&s.A, &s.B, &s.X, &s.Y, &s.T, &s.vec, &s.vec2, &s.part, &s.W, &s.Lk, &s.Sk}) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
   }
+  s.k_n = 0;
   s.cap = 0;
 }
 
@@ -74,14 +77,24 @@ int ensure(DmSolver& s, int n, std::string& err) {
     s.blas = h;
   }
   DM_BLAS(rocblas_set_stream((rocblas_handle)s.blas, s.stream), "rocblas_set_stream");
-  const size_t need = std::max<size_t>(1, (size_t)n * n);
+  if (!s.cus) {
+    int dev = 0;
+    DM_HIP(hipGetDevice(&dev), "hipGetDevice");
+    DM_HIP(hipDeviceGetAttribute(&s.cus, hipDeviceAttributeMultiprocessorCount, dev), "device attribute");
+  }
+  // every work matrix holds ld x ld (X and Y of the purification use that leading dimension)
+  const int ld = (n + 63) / 64 * 64;
+  const size_t need = std::max<size_t>(1, (size_t)ld * ld);
   if (need > s.cap) {
     free_matrices(s);
     bool ok = true;
-    for (double** p : {&s.A, &s.B, &s.X, &s.Y, &s.T})
+    for (double** p : {&s.A, &s.B, &s.X, &s.Y, &s.T, &s.Lk, &s.Sk})
       ok = ok && hipMalloc(p, need * sizeof(double)) == hipSuccess;
     for (double** p : {&s.vec, &s.vec2})
-      ok = ok && hipMalloc(p, 2 * std::max<size_t>(1, (size_t)n) * sizeof(double)) == hipSuccess;
+      ok = ok && hipMalloc(p, 2 * std::max<size_t>(1, (size_t)ld) * sizeof(double)) == hipSuccess;
+    const size_t nt = (size_t)std::max(1, purify_tiles(ld));
+    ok = ok && hipMalloc(&s.part, 4 * nt * sizeof(double)) == hipSuccess;
+    ok = ok && hipMalloc(&s.W, 4096 * (size_t)std::max(8, s.cus) * sizeof(double)) == hipSuccess;
     if (!ok) {
       (void)hipGetLastError();
       free_matrices(s);
@@ -197,8 +210,42 @@ int solve_eigen(DmSolver& s, int n, double n_elec, double kT, double* P, double*
   return 0;
 }
 
-int solve_purify(DmSolver& s, int n, double n_elec, double kT, double* P, double* mu,
-                 std::string& err) {
+// L^{-1} of S (lower, upper triangle zero) in s.Lk.  It is kept: while S is bitwise the matrix
+// it came from (the overlap changes only with the geometry, so in an s.c.f. loop every iteration
+// after the first) the Cholesky factorisation and the triangular inverse are skipped.
+int inverse_factor(DmSolver& s, int n, const double* S, std::string& err) {
+  rocblas_handle h = (rocblas_handle)s.blas;
+  const size_t elems = (size_t)n * n;
+  if (s.k_n == n) {
+    DM_HIP(launch_differ(S, s.Sk, elems, s.info, s.stream), "compare S");
+    int differ = 1;
+    DM_HIP(hipMemcpyAsync(&differ, s.info, sizeof(int), hipMemcpyDeviceToHost, s.stream), "read flag");
+    DM_HIP(hipStreamSynchronize(s.stream), "synchronize");
+    if (!differ) {
+      s.last_factored = 0;
+      return 0;
+    }
+  }
+  s.k_n = 0;
+  s.last_factored = 1;
+  DM_HIP(hipMemcpyAsync(s.Lk, S, elems * sizeof(double), hipMemcpyDeviceToDevice, s.stream), "copy S");
+  DM_BLAS(rocblas_set_pointer_mode(h, rocblas_pointer_mode_host), "pointer mode");
+  // S = L L^T (lower, column-major), then L <- L^{-1} with the upper triangle cleared
+  DM_BLAS(rocsolver_dpotrf(h, rocblas_fill_lower, n, s.Lk, n, s.info), "rocsolver_dpotrf");
+  int info = 0;
+  DM_HIP(hipMemcpyAsync(&info, s.info, sizeof(int), hipMemcpyDeviceToHost, s.stream), "read info");
+  DM_HIP(hipStreamSynchronize(s.stream), "synchronize");
+  if (info != 0) return fail_msg(err, kStatusArg, "S is not positive definite (leading minor %d)", info);
+  DM_BLAS(rocsolver_dtrtri(h, rocblas_fill_lower, rocblas_diagonal_non_unit, n, s.Lk, n, s.info),
+          "rocsolver_dtrtri");
+  DM_HIP(launch_zero_upper(s.Lk, n, s.stream), "clear triangle");
+  DM_HIP(hipMemcpyAsync(s.Sk, S, elems * sizeof(double), hipMemcpyDeviceToDevice, s.stream), "keep S");
+  s.k_n = n;
+  return 0;
+}
+
+int solve_purify(DmSolver& s, int n, const double* S, double n_elec, double kT, double* P,
+                 double* mu, std::string& err) {
   if (kT != 0.0) return fail_msg(err, kStatusUnsupported, "purification takes aufbau occupations (kT = 0)");
   const double n_occ = 0.5 * n_elec;
   if (n_occ != std::floor(n_occ))
@@ -213,79 +260,72 @@ int solve_purify(DmSolver& s, int n, double n_elec, double kT, double* P, double
     DM_HIP(hipMemsetAsync(P, 0, bytes, s.stream), "clear P");
     return 0;
   }
+  int rc = inverse_factor(s, n, S, err);
+  if (rc) return rc;
+  const double* Li = s.Lk;
   DM_BLAS(rocblas_set_pointer_mode(h, rocblas_pointer_mode_host), "pointer mode");
-  // S = L L^T (lower, column-major) in B, then B <- L^{-1} with the upper triangle cleared
-  DM_BLAS(rocsolver_dpotrf(h, rocblas_fill_lower, n, s.B, n, s.info), "rocsolver_dpotrf");
-  int info = 0;
-  DM_HIP(hipMemcpyAsync(&info, s.info, sizeof(int), hipMemcpyDeviceToHost, s.stream), "read info");
-  DM_HIP(hipStreamSynchronize(s.stream), "synchronize");
-  if (info != 0) return fail_msg(err, kStatusArg, "S is not positive definite (leading minor %d)", info);
-  DM_BLAS(rocsolver_dtrtri(h, rocblas_fill_lower, rocblas_diagonal_non_unit, n, s.B, n, s.info),
-          "rocsolver_dtrtri");
-  DM_HIP(launch_zero_upper(s.B, n, s.stream), "clear triangle");
-  // H' = L^{-1} H_s L^{-T}: T = H_s L^{-T}, X = L^{-1} T
+  // H' = L^{-1} H_s L^{-T}: T = H_s L^{-T}, A = L^{-1} T
   DM_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, n, n, n, &one, s.A,
-                        n, s.B, n, &zero, s.T, n),
+                        n, Li, n, &zero, s.T, n),
           "rocblas_dgemm");
-  DM_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, n, n, n, &one, s.B, n,
+  DM_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, n, n, n, &one, Li, n,
                         s.T, n, &zero, s.A, n),
           "rocblas_dgemm");
+  const int ld = (n + 63) / 64 * 64;             // X and Y: ld x ld, zero outside n x n
+  double* X = s.X;
   if (n_occ == n) {                               // every state full: X = I
-    DM_HIP(hipMemsetAsync(s.X, 0, bytes, s.stream), "clear X");
+    DM_HIP(hipMemsetAsync(s.X, 0, (size_t)ld * ld * sizeof(double), s.stream), "clear X");
     std::vector<double> ones(n, 1.0);
-    DM_HIP(hipMemcpy2DAsync(s.X, (n + 1) * sizeof(double), ones.data(), sizeof(double),
+    DM_HIP(hipMemcpy2DAsync(s.X, (ld + 1) * sizeof(double), ones.data(), sizeof(double),
                             sizeof(double), n, hipMemcpyHostToDevice, s.stream),
            "identity");
     DM_HIP(hipStreamSynchronize(s.stream), "synchronize");
   } else {
     double* sm = s.small;
+    const int nt = purify_tiles(ld);
+    double* part[2] = {s.part, s.part + 2 * nt};
+    double* buf[2] = {s.X, s.Y};
+    const PurifyPlan plan = purify_plan(ld, s.cus);
+    const double tol = 1e-8 * std::max(1.0, n_occ);
     DM_HIP(launch_gershgorin(s.A, n, s.vec, sm + kBounds, s.stream), "bounds");
-    DM_HIP(launch_purify_init(s.A, s.X, n, sm + kBounds, s.stream), "purify init");
-    DM_BLAS(rocblas_set_pointer_mode(h, rocblas_pointer_mode_device), "pointer mode");
-    double hist[2 * kMaxPurify];
-    bool done = false;
-    int it = 0, small_at = -1;
-    while (!done) {
+    DM_HIP(launch_purify_init(s.A, s.X, n, ld, sm + kBounds, s.stream), "purify init");
+    DM_HIP(launch_purify_partials(s.X, ld, part[0], sm + kState, s.stream), "purify shares");
+    // products in batches with no host round trip; the device stops the iteration itself
+    double state[2] = {-1.0, -1.0};
+    int it = 0;
+    while (state[1] < 0.0) {
       if (it >= kMaxPurify) {
-        DM_BLAS(rocblas_set_pointer_mode(h, rocblas_pointer_mode_host), "pointer mode");
-        return fail_msg(err, kStatusHip,
-                        "purification did not converge in %d products (no gap at the Fermi level?)",
-                        kMaxPurify);
-      }
-      DM_HIP(launch_purify_coef(s.X, n, n_occ, sm + kCoef, sm + kHist, it, s.stream), "coefficients");
-      DM_HIP(launch_frob2(s.X, n, sm + kPart, sm + kHist, it, s.stream), "norm");
-      DM_HIP(hipMemcpyAsync(s.Y, s.X, bytes, hipMemcpyDeviceToDevice, s.stream), "copy");
-      // Y = a X X + b Y  (a, b on the device)
-      DM_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, n, n, n, sm + kCoef,
-                            s.X, n, s.X, n, sm + kCoef + 1, s.Y, n),
-              "rocblas_dgemm");
-      std::swap(s.X, s.Y);
-      ++it;
-      if (it % kCheckEvery == 0) {
-        DM_HIP(hipMemcpyAsync(hist, sm + kHist, 2 * it * sizeof(double), hipMemcpyDeviceToHost,
+        double hist[2];
+        DM_HIP(hipMemcpyAsync(hist, sm + kHist + 2 * (it - 1), sizeof(hist), hipMemcpyDeviceToHost,
                               s.stream),
                "read history");
         DM_HIP(hipStreamSynchronize(s.stream), "synchronize");
-        // idempotency error tr X - ||X||_F^2 (of the matrix before each product)
-        for (int k = std::max(0, it - kCheckEvery); k < it && !done; ++k) {
-          const double e = std::fabs(hist[2 * k] - hist[2 * k + 1]);
-          if (small_at < 0 && e < 1e-8 * std::max(1.0, n_occ)) small_at = k;
-          // after the error is small, quadratic convergence needs a few more products
-          if (small_at >= 0 && k >= small_at + 3) done = true;
-        }
+        return fail_msg(err, kStatusHip,
+                        "purification did not converge in %d products (tr X %.17g, ||X||_F^2 %.17g; "
+                        "no gap at the Fermi level?)",
+                        kMaxPurify, hist[0], hist[1]);
       }
+      const int batch = std::min(kBatch, kMaxPurify - it);
+      for (int b = 0; b < batch; ++b, ++it)
+        DM_HIP(launch_purify_step(buf[it & 1], buf[(it + 1) & 1], ld, n_occ, part[it & 1],
+                                  part[(it + 1) & 1], plan, s.W, sm + kHist, it, tol, sm + kState,
+                                  s.stream),
+               "purification product");
+      DM_HIP(hipMemcpyAsync(state, sm + kState, sizeof(state), hipMemcpyDeviceToHost, s.stream),
+             "read state");
+      DM_HIP(hipStreamSynchronize(s.stream), "synchronize");
     }
-    DM_BLAS(rocblas_set_pointer_mode(h, rocblas_pointer_mode_host), "pointer mode");
-    s.last_iterations = it;
+    s.last_iterations = (int)state[1];
+    X = buf[s.last_iterations & 1];
   }
   // P = 2 L^{-T} X L^{-1}: T = X L^{-1}, P = 2 L^{-T} T
-  DM_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, n, n, n, &one, s.X, n,
-                        s.B, n, &zero, s.T, n),
+  DM_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, n, n, n, &one, X, ld, Li,
+                        n, &zero, s.T, n),
           "rocblas_dgemm");
-  DM_BLAS(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, n, n, n, &two, s.B,
-                        n, s.T, n, &zero, s.Y, n),
+  DM_BLAS(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, n, n, n, &two, Li,
+                        n, s.T, n, &zero, s.B, n),
           "rocblas_dgemm");
-  DM_HIP(launch_sym_part(s.Y, P, n, s.stream), "symmetrise");
+  DM_HIP(launch_sym_part(s.B, P, n, s.stream), "symmetrise");
   DM_HIP(hipStreamSynchronize(s.stream), "synchronize");
   return 0;
 }
@@ -298,11 +338,13 @@ int dm_solve(DmSolver& s, int method, int n, const double* H, const double* S, d
   int rc = ensure(s, n, err);
   if (rc) return rc;
   DM_HIP(launch_sym_part(H, s.A, n, s.stream), "symmetrise");
-  DM_HIP(hipMemcpyAsync(s.B, S, (size_t)n * n * sizeof(double), hipMemcpyDeviceToDevice, s.stream),
-         "copy S");
-  if (method == kDmEigen) return solve_eigen(s, n, n_elec, kT, P, eps_or_null, mu, err);
+  if (method == kDmEigen) {
+    DM_HIP(hipMemcpyAsync(s.B, S, (size_t)n * n * sizeof(double), hipMemcpyDeviceToDevice, s.stream),
+           "copy S");
+    return solve_eigen(s, n, n_elec, kT, P, eps_or_null, mu, err);
+  }
   if (eps_or_null) return fail_msg(err, kStatusUnsupported, "purification computes no eigenvalues");
-  return solve_purify(s, n, n_elec, kT, P, mu, err);
+  return solve_purify(s, n, S, n_elec, kT, P, mu, err);
 }
 
 void dm_release(DmSolver& s) {

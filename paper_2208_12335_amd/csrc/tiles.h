@@ -13,6 +13,13 @@ __device__ __forceinline__ int xcd_item(int g, int n) {
   return (g & 7) * per + (g >> 3);
 }
 
+// The same order as a bijection of [0, n) for a grid of exactly n workgroups: XCD x takes the
+// contiguous run of n / 8 (+1 for the first n % 8 XCDs) items that starts at x (n / 8) + min(x, n % 8).
+__device__ __forceinline__ int xcd_item_exact(int g, int n) {
+  const int x = g & 7, q = n >> 3, r = n & 7;
+  return x * q + (x < r ? x : r) + (g >> 3);
+}
+
 
 // Work distribution.  Grid mode (queue == NULL): one workgroup per item, XCD-aware order.
 // Persistent mode: a fixed grid of workgroups drains eight per-XCD queues of contiguous

@@ -76,6 +76,50 @@ def test_purify_matches_oracle(gpu, which):
     assert np.array_equal(P, P.T)
 
 
+def test_purify_repeatable_full_empty_and_grouped(gpu):
+    """The purification products carry the trace from one step to the next without atomics, so
+    a second solve is bitwise the first.  No electrons give P = 0, every state filled gives
+    P = 2 S^-1, and a group of molecules (basis counts below and above one 64-wide tile) each
+    meets the oracle."""
+    inst = CASES["cluster24"]()
+    g = AimsGrid(inst, device=gpu.index)
+    H, S = _gpu_HS(g, inst, gpu)
+    N = float(np.sum(inst.atom_Z))
+    N -= N % 2
+    P1, _, _ = g.density_matrix(H, S, N, method="purify")
+    k1 = g.last_purify_products()
+    # the second call reuses the kept inverse factor of S: bitwise the same result
+    P2, _, _ = g.density_matrix(H, S, N, method="purify")
+    assert torch.equal(P1, P2) and g.last_purify_products() == k1
+    # S changed in place (same buffer): the factor is recomputed.  S -> 1.5 S scales the
+    # S-orthonormal eigenvectors by 1.5^-1/2, so P -> P / 1.5 (H' -> H' / 1.5, the same projector)
+    S15 = S.clone()
+    S.mul_(1.5)
+    P3, _, _ = g.density_matrix(H, S, N, method="purify")
+    S.copy_(S15)
+    assert torch.max(torch.abs(P3 * 1.5 - P1)).item() <= 1e-7 * torch.max(torch.abs(P1)).item()
+    P4, _, _ = g.density_matrix(H, S, N, method="purify")
+    assert torch.equal(P4, P1)
+    nb = inst.n_basis
+    P0, _, _ = g.density_matrix(H, S, 0.0, method="purify")
+    assert torch.count_nonzero(P0).item() == 0
+    Pf, _, _ = g.density_matrix(H, S, 2.0 * nb, method="purify")
+    Sn = S.cpu().numpy().reshape(nb, nb)
+    want = 2.0 * np.linalg.inv(0.5 * (Sn + Sn.T))
+    assert np.max(np.abs(Pf.cpu().numpy().reshape(nb, nb) - want)) <= 1e-7 * np.max(np.abs(want))
+    mols = synth.make_molecule_set(n_mol=3, seed=21, n_min=2, n_max=8)
+    gm = AimsGrid(mols, device=gpu.index)
+    v = torch.cat([torch.from_numpy(m.v) for m in mols]).to(gpu)
+    Hm, Sm = gm.integrate_h(v, want_S=True)
+    Ns = [float(np.sum(m.atom_Z)) - float(np.sum(m.atom_Z)) % 2 for m in mols]
+    Pm, _, _ = gm.density_matrix(Hm, Sm, Ns, method="purify")
+    for k, m in enumerate(mols):
+        ref, _ = _oracle(m, Ns[k], 0.0)
+        err = np.max(np.abs(gm.blocks(Pm)[k].cpu().numpy() - ref["P"])) / np.max(np.abs(ref["P"]))
+        print(f"[dm] purify molecule {k} (nb {gm.nb_sys[k]}): P {err:.1e}", flush=True)
+        assert err <= 1e-7
+
+
 def test_hydrogen_loop_closed_form(gpu):
     """H and S integrated on the GPU for the hydrogen atom in four s functions, the density
     matrix of one electron, then the density pass: N = 1 and E = -1/2 (the exact 1s state is in
