@@ -260,8 +260,13 @@ aims_status aims_xc_gga(aims_grid *g, int32_t functional, const double *n, const
  *   rho_{a,lm}(r_k) = sum over the points of node k of atom a of w n Y_lm(u) / W_k,
  *   V_lm(r) = 4 pi/(2l+1) [ r^-(l+1) int_0^r rho_lm s^(l+2) ds + r^l int_r^inf rho_lm s^(1-l) ds ]
  *   (natural cubic splines of rho_lm and V_lm in theta, 6-point Gauss-Legendre per interval,
- *   exact exterior field beyond the outermost node, (r/r_min)^l inside the innermost),
+ *   (r/r_min)^l inside the innermost node),
  *   v_H(p) = sum_a sum_lm V_{a,lm}(|p - R_a|) Y_lm(u),  E_H = 1/2 sum w n v_H.
+ * Support: atom a's piece lives on its own points.  With k_o its outermost node that holds a
+ * point, its edge node is k_e = max(k_o - 1, 0) (0 for an atom without points); rho_lm is
+ * splined over nodes k_e..n_radial-1 and is zero beyond r(k_e), where V_lm is exactly the
+ * exterior field 4 pi q_lm / ((2l+1) r^(l+1)) with q_lm = int_0^r(k_e) rho_lm s^(l+2) ds: a
+ * point beyond an atom's edge takes only that atom's moments (no spline evaluation).
  * aims_grid_set_hartree: per point (caller order of the system) the owner atom and the radial
  * node, plus n_radial, r_map and l_max (0..6, the same for every system of the handle).
  * aims_hartree: n: DEVICE [n_points] (caller order); v_out: DEVICE [n_points];

@@ -14,12 +14,19 @@ package docstring).  Derived from textbook electrostatics:
   The radial nodes are Becke's map r = r_m cot^2(theta/2) on uniform theta_k = (k+1) pi/(K+1),
   so rho_lm is interpolated by a natural cubic spline in theta and each interval's integrals
   are taken by 6-point Gauss-Legendre in theta (Jacobian |dr/dtheta| = r_m cot(t/2) csc^2(t/2)).
-  Inside the innermost node rho_lm is taken as rho_lm(r_min) (r/r_min)^l; beyond the outermost
-  node it is zero.  q_lm = int_0^inf rho_lm s^(l+2) ds is the multipole moment.
+  Inside the innermost node rho_lm is taken as rho_lm(r_min) (r/r_min)^l.
+* Compact support.  An atom's piece of the density lives on that atom's points only, and the
+  partition weights vanish exactly beyond a finite radius, so the outer radial nodes of an atom
+  can carry no point.  With k_o the outermost node that carries a point of atom a, the spline
+  runs over the nodes from the innermost one out to the edge node k_e = k_o + 1 outwards (the
+  first empty node, where rho_lm = 0; the outermost node itself when k_o is it), and rho_lm = 0
+  beyond it: atom a's support ends at R_a = r(k_e).  q_lm = int_0^{R_a} rho_lm s^(l+2) ds is
+  the multipole moment, and for r >= R_a the Poisson solution is exactly the exterior form
+  4 pi q_lm / ((2l+1) r^(l+1)).
 * Potential at any point.  v_H(p) = sum_a sum_lm V_{a,lm}(|p - R_a|) Y_lm(u), with V_lm from a
-  natural cubic spline in theta through its node values between the innermost and outermost
-  nodes, the exact exterior form 4 pi q_lm / ((2l+1) r^(l+1)) beyond the outermost node, and
-  V_lm(r_min) (r/r_min)^l inside the innermost one.
+  natural cubic spline in theta through its node values from the innermost node out to the edge
+  node, the exterior form beyond the edge node (no spline: an atom whose support a point lies
+  outside costs only its moments), and V_lm(r_min) (r/r_min)^l inside the innermost node.
 * Hartree energy E_H = 1/2 sum_p w_p n_p v_H(p).
 
 Pinned in tests/test_oracle_hartree.py by Gaussian charge distributions (closed forms
@@ -72,12 +79,28 @@ def multipoles(inst, n: np.ndarray, pt_shell: np.ndarray, n_radial: int, r_map: 
     return rho / W[None, :, None]
 
 
-def radial_potentials(rho: np.ndarray, n_radial: int, r_map: float, l_max: int) -> Dict:
+def edge_nodes(inst, pt_shell: np.ndarray, n_radial: int) -> np.ndarray:
+    """k_e per atom: one node outwards of the outermost node that carries a point of the atom
+    (node 0 is the outermost); 0 for an atom without points."""
+    own = np.asarray(inst.pt_atom)
+    ke = np.zeros(inst.n_atoms, dtype=np.int64)
+    for a in range(inst.n_atoms):
+        nodes = np.asarray(pt_shell)[own == a]
+        if nodes.size:
+            ke[a] = max(0, int(nodes.min()) - 1)
+    return ke
+
+
+def radial_potentials(rho: np.ndarray, n_radial: int, r_map: float, l_max: int,
+                      edge: np.ndarray = None) -> Dict:
     """{"V": [n_atoms, K, nlm] node values, "q": [n_atoms, nlm] moments} from the node
-    multipoles."""
+    multipoles; rho_lm of atom a is splined over nodes edge[a]..K-1 and zero beyond (edge
+    None: every node).  V at the nodes outside the edge node is the exterior form."""
     th, r, _ = radial_nodes(n_radial, r_map)
     h = th[1] - th[0]
     na, K, nlm = rho.shape
+    if edge is None:
+        edge = np.zeros(na, dtype=np.int64)
     ls = np.array([l for l, _ in lm_list(l_max)])
     V = np.zeros_like(rho)
     q = np.zeros((na, nlm))
@@ -87,18 +110,21 @@ def radial_potentials(rho: np.ndarray, n_radial: int, r_map: float, l_max: int) 
     sg = _r_of(tg, r_map)
     jg = _jac(tg, r_map)
     for a in range(na):
+        e = int(edge[a])
         for c in range(nlm):
             l = int(ls[c])
-            S = scipy.interpolate.CubicSpline(th, rho[a, :, c], bc_type="natural")
-            f = S(tg)
-            A = np.sum(wg * f * sg ** (l + 2) * jg, axis=1)     # int over r in [r_k+1, r_k]
-            B = np.sum(wg * f * sg ** (1 - l) * jg, axis=1)
+            S = scipy.interpolate.CubicSpline(th[e:], rho[a, e:, c], bc_type="natural")
+            f = S(tg[e:])
+            A = np.sum(wg * f * sg[e:] ** (l + 2) * jg[e:], axis=1)     # int over r in [r_k+1, r_k]
+            B = np.sum(wg * f * sg[e:] ** (1 - l) * jg[e:], axis=1)
             tail = rho[a, -1, c] * r[-1] ** (l + 3) / (2 * l + 3)
             inner = tail + np.concatenate([np.cumsum(A[::-1])[::-1], [0.0]])   # int_0^{r_k}
-            outer = np.concatenate([[0.0], np.cumsum(B)])                      # int_{r_k}^inf
-            V[a, :, c] = 4 * math.pi / (2 * l + 1) * (r ** (-l - 1) * inner + r ** l * outer)
+            outer = np.concatenate([[0.0], np.cumsum(B)])                      # int_{r_k}^{R_a}
+            pref = 4 * math.pi / (2 * l + 1)
+            V[a, e:, c] = pref * (r[e:] ** (-l - 1) * inner + r[e:] ** l * outer)
             q[a, c] = inner[0]
-    return {"V": V, "q": q}
+            V[a, :e, c] = pref * q[a, c] / r[:e] ** (l + 1)
+    return {"V": V, "q": q, "edge": np.asarray(edge)}
 
 
 def potential_at(points: np.ndarray, atom_xyz: np.ndarray, pot: Dict, n_radial: int,
@@ -107,13 +133,15 @@ def potential_at(points: np.ndarray, atom_xyz: np.ndarray, pot: Dict, n_radial: 
     th, r, _ = radial_nodes(n_radial, r_map)
     ls = np.array([l for l, _ in lm_list(l_max)])
     V, q = pot["V"], pot["q"]
+    edge = pot.get("edge", np.zeros(atom_xyz.shape[0], dtype=np.int64))
     out = np.zeros(points.shape[0])
     for a in range(atom_xyz.shape[0]):
+        e = int(edge[a])
         d = points - atom_xyz[a]
         ra = np.linalg.norm(d, axis=1)
         u = d / np.maximum(ra, 1e-300)[:, None]
         Y = real_ylm(u, l_max)
-        far = ra >= r[0]
+        far = ra >= r[e]
         inner = ra < r[-1]
         mid = ~far & ~inner
         t = 2.0 * np.arctan(np.sqrt(r_map / np.maximum(ra, 1e-300)))
@@ -121,7 +149,7 @@ def potential_at(points: np.ndarray, atom_xyz: np.ndarray, pot: Dict, n_radial: 
             l = int(ls[c])
             val = np.zeros_like(ra)
             val[far] = 4 * math.pi / (2 * l + 1) * q[a, c] / ra[far] ** (l + 1)
-            S = scipy.interpolate.CubicSpline(th, V[a, :, c], bc_type="natural")
+            S = scipy.interpolate.CubicSpline(th[e:], V[a, e:, c], bc_type="natural")
             val[mid] = S(t[mid])
             val[inner] = V[a, -1, c] * (ra[inner] / r[-1]) ** l
             out += val * Y[:, c]
@@ -132,6 +160,6 @@ def hartree(inst, n: np.ndarray, pt_shell: np.ndarray, n_radial: int, r_map: flo
             l_max: int) -> Dict:
     """{"v": v_H at the instance's points, "E_H", "rho", "V", "q"}."""
     rho = multipoles(inst, n, pt_shell, n_radial, r_map, l_max)
-    pot = radial_potentials(rho, n_radial, r_map, l_max)
+    pot = radial_potentials(rho, n_radial, r_map, l_max, edge_nodes(inst, pt_shell, n_radial))
     v = potential_at(inst.pt_xyz, inst.atom_xyz, pot, n_radial, r_map, l_max)
     return {"v": v, "E_H": 0.5 * float(np.sum(inst.pt_w * n * v)), "rho": rho, **pot}

@@ -35,6 +35,8 @@ struct HartreeDev {
   const int32_t* shell_pts = nullptr;
   const HartreeSys* sys = nullptr;          // [n_sys]
   const int32_t* sys_natoms = nullptr;
+  const int32_t* edge = nullptr;            // [n_atoms]: edge node (splines over edge..K-1)
+  const double* r_edge = nullptr;           // [n_atoms]: its radius (exterior form from there on)
   const double* cp = nullptr;               // Thomas factors of the natural-spline system
   const double* den = nullptr;
   const double* gl = nullptr;               // [2 kGauss]: nodes on [-1, 1], then weights

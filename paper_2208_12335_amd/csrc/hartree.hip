@@ -7,8 +7,13 @@
 //                     for the two radial Poisson integrals,
 //                     V_lm at the nodes and its own natural spline, and the moment q_lm
 //   potential_kernel  one thread per point: v_H = sum_atoms sum_lm V_lm(r) Y_lm(u) (the V spline
-//                     as per-interval cubic coefficients, one 32-byte load per term), exterior
-//                     form beyond the outermost node, (r/r_min)^l inside the innermost
+//                     as per-interval cubic coefficients, one 32-byte load per term), the
+//                     exterior form 4 pi q_lm / ((2l+1) r^(l+1)) beyond the atom's support (no
+//                     spline, no table), (r/r_min)^l inside the innermost node
+// An atom's density piece lives on its own points, which end at a finite radius (the partition
+// weights vanish beyond it): rho_lm is splined from the innermost node out to the atom's edge
+// node (one node outwards of its outermost occupied node) and is zero beyond, so beyond the edge
+// radius V_lm is exactly the exterior form.
 // Real orthonormal Y_lm without the Condon-Shortley phase, from the associated-Legendre
 // recurrence in z and the powers (x + i y)^m, generated m-outer / l-inner and consumed as they
 // are produced.
@@ -130,8 +135,8 @@ __device__ __forceinline__ void natural_spline(const double* y, double* M, size_
 template <int L>
 __global__ void __launch_bounds__(256)
 radial_kernel(int n_atoms, const int32_t* __restrict__ atom_sys, const HartreeSys* __restrict__ hs,
-              const double* __restrict__ cp, const double* __restrict__ den,
-              const double* __restrict__ gl,
+              const int32_t* __restrict__ edge, const double* __restrict__ cp,
+              const double* __restrict__ den, const double* __restrict__ gl,
               const double* __restrict__ rho, double* __restrict__ Mr, double* __restrict__ V,
               double* __restrict__ MV, double* __restrict__ q, double4* __restrict__ Vc) {
   constexpr int NLM = (L + 1) * (L + 1);
@@ -141,21 +146,24 @@ radial_kernel(int n_atoms, const int32_t* __restrict__ atom_sys, const HartreeSy
   int l = 0;
   while ((l + 1) * (l + 1) <= c) ++l;
   const HartreeSys S = hs[atom_sys[a]];
-  const int K = S.K;
+  const int K = S.K, e = edge[a];            // nodes e..K-1 carry the spline (e <= K - 2)
   const double h = kPi / (double)(K + 1), rm = S.r_map;
   // node arrays of this atom: element (k, lm) at (a K_max + k) NLM + lm
   const double* y = rho + (size_t)a * S.K_max * NLM + c;
   double* My = Mr + (size_t)a * S.K_max * NLM + c;
   double* Vy = V + (size_t)a * S.K_max * NLM + c;
   double* MVy = MV + (size_t)a * S.K_max * NLM + c;
-  natural_spline(y, My, NLM, K, h, cp + S.fac_off, den + S.fac_off);
+  // the Thomas factors of row i do not depend on the system size, so the spline over the
+  // K - e nodes from e on uses the same cp / den
+  natural_spline(y + (size_t)e * NLM, My + (size_t)e * NLM, NLM, K - e, h, cp + S.fac_off,
+                 den + S.fac_off);
   // Poisson integrals per interval [theta_k, theta_k+1] (r from r_k+1 up to r_k): inner
   // (s^(l+2)) accumulated from the centre outwards, outer (s^(1-l)) from infinity inwards
   const double rmin = rm / (tan(0.5 * h * K) * tan(0.5 * h * K));
   double inner = y[(size_t)(K - 1) * NLM] * pow(rmin, l + 3) / (double)(2 * l + 3);
   // pass 1: inner integral at each node, stored in Vy temporarily
   Vy[(size_t)(K - 1) * NLM] = inner;
-  for (int k = K - 2; k >= 0; --k) {
+  for (int k = K - 2; k >= e; --k) {
     double A = 0.0;
     for (int g = 0; g < kGauss; ++g) {
       const double b = 0.5 + 0.5 * gl[g];
@@ -168,11 +176,17 @@ radial_kernel(int n_atoms, const int32_t* __restrict__ atom_sys, const HartreeSy
     Vy[(size_t)k * NLM] = inner;
   }
   q[(size_t)a * NLM + c] = inner;
-  // pass 2: outer integral from infinity inwards and V at the nodes
+  // pass 2: outer integral from the edge inwards and V at the nodes; outside the edge node V is
+  // the exterior form
   double outer = 0.0;
   const double pref = 4.0 * kPi / (double)(2 * l + 1);
-  for (int k = 0; k < K; ++k) {
-    if (k > 0) {
+  for (int k = 0; k < e; ++k) {
+    const double tk = h * (double)(k + 1);
+    const double ctk = 1.0 / tan(0.5 * tk);
+    Vy[(size_t)k * NLM] = pref * inner * pow(rm * ctk * ctk, -(l + 1));
+  }
+  for (int k = e; k < K; ++k) {
+    if (k > e) {
       double B = 0.0;
       for (int g = 0; g < kGauss; ++g) {
         const double b = 0.5 + 0.5 * gl[g];
@@ -188,12 +202,13 @@ radial_kernel(int n_atoms, const int32_t* __restrict__ atom_sys, const HartreeSy
     const double rk = rm * ctk * ctk;
     Vy[(size_t)k * NLM] = pref * (Vy[(size_t)k * NLM] * pow(rk, -(l + 1)) + outer * pow(rk, l));
   }
-  natural_spline(Vy, MVy, NLM, K, h, cp + S.fac_off, den + S.fac_off);
+  natural_spline(Vy + (size_t)e * NLM, MVy + (size_t)e * NLM, NLM, K - e, h, cp + S.fac_off,
+                 den + S.fac_off);
   // the same spline per interval as c0 + c1 b + c2 b^2 + c3 b^3 in the local b in [0, 1]:
   // a y_k + b y_k+1 + ((a^3 - a) M_k + (b^3 - b) M_k+1) h^2/6 with a = 1 - b, expanded
   double4* C = Vc + (size_t)a * S.K_max * NLM + c;
   const double h26 = h * h / 6.0;
-  for (int k = 0; k + 1 < K; ++k) {
+  for (int k = e; k + 1 < K; ++k) {
     const double y0 = Vy[(size_t)k * NLM], y1 = Vy[(size_t)(k + 1) * NLM];
     const double m0 = MVy[(size_t)k * NLM], m1 = MVy[(size_t)(k + 1) * NLM];
     C[(size_t)k * NLM] = double4{y0, y1 - y0 - h26 * (2.0 * m0 + m1), 3.0 * h26 * m0, h26 * (m1 - m0)};
@@ -205,7 +220,8 @@ __global__ void __launch_bounds__(256)
 potential_kernel(const double4* __restrict__ pts, const int32_t* __restrict__ perm,
                  const int64_t* __restrict__ sys_pt_range, const SystemDesc* __restrict__ systems,
                  const int32_t* __restrict__ sys_natoms, const double* __restrict__ atom_xyz,
-                 const HartreeSys* __restrict__ hs, const double* __restrict__ V,
+                 const HartreeSys* __restrict__ hs, const int32_t* __restrict__ edge,
+                 const double* __restrict__ r_edge, const double* __restrict__ V,
                  const double4* __restrict__ Vc, const double* __restrict__ q,
                  const double* __restrict__ n_in, double* __restrict__ v_out,
                  double* __restrict__ part) {
@@ -217,7 +233,6 @@ potential_kernel(const double4* __restrict__ pts, const int32_t* __restrict__ pe
   const HartreeSys S = hs[s];
   const int K = S.K;
   const double h = kPi / (double)(K + 1), rm = S.r_map;
-  const double ct1 = 1.0 / tan(0.5 * h), rmax = rm * ct1 * ct1;
   const double ctK = 1.0 / tan(0.5 * h * K), rmin = rm * ctK * ctK;
   double se = 0.0;
   for (int64_t i = p0 + blockIdx.x * 256 + threadIdx.x; i < p1; i += (int64_t)nblk * 256) {
@@ -229,19 +244,28 @@ potential_kernel(const double4* __restrict__ pts, const int32_t* __restrict__ pe
       const double r = sqrt(dx * dx + dy * dy + dz * dz);
       const double ir = r > 0.0 ? 1.0 / r : 0.0;
       const double* Va = V + (size_t)a * S.K_max * NLM;
-      if (r >= rmax) {                      // exterior: 4 pi q / ((2l+1) r^(l+1))
+      double pw[L + 1];                     // running powers, indexed by the unrolled l
+      if (r >= r_edge[a]) {                 // beyond the support: 4 pi q / ((2l+1) r^(l+1))
         const double* qa = q + (size_t)a * NLM;
+        pw[0] = ir;
+#pragma unroll
+        for (int l = 1; l <= L; ++l) pw[l] = pw[l - 1] * ir;
         for_each_ylm<L>(dx * ir, dy * ir, dz * ir, [&](int l, int m, double Y) {
-          v += 4.0 * kPi / (double)(2 * l + 1) * qa[l * l + l + m] * pow(ir, l + 1) * Y;
+          v += (4.0 * kPi / (double)(2 * l + 1)) * qa[l * l + l + m] * pw[l] * Y;
         });
       } else if (r < rmin) {                // inside the innermost node
+        const double x = r / rmin;
+        pw[0] = 1.0;
+#pragma unroll
+        for (int l = 1; l <= L; ++l) pw[l] = pw[l - 1] * x;
         for_each_ylm<L>(dx * ir, dy * ir, r > 0.0 ? dz * ir : 1.0, [&](int l, int m, double Y) {
-          v += Va[(size_t)(K - 1) * NLM + l * l + l + m] * pow(r / rmin, l) * Y;
+          v += Va[(size_t)(K - 1) * NLM + l * l + l + m] * pw[l] * Y;
         });
       } else {
         const double t = 2.0 * atan(sqrt(rm / r));
+        const int e = edge[a];
         int k = (int)floor(t / h) - 1;      // interval [theta_k, theta_k+1], theta_k = (k+1) h
-        k = k < 0 ? 0 : (k > K - 2 ? K - 2 : k);
+        k = k < e ? e : (k > K - 2 ? K - 2 : k);
         const double b = (t - h * (double)(k + 1)) / h;
         const double4* Ck = Vc + ((size_t)a * S.K_max + k) * NLM;
         for_each_ylm<L>(dx * ir, dy * ir, dz * ir, [&](int l, int m, double Y) {
@@ -287,13 +311,13 @@ hipError_t launch_all(const DeviceView& dv, const HartreeDev& hd, const double* 
   }
   const int nt = hd.n_atoms * NLM;
   hipLaunchKernelGGL(radial_kernel<L>, dim3((nt + 255) / 256), dim3(256), 0, st, hd.n_atoms,
-                     dv.atom_sys, hd.sys, hd.cp, hd.den, hd.gl, hd.rho, hd.Mr, hd.V, hd.MV, hd.q,
-                     hd.Vc);
+                     dv.atom_sys, hd.sys, hd.edge, hd.cp, hd.den, hd.gl, hd.rho, hd.Mr, hd.V, hd.MV,
+                     hd.q, hd.Vc);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(potential_kernel<L>, dim3(kHartreeBlocks, dv.n_sys), dim3(256), 0, st, dv.pts,
                      dv.perm, dv.sys_pt_range, dv.systems, hd.sys_natoms, dv.atom_xyz, hd.sys,
-                     hd.V, hd.Vc, hd.q, n, v_out, hd.part);
+                     hd.edge, hd.r_edge, hd.V, hd.Vc, hd.q, n, v_out, hd.part);
   e = hipGetLastError();
   if (e != hipSuccess || !E_or_null) return e;
   hipLaunchKernelGGL(energy_kernel, dim3(dv.n_sys), dim3(256), 0, st, hd.part, kHartreeBlocks,

@@ -1537,6 +1537,9 @@ void build_hartree(aims_grid* g) {
   std::vector<HartreeSys> hs(g->n_sys);
   std::vector<double> cp, den;
   std::vector<int32_t> natoms(g->n_sys);
+  // edge node per atom: one node outwards (towards node 0) of the outermost node with a point
+  std::vector<int32_t> edge(g->n_atoms, 0);
+  std::vector<double> r_edge(g->n_atoms, 0.0);
   for (int s = 0; s < g->n_sys; ++s) {
     const int K = g->h_K[s];
     const double rm = g->h_rmap[s];
@@ -1551,6 +1554,14 @@ void build_hartree(aims_grid* g) {
     den.insert(den.end(), d.begin(), d.end());
     const int a0 = (int)g->sys_atom_range[2 * s], a1 = (int)g->sys_atom_range[2 * s + 1];
     natoms[s] = a1 - a0;
+    for (int a = a0; a < a1; ++a) {
+      int ko = -1;
+      for (int k = 0; k < K && ko < 0; ++k)
+        if (count[(size_t)a * K_max + k] > 0) ko = k;
+      edge[a] = ko > 0 ? ko - 1 : 0;
+      const double te = (double)(edge[a] + 1) * M_PI / (double)(K + 1), xe = std::cos(te);
+      r_edge[a] = rm * (1.0 + xe) / (1.0 - xe);
+    }
     for (int a = a0; a < a1; ++a)
       for (int k = 0; k < K; ++k) {
         // Becke radial weight with r^2: W = pi/(K+1) sin t 2 r_m/(1 - cos t)^2 r^2
@@ -1569,6 +1580,8 @@ void build_hartree(aims_grid* g) {
   drop(hd.shell_pts);
   drop(hd.sys);
   drop(hd.sys_natoms);
+  drop(hd.edge);
+  drop(hd.r_edge);
   drop(hd.cp);
   drop(hd.den);
   drop(hd.gl);
@@ -1587,6 +1600,8 @@ void build_hartree(aims_grid* g) {
   hd.shell_pts = g->upload(pts_sorted);
   hd.sys = g->upload(hs);
   hd.sys_natoms = g->upload(natoms);
+  hd.edge = g->upload(edge);
+  hd.r_edge = g->upload(r_edge);
   hd.cp = g->upload(cp);
   hd.den = g->upload(den);
   hd.gl = g->upload(gauss_legendre(kGauss));

@@ -78,3 +78,34 @@ def test_hartree_gaussian_closed_form_and_grouped(gpu):
     with pytest.raises(AimsError) as e:
         h2.hartree(torch.zeros(m1.n_points, dtype=torch.float64, device=gpu))
     assert e.value.status == -1
+
+
+def test_hartree_exterior_beyond_support(gpu):
+    """Two atoms 9 bohr apart, the charge on the first atom's points: the second atom's far
+    points lie beyond the first atom's edge node and take the exterior form (Q / r at l_max 0);
+    every point against the oracle at l_max 0 and 6."""
+    def f(r):
+        e = np.exp(-r * r)
+        return e, -0.5 * (4 * r * r - 6) * e
+    A, B = np.array([0.0, 0.0, 0.0]), np.array([0.0, 0.0, 9.0])
+    inst = synth.custom_instance(np.array([A, B]), [0, 1], [[0], [0]], [f, f], n_log=200,
+                                 n_radial=75, angular="lobatto302")
+    own_a = np.asarray(inst.pt_atom) == 0
+    n = (2.0 / math.pi) ** 1.5 * np.exp(-2.0 * ((inst.pt_xyz - A) ** 2).sum(1)) * own_a
+    node, K, rm = synth.radial_shells(inst)
+    from oracle.hartree import edge_nodes, radial_nodes
+    R_a = radial_nodes(K, rm)[1][edge_nodes(inst, node, K)[0]]
+    ra = np.linalg.norm(inst.pt_xyz - A, axis=1)
+    far = ra >= R_a
+    assert far.sum() > 100
+    for l_max in (0, 6):
+        _, v, E = _run(inst, n, gpu, l_max)
+        ref = hartree(inst, n, node, K, rm, l_max)
+        err = np.max(np.abs(v - ref["v"])) / np.max(np.abs(ref["v"]))
+        print(f"[hartree] beyond the support, l_max={l_max}: {err:.1e} ({far.sum()} far points)",
+              flush=True)
+        assert err <= 1e-11
+        assert abs(E[0] - ref["E_H"]) <= 1e-11 * abs(ref["E_H"])
+        if l_max == 0:
+            Q = ref["q"][0, 0] * math.sqrt(4 * math.pi)
+            assert np.max(np.abs(v[far] * ra[far] - Q)) < 1e-12

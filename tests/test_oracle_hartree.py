@@ -88,3 +88,35 @@ def test_off_centre_charge_needs_higher_multipoles():
     # the dipole moment along z: q_10 = sqrt(3/(4 pi)) * 0.25
     h = hartree(inst, n, shell, K, rm, 1)
     assert abs(h["q"][0, 2] - math.sqrt(3 / (4 * math.pi)) * 0.25) < 1e-5      # spline order, as above
+
+
+def test_exterior_form_beyond_the_support():
+    """Two atoms 9 bohr apart, a Gaussian charge on the first atom's points.  Its points end
+    at a finite radius (the partition weights vanish beyond it), its edge node lies there, and
+    at the second atom's outer points, beyond that edge, the potential is the exterior form of
+    the first atom's moments: for a spherical charge Q/r, the erf potential of the Gaussian to
+    the quadrature accuracy of Q."""
+    from oracle.hartree import edge_nodes, radial_nodes
+    A = np.array([0.0, 0.0, 0.0])
+    B = np.array([0.0, 0.0, 9.0])
+    inst = _grid([A, B])
+    shell, K, rm = synth.radial_shells(inst)
+    ke = edge_nodes(inst, shell, K)
+    _, r, _ = radial_nodes(K, rm)
+    own_a = np.asarray(inst.pt_atom) == 0
+    ra = np.linalg.norm(inst.pt_xyz - A, axis=1)
+    R_a = r[ke[0]]
+    assert ke[0] > 0 and ra[own_a].max() < R_a             # the support ends inside the grid
+    far = ra >= R_a
+    assert far.sum() > 100                                  # points beyond it (atom B's far side)
+    alpha = 2.0
+    # the Gaussian on the first atom's points only (the second atom's share, ~1e-7 of the
+    # charge, is dropped), so the second atom's piece is exactly zero
+    n = _gauss(inst.pt_xyz, A, alpha, 1.0) * own_a
+    h = hartree(inst, n, shell, K, rm, 0)
+    ref = _gauss_potential(inst.pt_xyz, A, alpha, 1.0)
+    Q = h["q"][0, 0] * math.sqrt(4 * math.pi)
+    assert abs(Q - 1.0) < 1e-5
+    # beyond the support: exactly Q / r (the second atom carries no charge)
+    assert np.max(np.abs(h["v"][far] * ra[far] - Q)) < 1e-12
+    assert np.max(np.abs(h["v"][far] - ref[far])) < 1e-5 / R_a
