@@ -12,7 +12,8 @@ stdout.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--workload c2|c3|c4|c5]
 
-Workloads: c2 (default) the 64-atom random cluster, 75 x 302 grid, batches <= 256;
+Workloads: c2 (default) the 64-atom random cluster, 75 x 302 grid, batches <= 256 (its line
+also carries every form on c3 under "scale_c3", unless --no-c3 or --step-only);
 c3 the 512-atom water cluster; c4 256 independent molecules in one grouped handle (timed as a
 graph replay, as eager calls and as 256 per-molecule launch sets); c5 the 128-atom cluster,
 forward + backward (dE/dP, dE/dv, dE/dR) per step, F = 8 sum_b n_p n_b^2.
@@ -29,9 +30,12 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "int8x7": 5000.0} 
 MFMA_PER_FLOP_INT8 = {"density": 34, "hs": 28}   # int8 digit products per product
 SINGLE_SCRATCH_MB = 512     # scratch budget of each per-molecule baseline handle (c4)
 HERE = os.path.dirname(os.path.abspath(__file__))
-TRAFFIC_FILE = os.path.join(HERE, "profiles", "tiled_kernels_c2_fp64_hbm_traffic.md")
-KERNEL_SRC = os.path.join(HERE, "paper_2208_12335_amd", "csrc", "kernels.hip")
-HOST_SRC = os.path.join(HERE, "paper_2208_12335_amd", "csrc", "host.cpp")     # batch partitions
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "tiled_kernels_c2_all_forms_counters.md")
+KERNEL_SRCS = [os.path.join(HERE, "paper_2208_12335_amd", "csrc", f)
+               for f in ("kernels.hip", "int8.hip", "tiles.h")]
+# the tuning fields that shape each family's launches
+FAMILY_TUNING = {"density": ("density_pblocks", "density_bucket_pblocks", "persistent"),
+                 "hs": ("h_merge", "h_flops_per_atomic", "h_tile32_mask", "persistent")}
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "int8x7": "int8x7"}
 FAMILIES = ("phi_eval", "density", "hs", "backward", "finish", "operands")
 
@@ -119,20 +123,21 @@ def _kernels(g, steps):
 def _measured_traffic(workload, form, family, tuning, flop_per_step=None):
     """HBM bytes per launch of the dominant kernel from the committed profiler summary (two
     rocprofv3 --pmc passes, FETCH_SIZE and WRITE_SIZE, scaled by a plain copy kernel), used only
-    when that summary was taken on the same kernel and partitioning sources (kernels.hip and
-    host.cpp), workload (and batching: the same algorithmic flops per step), form and
-    tuning."""
+    when that summary was taken on the same kernel sources, workload (and batching: the same
+    algorithmic flops per step), form and tuning fields of that kernel family."""
     import hashlib
     try:
         text = open(TRAFFIC_FILE).read()
         recs = [json.loads(l) for l in text.splitlines() if l.startswith("{")]
-        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read() + open(HOST_SRC, "rb").read()).hexdigest()
+        sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SRCS)).hexdigest()
     except (OSError, ValueError):
         return None
+    keys = FAMILY_TUNING.get(family, ())
     for rec in recs:
         if (rec.get("sources_sha256") == sha and rec.get("workload") == workload and
                 rec.get("form") == form and rec.get("family") == family and
-                rec.get("tuning") == tuning and rec.get("flop_per_step") == flop_per_step):
+                rec.get("flop_per_step") == flop_per_step and tuning is not None and
+                all(rec.get("tuning", {}).get(k) == tuning.get(k) for k in keys)):
             return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
     return None
 
@@ -185,10 +190,94 @@ def _make(workload, torch):
         return synth.make_instance(workload, seed=0)
 
 
+def _time_forms(args, torch, g, P, v, F, forms, fixed, backward, steps, warmup, timer, n, sums,
+                H, gE, reps=2):
+    """Every precision form on one handle: autotuned (or fixed) tuning, then K timed steps."""
+    from paper_2208_12335_amd.autotune import autotune
+    res = {}
+    for prec in forms:
+        if prec in fixed:
+            g.set_tuning(prec=prec, **fixed[prec])
+        elif not args.no_autotune:
+            t0 = time.time()
+            r = autotune(g, P, v, prec=prec, reps=reps, cache="")   # measured here, never cached
+            _log(f"{prec}: autotuned {dict((k, r[k]) for k in ('h_merge', 'density_pblocks', 'persistent', 'h_flops_per_atomic', 'h_tile32_mask', 'density_bucket_pblocks') if k in r)}"
+                 f" ({time.time() - t0:.1f} s)")
+
+        if backward:
+            def step():
+                g.update_density(P, v, prec=prec, n_out=n, sums_out=sums)
+                g.backward(P, v, gE, prec=prec)
+        else:
+            def step():
+                g.update_density(P, v, prec=prec, n_out=n, sums_out=sums)
+                g.integrate_h(v, prec=prec, H_out=H)
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        g.profile(True)
+        ms, wall = timer.run(step, steps, 0)
+        kern = _kernels(g, steps)
+        g.profile(False)
+        s = sums.cpu().numpy()[0]
+        res[prec] = {"ms_per_step": ms, "wall_ms_per_step": wall, "gflops": F / (ms * 1e-3) / 1e9,
+                     "ms_per_step_median": timer.last["median"], "ms_per_step_min": timer.last["min"],
+                     "N": float(s[0]), "E": float(s[1] + s[2]), "kernels": kern,
+                     "tuning": g.get_tuning(prec)}
+        _log(f"{prec}: {ms:.3f} ms/step, {res[prec]['gflops']:.1f} GFLOP/s")
+    return res
+
+
+def bench_scale_c3(args, torch, forms):
+    """The 512-atom water cluster beside the headline workload: every form autotuned (one
+    repetition per candidate) and timed over a few steps; the same per-form record as the
+    headline's, without the measurements outside the step."""
+    import synth
+    from paper_2208_12335_amd import AimsGrid
+    dev = torch.device("cuda", 0)
+    t0 = time.time()
+    with synth.generator_device(dev):
+        inst = synth.make_instance("c3", seed=0)
+    t_inst = time.time() - t0
+    t0 = time.time()
+    g = AimsGrid(inst, device=0)
+    torch.cuda.synchronize()
+    setup_s = time.time() - t0
+    ws = g.work_stats()
+    F = ws["flops_per_step"]
+    _log(f"c3: instance {t_inst:.1f} s, setup {setup_s:.1f} s, {ws['n_batches']} batches, F = {F:.3e}")
+    P = torch.from_numpy(inst.P).to(dev).reshape(-1)
+    v = torch.from_numpy(inst.v).to(dev)
+    n = torch.empty(g.n_points, dtype=torch.float64, device=dev)
+    sums = torch.empty(1, 3, dtype=torch.float64, device=dev)
+    H = torch.empty(g.mat_elems, dtype=torch.float64, device=dev)
+    timer = Timer(torch, g.stream)
+    steps, warmup = 3, 1
+    res = _time_forms(args, torch, g, P, v, F, forms, {}, False, steps, warmup, timer, n, sums, H,
+                      None, reps=1)
+    head, fastest = _forms_summary(res)
+    out = {"config": {"workload": WORKLOADS["c3"], "n_points": inst.n_points,
+                      "n_basis": inst.n_basis, "n_batches": ws["n_batches"], "flop_per_step": F,
+                      "sum_np_nb2": ws["sum_np_nb2"], "setup_s": setup_s, "instance_s": t_inst},
+           "steps": steps, "warmup": warmup, "headline_form": head,
+           "value": res[head]["gflops"], "unit": "GFLOP/s", "ms_per_step": res[head]["ms_per_step"],
+           "forms": {p: {k: r[k] for k in ("ms_per_step", "ms_per_step_median", "ms_per_step_min",
+                                            "gflops", "abs_dE_Ha_vs_fp64", "meets_1e-6_Ha",
+                                            "rel_dN_vs_fp64", "tuning", "E", "N")}
+                        | {"roofline": _roofline(r["kernels"], p, steps, "c3", r["tuning"], F)}
+                     for p, r in res.items()},
+           "fastest_form": {"form": fastest, "ms_per_step": res[fastest]["ms_per_step"]},
+           "kernels": {p: r["kernels"] for p, r in res.items()}}
+    del g
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_single(args, torch, inst, backward=False):
     """c2 / c3 / c5: one handle, every precision form, optionally with the backward."""
     from paper_2208_12335_amd import AimsGrid
-    from paper_2208_12335_amd.autotune import autotune
 
     dev = torch.device("cuda", 0)
     t0 = time.time()
@@ -208,39 +297,8 @@ def bench_single(args, torch, inst, backward=False):
 
     forms = ["fp64"] + [f for f in args.forms.split(",") if f and f != "fp64"]
     fixed = json.loads(args.tuning) if args.tuning else {}
-    res = {}
-    for prec in forms:
-        if prec in fixed:
-            g.set_tuning(prec=prec, **fixed[prec])
-        elif not args.no_autotune:
-            t0 = time.time()
-            r = autotune(g, P, v, prec=prec, reps=2, cache="")   # measured here, never cached
-            _log(f"{prec}: autotuned {dict((k, r[k]) for k in ('h_merge', 'density_pblocks', 'persistent', 'h_flops_per_atomic', 'h_tile32_mask', 'density_bucket_pblocks') if k in r)}"
-                 f" ({time.time() - t0:.1f} s)")
-
-        if backward:
-            def step():
-                g.update_density(P, v, prec=prec, n_out=n, sums_out=sums)
-                g.backward(P, v, gE, prec=prec)
-        else:
-            def step():
-                g.update_density(P, v, prec=prec, n_out=n, sums_out=sums)
-                g.integrate_h(v, prec=prec, H_out=H)
-
-        for _ in range(args.warmup):
-            step()
-        torch.cuda.synchronize()
-        g.profile(True)
-        ms, wall = timer.run(step, args.steps, 0)
-        kern = _kernels(g, args.steps)
-        g.profile(False)
-        s = sums.cpu().numpy()[0]
-        res[prec] = {"ms_per_step": ms, "wall_ms_per_step": wall, "gflops": F / (ms * 1e-3) / 1e9,
-                     "ms_per_step_median": timer.last["median"], "ms_per_step_min": timer.last["min"],
-                     "N": float(s[0]), "E": float(s[1] + s[2]), "kernels": kern,
-                     "tuning": g.get_tuning(prec)}
-        _log(f"{prec}: {ms:.3f} ms/step, {res[prec]['gflops']:.1f} GFLOP/s")
-
+    res = _time_forms(args, torch, g, P, v, F, forms, fixed, backward, args.steps, args.warmup,
+                      timer, n, sums, H, gE)
     head, fastest = _forms_summary(res)
     hr = res[head]
     # outside the step: the overlap matrix (computed once per geometry)
@@ -381,6 +439,8 @@ def bench_single(args, torch, inst, backward=False):
         "outside_step": outside,
         "roofline": _roofline(hr["kernels"], head, args.steps, args.workload, hr["tuning"], F),
     }
+    if args.workload == "c2" and not args.step_only and not args.no_c3:
+        line["scale_c3"] = bench_scale_c3(args, torch, forms)
     if args.cpu_chunks > 0:
         _log("CPU baseline (oracle sample)...")
         cb = _cpu_baseline(inst, ws["flops_per_step"], args.cpu_chunks)
@@ -507,6 +567,9 @@ def main():
     ap.add_argument("--step-only", action="store_true",
                     help="time the step alone: skip the measurements outside it (density matrix, "
                          "exchange-correlation, Hartree, total forces), e.g. for profiler runs")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="skip the 512-atom water cluster that the default (c2) line carries "
+                         "beside the headline")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 launches): the reference "
                          "kernel that scales the HBM byte counters of a profiler run")
