@@ -109,3 +109,27 @@ def test_hartree_exterior_beyond_support(gpu):
         if l_max == 0:
             Q = ref["q"][0, 0] * math.sqrt(4 * math.pi)
             assert np.max(np.abs(v[far] * ra[far] - Q)) < 1e-12
+
+
+def test_hartree_full_size_sampled(gpu):
+    """The 64-atom cluster at its full size (1.1M points, l_max = 6, the benchmark's Hartree
+    step): v_H at 400 sampled points and E_H against the oracle (node multipoles and radial
+    solve over every point, the potential at the sampled ones)."""
+    from oracle.hartree import edge_nodes, multipoles, potential_at, radial_potentials
+    inst = synth.make_instance("c2", seed=0)
+    g = AimsGrid(inst, device=gpu.index)
+    node, K, rm = synth.radial_shells(inst)
+    g.set_hartree_grid([(node, K, rm)], l_max=6)
+    P = torch.from_numpy(inst.P).to(gpu).reshape(-1)
+    n, _ = g.update_density(P, torch.from_numpy(inst.v).to(gpu))
+    v, E = g.hartree(n)
+    nn, v = n.cpu().numpy(), v.cpu().numpy()
+    rho = multipoles(inst, nn, node, K, rm, 6)
+    pot = radial_potentials(rho, K, rm, 6, edge_nodes(inst, node, K))
+    idx = np.random.default_rng(7).choice(inst.n_points, 400, replace=False)
+    ref = potential_at(inst.pt_xyz[idx], inst.atom_xyz, pot, K, rm, 6)
+    err = np.max(np.abs(v[idx] - ref)) / np.max(np.abs(ref))
+    E_ref = 0.5 * float(np.sum(inst.pt_w * nn * v))      # E_H of the GPU potential, summed on the host
+    print(f"[hartree] c2 full size: sampled v_H {err:.1e}, E_H {E.cpu().numpy()[0]:.10f}", flush=True)
+    assert err <= 1e-11
+    assert abs(E.cpu().numpy()[0] - E_ref) <= 1e-12 * abs(E_ref)
