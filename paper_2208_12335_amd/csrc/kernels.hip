@@ -868,6 +868,12 @@ density_kernel_bf16(const TileItem* __restrict__ items, int n_items, const Batch
 }
 
 
+// 16-byte segment of row `row` that holds k segment `seg` in the swizzled 64-byte LDS rows of
+// the BF16 H kernel: rows are unpadded and the segment index is XORed with bits 1-2 of the
+// row, so that the staging writes (four threads per row) and the fragment reads (16 rows per
+// 16 lanes) fall on distinct 16-byte bank groups for 8- and 16-lane phases alike.
+__device__ __forceinline__ int bf_seg(int row, int seg) { return seg ^ (((row >> 1) ^ (row >> 2)) & 3); }
+
 // H/S: C[i][j] = sum_p slab1[i][p] slab2[j][p] from function-major bf16 slabs.
 __device__ __forceinline__ void
 hs_tile_bf16(int item, const TileItem* __restrict__ items, int n_items, const BatchDesc* __restrict__ batches,
@@ -881,8 +887,8 @@ hs_tile_bf16(int item, const TileItem* __restrict__ items, int n_items, const Ba
   const int i0 = it.ti * kTile, jb = it.tj * kTile;
   const int* cols = batch_cols + d.col_off;
 
-  __shared__ __attribute__((aligned(16))) bf16_t Ah[2][kTile * kLdB], Al[2][kTile * kLdB];
-  __shared__ __attribute__((aligned(16))) bf16_t Bh[2][kTile * kLdB], Bl[2][kTile * kLdB];
+  __shared__ __attribute__((aligned(16))) bf16_t Ah[2][kTile * kKB], Al[2][kTile * kKB];
+  __shared__ __attribute__((aligned(16))) bf16_t Bh[2][kTile * kKB], Bl[2][kTile * kKB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
   const int mrows = nb - (i0 + wm * 32), ncols = nb - (jb + wn * 32);
@@ -905,19 +911,21 @@ hs_tile_bf16(int item, const TileItem* __restrict__ items, int n_items, const Ba
   };
   auto stash = [&](int buf) {
     const bf16x8_t z = {};
-    *reinterpret_cast<bf16x8_t*>(&Ah[buf][r * kLdB + 8 * sg]) = a_ok ? ah : z;
-    *reinterpret_cast<bf16x8_t*>(&Al[buf][r * kLdB + 8 * sg]) = a_ok ? al : z;
-    *reinterpret_cast<bf16x8_t*>(&Bh[buf][r * kLdB + 8 * sg]) = b_ok ? bh : z;
-    *reinterpret_cast<bf16x8_t*>(&Bl[buf][r * kLdB + 8 * sg]) = b_ok ? bl : z;
+    const int o = r * kKB + 8 * bf_seg(r, sg);
+    *reinterpret_cast<bf16x8_t*>(&Ah[buf][o]) = a_ok ? ah : z;
+    *reinterpret_cast<bf16x8_t*>(&Al[buf][o]) = a_ok ? al : z;
+    *reinterpret_cast<bf16x8_t*>(&Bh[buf][o]) = b_ok ? bh : z;
+    *reinterpret_cast<bf16x8_t*>(&Bl[buf][o]) = b_ok ? bl : z;
   };
   const bool full = mrows >= 32 && ncols >= 32;
   auto multiply = [&](int buf) {
-    const int kq = 8 * (lane >> 4);
+    const int kseg = lane >> 4;
     bf16x8_t a_h[2], a_l[2], b_h[2], b_l[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      const int oa = (wm * 32 + i * 16 + (lane & 15)) * kLdB + kq;
-      const int ob = (wn * 32 + i * 16 + (lane & 15)) * kLdB + kq;
+      const int ra = wm * 32 + i * 16 + (lane & 15), rb = wn * 32 + i * 16 + (lane & 15);
+      const int oa = ra * kKB + 8 * bf_seg(ra, kseg);
+      const int ob = rb * kKB + 8 * bf_seg(rb, kseg);
       a_h[i] = *reinterpret_cast<const bf16x8_t*>(&Ah[buf][oa]);
       a_l[i] = *reinterpret_cast<const bf16x8_t*>(&Al[buf][oa]);
       b_h[i] = *reinterpret_cast<const bf16x8_t*>(&Bh[buf][ob]);
