@@ -13,7 +13,8 @@ stdout.
     python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--workload c2|c3|c4|c5]
 
 Workloads: c2 (default) the 64-atom random cluster, 75 x 302 grid, batches <= 256 (its line
-also carries every form on c3 under "scale_c3", unless --no-c3 or --step-only);
+also carries c3, c4 and c5 under "scale_c3", "grouped_c4" and "backward_c5", unless --extras ''
+or --step-only);
 c3 the 512-atom water cluster; c4 256 independent molecules in one grouped handle (timed as a
 graph replay, as eager calls and as 256 per-molecule launch sets); c5 the 128-atom cluster,
 forward + backward (dE/dP, dE/dv, dE/dR) per step, F = 8 sum_b n_p n_b^2.
@@ -275,7 +276,41 @@ def bench_scale_c3(args, torch, forms):
     return out
 
 
-def bench_single(args, torch, inst, backward=False):
+def bench_extra_c4(args, torch):
+    """The grouped workload beside the headline: the c4 record (3 timed steps)."""
+    import copy
+    a = copy.copy(args)
+    a.steps, a.warmup, a.workload = 3, 1, "c4"
+    t0 = time.time()
+    mols = _make("c4", torch)
+    _log(f"c4: instance {time.time() - t0:.1f} s")
+    rec = bench_grouped(a, torch, mols)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    for k in ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data"):
+        rec.pop(k, None)
+    return rec
+
+
+def bench_extra_c5(args, torch, forms):
+    """The backward workload beside the headline: every form, density + backward per step
+    (3 timed steps, autotuned with one repetition), without the total-force measurements."""
+    import copy
+    a = copy.copy(args)
+    a.steps, a.warmup, a.workload, a.step_only, a.cpu_chunks, a.extras, a.tuning = 3, 1, "c5", True, 0, "", ""
+    a.forms = ",".join(f for f in forms if f != "int8x7")     # the sliced form has no backward
+    t0 = time.time()
+    inst = _make("c5", torch)
+    _log(f"c5: instance {time.time() - t0:.1f} s")
+    rec = bench_single(a, torch, inst, backward=True, reps=1)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    keep = ("value", "unit", "ms_per_step", "headline_form", "config", "forms", "fastest_form",
+            "kernels", "roofline")
+    return {k: rec[k] for k in keep if k in rec} | {"steps": a.steps, "warmup": a.warmup}
+
+
+def bench_single(args, torch, inst, backward=False, reps=2):
     """c2 / c3 / c5: one handle, every precision form, optionally with the backward."""
     from paper_2208_12335_amd import AimsGrid
 
@@ -298,7 +333,7 @@ def bench_single(args, torch, inst, backward=False):
     forms = ["fp64"] + [f for f in args.forms.split(",") if f and f != "fp64"]
     fixed = json.loads(args.tuning) if args.tuning else {}
     res = _time_forms(args, torch, g, P, v, F, forms, fixed, backward, args.steps, args.warmup,
-                      timer, n, sums, H, gE)
+                      timer, n, sums, H, gE, reps=reps)
     head, fastest = _forms_summary(res)
     hr = res[head]
     # outside the step: the overlap matrix (computed once per geometry)
@@ -439,8 +474,13 @@ def bench_single(args, torch, inst, backward=False):
         "outside_step": outside,
         "roofline": _roofline(hr["kernels"], head, args.steps, args.workload, hr["tuning"], F),
     }
-    if args.workload == "c2" and not args.step_only and not args.no_c3:
+    extras = [] if args.workload != "c2" or args.step_only else [x for x in args.extras.split(",") if x]
+    if "c3" in extras:
         line["scale_c3"] = bench_scale_c3(args, torch, forms)
+    if "c4" in extras:
+        line["grouped_c4"] = bench_extra_c4(args, torch)
+    if "c5" in extras:
+        line["backward_c5"] = bench_extra_c5(args, torch, forms)
     if args.cpu_chunks > 0:
         _log("CPU baseline (oracle sample)...")
         cb = _cpu_baseline(inst, ws["flops_per_step"], args.cpu_chunks)
@@ -567,9 +607,10 @@ def main():
     ap.add_argument("--step-only", action="store_true",
                     help="time the step alone: skip the measurements outside it (density matrix, "
                          "exchange-correlation, Hartree, total forces), e.g. for profiler runs")
-    ap.add_argument("--no-c3", action="store_true",
-                    help="skip the 512-atom water cluster that the default (c2) line carries "
-                         "beside the headline")
+    ap.add_argument("--extras", default="c3,c4,c5",
+                    help="the other workloads the default (c2) line carries beside the headline: "
+                         "c3 every form, c4 the grouped step (graph, eager, per molecule), c5 "
+                         "every form with the backward; '' skips them")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 launches): the reference "
                          "kernel that scales the HBM byte counters of a profiler run")

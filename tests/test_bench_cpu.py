@@ -43,12 +43,11 @@ def test_bf16x3_states_the_mfma_fraction():
 
 
 def test_traffic_record_matching(tmp_path, monkeypatch):
-    src = tmp_path / "k.hip"
-    src.write_text("kernel source")
-    host = tmp_path / "h.cpp"
-    host.write_text("partition source")
+    srcs = [tmp_path / "k.hip", tmp_path / "i.hip", tmp_path / "t.h"]
+    for i, f in enumerate(srcs):
+        f.write_text(f"kernel source {i}")
     import hashlib
-    sha = hashlib.sha256(src.read_bytes() + host.read_bytes()).hexdigest()
+    sha = hashlib.sha256(b"".join(f.read_bytes() for f in srcs)).hexdigest()
     rec = {"workload": "c2", "form": "fp64", "family": "hs", "tuning": TUNING,
            "fetch_bytes_per_launch": 5, "write_bytes_per_launch": 2, "sources_sha256": sha,
            "flop_per_step": 7.3e11}
@@ -56,8 +55,7 @@ def test_traffic_record_matching(tmp_path, monkeypatch):
     f = tmp_path / "t.md"
     f.write_text("# summary\n\n" + json.dumps(other) + "\n" + json.dumps(rec) + "\n")
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
-    monkeypatch.setattr(bench, "KERNEL_SRC", str(src))
-    monkeypatch.setattr(bench, "HOST_SRC", str(host))
+    monkeypatch.setattr(bench, "KERNEL_SRCS", [str(x) for x in srcs])
     assert bench._measured_traffic("c2", "fp64", "hs", TUNING, 7.3e11) == 7
     assert bench._measured_traffic("c2", "fp64", "density", TUNING, 7.3e11) == 102
     # any mismatch: no traffic
@@ -65,11 +63,15 @@ def test_traffic_record_matching(tmp_path, monkeypatch):
     assert bench._measured_traffic("c3", "fp64", "hs", TUNING, 7.3e11) is None      # workload
     assert bench._measured_traffic("c2", "fp32", "hs", TUNING, 7.3e11) is None      # form
     assert bench._measured_traffic("c2", "fp64", "hs", dict(TUNING, h_merge=2), 7.3e11) is None
-    host.write_text("changed partition source")
-    assert bench._measured_traffic("c2", "fp64", "hs", TUNING, 7.3e11) is None      # partitions
-    host.write_text("partition source")
-    src.write_text("changed kernel source")
-    assert bench._measured_traffic("c2", "fp64", "hs", TUNING, 7.3e11) is None      # kernels
+    # a tuning field of the other family does not matter, one of its own does
+    assert bench._measured_traffic("c2", "fp64", "hs", dict(TUNING, density_pblocks=5), 7.3e11) == 7
+    assert bench._measured_traffic("c2", "fp64", "density", dict(TUNING, density_pblocks=5), 7.3e11) is None
+    for x in srcs:                                   # any of the kernel sources changed
+        old = x.read_text()
+        x.write_text("changed")
+        assert bench._measured_traffic("c2", "fp64", "hs", TUNING, 7.3e11) is None
+        x.write_text(old)
+    assert bench._measured_traffic("c2", "fp64", "hs", TUNING, 7.3e11) == 7
 
 
 def test_more_than_one_gpu_is_refused():
