@@ -25,7 +25,9 @@
 //   slice_p_kernel          P -> digit words P8 and one exponent per row (once per call)
 //   phi_eval_i8_kernel      basis values of one batch -> digit slabs; the scales come from a
 //                           first sweep over the batch (radial bounds |R| Ymax_l), per point for
-//                           the density pass and per function for the H / S pass
+//                           the density pass and per function for the H / S pass.  The density
+//                           pass's second slab (t phi, read only by its FP64 epilogue, never by
+//                           the matrix cores) holds plain FP64 values
 //   density_i8_kernel       X^T = P_b Phi^T (64 functions x 64 points per tile), epilogue
 //                           n_p += sum_j X_jp phi_jp and the E_T partial, in FP64
 //   hs_i8_kernel            C = Phi^T (second operand) over the batch's points (64 x 64 tiles),
@@ -355,7 +357,9 @@ phi_eval_i8_kernel(const BatchDesc* __restrict__ batches, int b0, const double4*
         int x1 = pe1, x2 = pe2;
         if (MODE != kModeDensity) exps(f + m, x1, x2);
         o1[(size_t)(f + m) * ldp + p] = to_digits(MODE == kModeDensity ? ldexp(phi, -fe) : phi, x1);
-        o2[(size_t)(f + m) * ldp + p] = to_digits(second, x2);
+        // the density pass reads t phi only in its FP64 epilogue: kept as FP64 bits
+        o2[(size_t)(f + m) * ldp + p] =
+            MODE == kModeDensity ? (uint64_t)__double_as_longlong(second) : to_digits(second, x2);
       }
       f += 2 * l + 1;
     }
@@ -465,7 +469,7 @@ density_i8_tile(int item, const TileItem* __restrict__ items, const BatchDesc* _
   const int p = p0 + 32 * wn + (lane & 31);
   double sn = 0.0, se = 0.0;
   if (live && p < d.n_p) {
-    const int e1 = ex1[d.pt_off + p], e2 = ex2[d.pt_off + p];
+    const int e1 = ex1[d.pt_off + p];
     uint64_t f1[16], f2[16];             // the epilogue's basis digits, loaded together
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -479,9 +483,9 @@ density_i8_tile(int item, const TileItem* __restrict__ items, const BatchDesc* _
       const int jl = 32 * wm + acc_row32(lane, r);
       if (j0 + jl < nb) {
         const double x = level_sum<kLevelsD>(acc, r);
-        // X phi = 2^(eP + e1) x * 2^(e1 + f) digits(phi);  X t phi = 2^(eP + e1) x * 2^e2 digits
+        // X phi = 2^(eP + e1) x * 2^(e1 + f) digits(phi);  X t phi = 2^(eP + e1) x * t phi (FP64)
         sn += ldexp(x * from_digits(f1[r], 0), rowc[64 + jl] + 2 * e1);
-        se += ldexp(x * from_digits(f2[r], 0), rowc[jl] + e1 + e2);
+        se += ldexp(x * __longlong_as_double((long long)f2[r]), rowc[jl] + e1);
       }
     }
     se *= pts[d.pt_off + p].w;
