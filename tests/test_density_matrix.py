@@ -190,3 +190,27 @@ def ctypes_args(H, S, P, N):
     return (ctypes.c_void_p(H.data_ptr()), ctypes.c_void_p(S.data_ptr()),
             ne.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0.0, ctypes.c_void_p(P.data_ptr()),
             ctypes.c_void_p(eps.data_ptr()), None)
+
+
+def test_purify_full_size_against_oracle(gpu):
+    """The 64-atom cluster at its full size (1,445 functions): the purification's product runs
+    its whole-tile plus split-K plan (256 whole 64 x 64 tiles and 20 tiles in K parts), stops
+    on the device, and meets the oracle's eigendecomposition of the same H and S."""
+    inst = synth.make_instance("c2", seed=0)
+    g = AimsGrid(inst, device=gpu.index)
+    H, S = _gpu_HS(g, inst, gpu)
+    N = float(np.sum(inst.atom_Z))
+    N -= N % 2
+    P, _, _ = g.density_matrix(H, S, N, method="purify")
+    nb = inst.n_basis
+    Hn = H.cpu().numpy().reshape(nb, nb)
+    Sn = S.cpu().numpy().reshape(nb, nb)
+    ref = dm_ref(Hn, Sn, N, 0.0)
+    P = P.cpu().numpy().reshape(nb, nb)
+    err = np.max(np.abs(P - ref["P"])) / np.max(np.abs(ref["P"]))
+    k = int(N // 2)
+    print(f"[dm] c2 purify: {g.last_purify_products()} products, gap {ref['eps'][k] - ref['eps'][k - 1]:.3f}, "
+          f"P {err:.1e}", flush=True)
+    assert err <= 1e-7
+    assert np.array_equal(P, P.T)
+    assert abs(np.sum(P * Sn) - N) <= 1e-8 * N
