@@ -289,9 +289,13 @@ aims_status aims_hartree(aims_grid *g, const double *n, double *v_out, double *E
  * (the lowest floor(N/2) states full, a remaining fraction in the next), Fermi-Dirac
  * f_k = 2 / (1 + exp((eps_k - mu) / kT)) for kT > 0 with mu fixed by the electron count.
  * method AIMS_DM_EIGEN: generalised eigensolver (rocSOLVER sygvd), eigenvalues available.
- * method AIMS_DM_PURIFY: Cholesky orthogonalisation and trace-correcting purification, GEMMs
- *   only; needs kT = 0, an even electron count and a gap at the Fermi level; no eigenvalues
- *   (eps_out must be NULL) and mu_out receives NaN.
+ * method AIMS_DM_PURIFY: Cholesky orthogonalisation and trace-correcting purification (X <- X^2
+ *   or 2 X - X^2 by the trace; stop three products after |tr X - ||X||_F^2| < 1e-8 N_e/2,
+ *   decided on the device), no eigenvectors; needs kT = 0, an even electron count and a gap at
+ *   the Fermi level; no eigenvalues (eps_out must be NULL) and mu_out receives NaN.  The
+ *   inverse Cholesky factor of S is kept by the handle and reused while a system's S is bitwise
+ *   the one it came from (a device comparison per call); any change of S, in place or not,
+ *   factorises it again.
  * H, S: DEVICE, the concatenated nb_s x nb_s blocks as aims_integrate_h writes them (H need not
  * be symmetric; S must be symmetric positive definite).  n_electrons: HOST [n_sys].  P_out:
  * DEVICE, same layout, symmetric.  eps_out_or_null: DEVICE [sum nb_s], ascending per system.
