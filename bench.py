@@ -258,6 +258,7 @@ def bench_scale_c3(args, torch, forms):
     res = _time_forms(args, torch, g, P, v, F, forms, {}, False, steps, warmup, timer, n, sums, H,
                       None, reps=1)
     head, fastest = _forms_summary(res)
+    dm = _density_matrix_at_scale(torch, g, inst, v, H, timer, res, n, sums)
     out = {"config": {"workload": WORKLOADS["c3"], "n_points": inst.n_points,
                       "n_basis": inst.n_basis, "n_batches": ws["n_batches"], "flop_per_step": F,
                       "sum_np_nb2": ws["sum_np_nb2"], "setup_s": setup_s, "instance_s": t_inst},
@@ -269,9 +270,73 @@ def bench_scale_c3(args, torch, forms):
                         | {"roofline": _roofline(r["kernels"], p, steps, "c3", r["tuning"], F)}
                      for p, r in res.items()},
            "fastest_form": {"form": fastest, "ms_per_step": res[fastest]["ms_per_step"]},
-           "kernels": {p: r["kernels"] for p, r in res.items()}}
+           "kernels": {p: r["kernels"] for p, r in res.items()},
+           "density_matrix_fp64": dm}
     del g
     torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
+
+
+def _density_matrix_at_scale(torch, g, inst, v, H, timer, res, n, sums):
+    """The step after H on a large system: the occupied-subspace density matrix by the
+    eigensolver and by purification (times and their agreement), and every form's density
+    pass on that occupied-orbital P next to two FP64 routes to its energy (the density pass,
+    and tr(P H) from the H pass)."""
+    dev = H.device
+    nb = inst.n_basis
+    S = torch.empty_like(H)
+    g.set_tuning(prec="fp64", **res["fp64"]["tuning"])
+    g.integrate_h(v, prec="fp64", H_out=H, S_out=S, want_S=True)
+    n_e = float(np.sum(inst.atom_Z))
+    n_e -= n_e % 2
+    P_eig = torch.empty_like(H)
+    P_pur = torch.empty_like(H)
+    out = {"n_electrons": n_e, "n_basis": nb}
+    ms, _ = timer.run(lambda: g.density_matrix(H, S, n_e, method="eigen", P_out=P_eig,
+                                               want_eps=False), 2, 1)
+    out["eigen"] = {"ms": ms}
+    try:
+        ms, _ = timer.run(lambda: g.density_matrix(H, S, n_e, method="purify", P_out=P_pur,
+                                                   want_eps=False), 3, 1)
+        k = g.last_purify_products()
+        S_alt = (S * (1.0 + 2.0 ** -40)).contiguous()
+        flip = [S_alt, S]
+
+        def solve_factor():
+            flip.reverse()
+            g.density_matrix(H, flip[0], n_e, method="purify", P_out=P_pur, want_eps=False)
+        ms_f, _ = timer.run(solve_factor, 2, 0)
+        g.density_matrix(H, S, n_e, method="purify", P_out=P_pur, want_eps=False)
+        out["purify"] = {"ms": ms, "ms_with_factorisation": ms_f, "products": k,
+                         "symmetric_product_tflops": k * float(nb) ** 3 / (ms * 1e-3) / 1e12,
+                         "max_abs_dP_vs_eigen_rel": float((P_pur - P_eig).abs().max() /
+                                                          P_eig.abs().max()),
+                         "tr_PS_minus_n_e": float((P_pur * S).sum()) - n_e,
+                         "speedup_vs_eigen": out["eigen"]["ms"] / ms}
+        _log(f"c3 density matrix: eigen {out['eigen']['ms']:.1f} ms, purify {ms:.1f} ms "
+             f"({k} products)")
+    except Exception as e:                      # e.g. no gap for the purification
+        out["purify"] = {"error": str(e)}
+    out["eigen"]["tr_PS_minus_n_e"] = float((P_eig * S).sum()) - n_e
+    out["max_abs_P"] = float(P_eig.abs().max())
+    del S, P_pur
+    occ = {}
+    for prec in res:
+        g.set_tuning(prec=prec, **res[prec]["tuning"])
+        g.update_density(P_eig, v, prec=prec, n_out=n, sums_out=sums)
+        s_ = sums.cpu().numpy()[0]
+        occ[prec] = {"E": float(s_[1] + s_[2]), "N": float(s_[0])}
+    e64 = occ["fp64"]["E"]
+    for prec, r in occ.items():
+        if prec != "fp64":
+            r["abs_dE_Ha_vs_fp64"] = abs(r["E"] - e64)
+            r["meets_1e-6_Ha"] = r["abs_dE_Ha_vs_fp64"] <= 1e-6
+    g.integrate_h(v, prec="fp64", H_out=H)
+    occ["fp64_trPH_minus_density_route_Ha"] = float((P_eig * H).sum()) - e64
+    out["forms_on_occupied_P"] = occ
+    _log(f"c3 forms on the occupied P: {json.dumps(occ)}")
+    del P_eig
     torch.cuda.empty_cache()
     return out
 
