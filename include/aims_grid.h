@@ -124,7 +124,9 @@ aims_status aims_grid_setup_many(const aims_system *sys, int32_t n_sys, int devi
 
 /* Density update: n_out[p] = sum_ij P_ij phi_i(p) phi_j(p) for every point (caller order) and
  * sums_out[3] = { N = sum w n, E_V = sum w v n, E_T = sum_p w_p sum_ij P_ij phi_i tphi_j }.
- * P: DEVICE, FP64, [nb][nb] row-major, symmetric (the caller's responsibility).  v_or_null:
+ * P: DEVICE, FP64, [nb][nb] row-major, symmetric (the caller's responsibility; with the
+ * environment variable AIMS_DEBUG=1 at setup, every call that reads P checks it on the device,
+ * max|P - P^T| <= 1e-12 max|P| and finite, and refuses it with AIMS_ERR_ARG).  v_or_null:
  * DEVICE [n_points] or NULL (then E_V = 0).  n_out: DEVICE [n_points].  sums_out: DEVICE [3].
  * atom_xyz: NULL (positions from setup) or a host or device [n_atoms][3] array within
  * screen_margin of the setup positions.  A host array is checked before any launch

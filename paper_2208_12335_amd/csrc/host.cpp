@@ -268,6 +268,7 @@ struct aims_grid {
   double* d_atom_xyz = nullptr;
   double* d_atom_xyz0 = nullptr;      // set-up positions (restored device to device)
   int* d_pos_flag = nullptr;          // 1 when the last device positions failed the screening check
+  unsigned long long* d_dbg = nullptr;  // AIMS_DEBUG: maxima of the symmetry check, 2 per system
   bool pos_async = false;             // this call took positions on the device (outputs checked)
   double* d_n_sorted = nullptr;
   double* d_part = nullptr;
@@ -989,6 +990,7 @@ aims_grid* build(const aims_system* sys, int n_sys, int device, void* stream) {
   g->d_atom_xyz = g->upload(g->atom_xyz0);
   g->d_atom_xyz0 = g->upload(g->atom_xyz0);
   g->d_pos_flag = g->upload(std::vector<int>(1, 0));
+  if (g->debug) g->d_dbg = (unsigned long long*)g->alloc(2 * g->systems.size() * sizeof(unsigned long long));
   dv.atom_xyz = g->d_atom_xyz;
   dv.atom_species = g->upload(atom_species);
   dv.atom_sys = g->upload(atom_sys);
@@ -1089,6 +1091,35 @@ void set_positions(aims_grid* g, const double* xyz) {
   hipchk(launch_positions_check(g->d_atom_xyz, g->d_atom_xyz0, g->n_atoms, g->margin, g->d_pos_flag,
                                 g->stream), "position check");
   g->moved = true;
+}
+
+// AIMS_DEBUG: a density matrix that is not symmetric is refused.  Every formula here takes
+// P = P^T: the backward's X = Phi P and Y = (T Phi) P, the forces and the density gradient are
+// the derivatives only for a symmetric P, and an asymmetric P's kinetic term depends on which
+// index a kernel contracts first.  Checked on the device per system (max |P - P^T| <= 1e-12
+// max |P|, every entry finite), with one synchronisation; skipped while the stream is being
+// captured.
+void debug_check_symmetric(aims_grid* g, const double* P, const char* name) {
+  if (!g->debug || !g->d_dbg) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(g->stream, &cs) != hipSuccess) (void)hipGetLastError();
+  if (cs != hipStreamCaptureStatusNone) return;
+  const size_t ns = g->systems.size();
+  for (size_t k = 0; k < ns; ++k)
+    hipchk(launch_asym_max(P + g->systems[k].mat_off, g->systems[k].nb, g->d_dbg + 2 * k, g->stream),
+           "AIMS_DEBUG symmetry check");
+  std::vector<unsigned long long> h(2 * ns);
+  hipchk(hipMemcpyAsync(h.data(), g->d_dbg, h.size() * sizeof(unsigned long long),
+                        hipMemcpyDeviceToHost, g->stream), "AIMS_DEBUG symmetry check");
+  hipchk(hipStreamSynchronize(g->stream), "AIMS_DEBUG symmetry check");
+  for (size_t k = 0; k < ns; ++k) {
+    double a, m;
+    std::memcpy(&a, &h[2 * k], sizeof(double));
+    std::memcpy(&m, &h[2 * k + 1], sizeof(double));
+    if (!(a <= 1e-12 * m))
+      fail(AIMS_ERR_ARG, "AIMS_DEBUG: %s of system %zu is not symmetric (max|P - P^T| = %.3e, max|P| = %.3e)",
+           name, k, a, m);
+  }
 }
 
 // Outputs of a call that took device positions: NaN if those failed the check.
@@ -1651,6 +1682,7 @@ aims_status aims_update_density(aims_grid* g, aims_precision prec, const double*
     require_device(P, "P", (size_t)g->mat_total * sizeof(double));
     require_device(n_out, "n_out", (size_t)g->n_points * sizeof(double));
     require_device(sums_out, "sums_out", 3 * (size_t)g->n_sys * sizeof(double));
+    debug_check_symmetric(g, P, "P");
     if (v_or_null) require_device(v_or_null, "v", (size_t)g->n_points * sizeof(double));
     set_positions(g, atom_xyz);
     density_call(g, prec, P, v_or_null, n_out, sums_out);
@@ -1667,6 +1699,7 @@ aims_status aims_update_density_noalloc(aims_grid* g, aims_precision prec, const
     require_device(n_out, "n_out", (size_t)g->n_points * sizeof(double));
     require_device(sums_out, "sums_out", 3 * (size_t)g->n_sys * sizeof(double));
     if (v_or_null) require_device(v_or_null, "v", (size_t)g->n_points * sizeof(double));
+    debug_check_symmetric(g, P, "P");
     if (!g->na_error.empty()) fail(AIMS_ERR_UNSUPPORTED, "%s", g->na_error.c_str());
     set_positions(g, nullptr);
     density_call(g, prec, P, v_or_null, n_out, sums_out, true);
@@ -1715,6 +1748,7 @@ aims_status aims_integrate_h_backward(aims_grid* g, aims_precision prec, const d
     require_device(gE, "gE", sizeof(double));
     if (dE_dP_or_null) require_device(dE_dP_or_null, "dE_dP", (size_t)g->mat_total * sizeof(double));
     if (dE_dv_or_null) require_device(dE_dv_or_null, "dE_dv", (size_t)g->n_points * sizeof(double));
+    debug_check_symmetric(g, P, "P");
     if (dE_dR_or_null) require_device(dE_dR_or_null, "dE_dR", 3 * (size_t)g->n_atoms * sizeof(double));
     set_positions(g, atom_xyz);
     hipStream_t st = g->stream;
@@ -1889,6 +1923,7 @@ aims_status aims_total_forces(aims_grid* g, aims_precision prec, const double* P
     require_device(P, "P", (size_t)g->mat_total * sizeof(double));
     require_device(gE, "gE", sizeof(double));
     require_device(dE_dR, "dE_dR", 3 * (size_t)g->n_atoms * sizeof(double));
+    debug_check_symmetric(g, P, "P");
     if (sums_out_or_null) require_device(sums_out_or_null, "sums_out", 3 * (size_t)g->n_sys * sizeof(double));
     set_positions(g, nullptr);
     if (g->moved) fail(AIMS_ERR_ARG, "total forces are taken at the setup positions");
@@ -2107,6 +2142,7 @@ aims_status aims_density_gradient(aims_grid* g, const double* P, double* n_out_o
   return guarded(__func__, g, [&] {
     require_device(P, "P", (size_t)g->mat_total * sizeof(double));
     require_device(grad_out, "grad_out", 3 * (size_t)g->n_points * sizeof(double));
+    debug_check_symmetric(g, P, "P");
     if (n_out_or_null) require_device(n_out_or_null, "n_out", (size_t)g->n_points * sizeof(double));
     set_positions(g, nullptr);
     if (g->moved) fail(AIMS_ERR_ARG, "the density gradient is taken at the setup positions");
@@ -2180,6 +2216,7 @@ aims_status aims_step_graph_create(aims_grid* g, aims_precision prec, const doub
     require_device(v, "v", (size_t)g->n_points * sizeof(double));
     require_device(n_out, "n_out", (size_t)g->n_points * sizeof(double));
     require_device(sums_out, "sums_out", 3 * (size_t)g->n_sys * sizeof(double));
+    debug_check_symmetric(g, P, "P");
     require_device(H, "H", (size_t)g->mat_total * sizeof(double));
     set_positions(g, nullptr);
     if (!g->stream) fail(AIMS_ERR_ARG, "step graphs need a non-default stream at setup");

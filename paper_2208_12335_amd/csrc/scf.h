@@ -34,6 +34,9 @@ hipError_t launch_purify_partials(const double* X, int ld, double* part, double*
                                   hipStream_t st);
 // *flag = 1 if the n doubles at a and b differ in any bit, else 0
 hipError_t launch_differ(const double* a, const double* b, size_t n, int* flag, hipStream_t st);
+// out[0] = bits of max |P_ij - P_ji|, out[1] = bits of max |P_ij| over the n x n row-major block P
+// (out[0] = bits of +inf if an entry is not finite); out is cleared first
+hipError_t launch_asym_max(const double* P, int n, unsigned long long* out, hipStream_t st);
 // Work split of one product: tiles [0, n_full) whole, the remaining tiles in ks K parts each
 // (ks >= 2, at most `cus` parts in all), summed by a second kernel
 struct PurifyPlan {

@@ -410,6 +410,31 @@ __global__ void __launch_bounds__(256) differ_kernel(const unsigned long long* _
   if (__any(d) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
 }
 
+// Largest |P_ij - P_ji| and |P_ij| of one block.  Non-negative doubles order like their bit
+// patterns, so the maxima are taken with integer atomics on those; an entry that is not finite
+// makes the first one +inf.
+__global__ void __launch_bounds__(256) asym_max_kernel(const double* __restrict__ P, int n,
+                                                        unsigned long long* __restrict__ out) {
+  double a = 0.0, m = 0.0;
+  const size_t nn = (size_t)n * n;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < nn;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const size_t i = e / n, j = e - i * n;
+    const double x = P[e];
+    if (!isfinite(x)) a = INFINITY;
+    else a = fmax(a, fabs(x - P[j * n + i]));
+    m = fmax(m, fabs(x));
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    a = fmax(a, __shfl_xor(a, o));
+    m = fmax(m, __shfl_xor(m, o));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(out, (unsigned long long)__double_as_longlong(a));
+    atomicMax(out + 1, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
 inline int grid_1d(size_t n) {
   size_t g = (n + 255) / 256;
   if (g > 8192) g = 8192;
@@ -465,6 +490,13 @@ hipError_t launch_purify_partials(const double* X, int ld, double* part, double*
                                   hipStream_t st) {
   hipLaunchKernelGGL(purify_partials_kernel, dim3(purify_tiles(ld)), dim3(256), 0, st, X, ld, part,
                      state);
+  return hipGetLastError();
+}
+
+hipError_t launch_asym_max(const double* P, int n, unsigned long long* out, hipStream_t st) {
+  hipError_t e = hipMemsetAsync(out, 0, 2 * sizeof(unsigned long long), st);
+  if (e != hipSuccess || n <= 0) return e;
+  hipLaunchKernelGGL(asym_max_kernel, dim3(grid_1d((size_t)n * n)), dim3(256), 0, st, P, n, out);
   return hipGetLastError();
 }
 

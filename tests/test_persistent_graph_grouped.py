@@ -175,3 +175,36 @@ def test_debug_table_checks(gpu, monkeypatch):
         o = GridOracle(systems[k])
         Hr, _ = o.integrate_h(systems[k].v, want_S=False)
         assert relerr(g.blocks(H)[k].cpu().numpy(), Hr) <= 1e-10
+
+
+def test_debug_refuses_an_asymmetric_P(gpu, monkeypatch):
+    """With AIMS_DEBUG=1 every call that reads P checks on the device that it is symmetric and
+    finite, per system of a grouped handle: a symmetric P passes with unchanged results, one
+    asymmetric entry in the second system, or one NaN, is refused with AIMS_ERR_ARG by the
+    density pass, the backward and the density gradient alike."""
+    from paper_2208_12335_amd import AimsError
+    monkeypatch.setenv("AIMS_DEBUG", "1")
+    mols = synth.make_molecule_set(n_mol=2, seed=9, n_min=2, n_max=4)
+    g = AimsGrid(mols, device=gpu.index)
+    P = torch.cat([torch.from_numpy(m.P).reshape(-1) for m in mols]).to(gpu)
+    v = torch.cat([torch.from_numpy(m.v) for m in mols]).to(gpu)
+    gE = torch.ones(1, dtype=torch.float64, device=gpu)
+    n, sums = g.update_density(P, v)
+    torch.cuda.synchronize()
+    monkeypatch.delenv("AIMS_DEBUG")
+    g0 = AimsGrid(mols, device=gpu.index)
+    n0, sums0 = g0.update_density(P, v)
+    assert relerr(sums.cpu().numpy(), sums0.cpu().numpy()) <= 1e-13
+    nb1 = g.nb_sys[1]
+    off = g.nb_sys[0] ** 2
+    bad = P.clone()
+    bad[off + 1] += 1e-6 * bad[off:].abs().max()      # entry (0, 1) of system 1 only
+    nan = P.clone()
+    nan[off + nb1 + 1] = float("nan")                  # entry (1, 1) of system 1
+    for Q in (bad, nan):
+        for call in (lambda: g.update_density(Q, v), lambda: g.backward(Q, v, gE),
+                     lambda: g.density_gradient(Q)):
+            with pytest.raises(AimsError) as e:
+                call()
+            assert "not symmetric" in str(e.value) and "system 1" in str(e.value)
+    g.update_density(P, v)                             # the handle still works
