@@ -1,6 +1,6 @@
 // Density matrix of the occupied subspace from H and S (the step after the H integration):
-// device kernels (scf.hip) and the solver driver (scf.cpp).  All matrices here are n x n,
-// symmetric on input and output; the driver works in rocBLAS's column-major convention
+// device kernels (scf.hip) and the host-side solver (scf.cpp).  All matrices here are n x n,
+// symmetric on input and output; the solver works in rocBLAS's column-major convention
 // internally (for a symmetric matrix the two conventions coincide).
 #pragma once
 
