@@ -250,9 +250,14 @@ potential_kernel(const double4* __restrict__ pts, const int32_t* __restrict__ pe
         pw[0] = ir;
 #pragma unroll
         for (int l = 1; l <= L; ++l) pw[l] = pw[l - 1] * ir;
+        double sl[L + 1];                   // sum over m of q_lm Y_lm: one chain per l
+#pragma unroll
+        for (int l = 0; l <= L; ++l) sl[l] = 0.0;
         for_each_ylm<L>(dx * ir, dy * ir, dz * ir, [&](int l, int m, double Y) {
-          v += (4.0 * kPi / (double)(2 * l + 1)) * qa[l * l + l + m] * pw[l] * Y;
+          sl[l] = fma(qa[l * l + l + m], Y, sl[l]);
         });
+#pragma unroll
+        for (int l = 0; l <= L; ++l) v = fma((4.0 * kPi / (double)(2 * l + 1)) * pw[l], sl[l], v);
       } else if (r < rmin) {                // inside the innermost node
         const double x = r / rmin;
         pw[0] = 1.0;
