@@ -702,29 +702,35 @@ density_tile_bf16(int item, const TileItem* __restrict__ items, int n_items, con
 #pragma unroll
     for (int ni = 0; ni < NBN; ++ni) acc[mi][ni] = f4_t{0, 0, 0, 0};
 
-  const int r = tid >> 2, sg = tid & 3;
-  const int grow = (j0 + r < nb) ? cols[j0 + r] : -1;
-  const float* Prow = Pm + (size_t)(grow < 0 ? 0 : grow) * sys.nb;
+  // P_b staging: load c of a thread reads tile row 8 (tid / 32) + c at chunk column tid % 32, so
+  // one load instruction covers two rows of 32 consecutive columns (two cache lines of P)
+  // instead of sixteen rows
+  const int kq = tid & 31, rb = 8 * (tid >> 5);
+  uint32_t prow[8];                 // row offsets into the system's P (n_basis <= 65535)
+  bool rok[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int j = j0 + rb + c;
+    rok[c] = j < nb;
+    prow[c] = (uint32_t)cols[rok[c] ? j : 0] * (uint32_t)sys.nb;
+  }
 
-  int cidx[8];
+  int cidx = 0;
   float pa[8];
   bf16x8_t bh[BQ], bl[BQ];
   const bool full = mrows >= 32 && ncols >= 16 * NBN;
-  bool kval[8];
+  bool kval = false;
   auto load_cols = [&](int kc) {     // unconditional load of a clamped index (no branch)
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int k = kc + 8 * sg + c;
-      kval[c] = k < nb;
-      cidx[c] = cols[k < nb ? k : nb - 1];
-    }
+    const int k = kc + kq;
+    kval = k < nb;
+    cidx = cols[k < nb ? k : nb - 1];
   };
   bool aok[8], bok[BQ];
   auto fetch = [&](int kc) {
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-      aok[c] = grow >= 0 && kval[c];
-      pa[c] = Prow[cidx[c]];
+      aok[c] = rok[c] && kval;
+      pa[c] = Pm[prow[c] + (uint32_t)cidx];
     }
 #pragma unroll
     for (int q = 0; q < BQ; ++q) {
@@ -737,16 +743,13 @@ density_tile_bf16(int item, const TileItem* __restrict__ items, int n_items, con
     }
   };
   auto stash = [&](int buf) {
-    bf16x8_t h, l;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       bf16_t hh, ll;
       split_bf16(aok[c] ? pa[c] : 0.f, hh, ll);
-      h[c] = hh;
-      l[c] = ll;
+      Ah[buf][(rb + c) * kLdB + kq] = hh;
+      Al[buf][(rb + c) * kLdB + kq] = ll;
     }
-    *reinterpret_cast<bf16x8_t*>(&Ah[buf][r * kLdB + 8 * sg]) = h;
-    *reinterpret_cast<bf16x8_t*>(&Al[buf][r * kLdB + 8 * sg]) = l;
     const bf16_t zero = (bf16_t)0.f;
 #pragma unroll
     for (int q = 0; q < BQ; ++q) {
